@@ -1,0 +1,145 @@
+/*
+ * pms.h -- C ABI of the MI355X (gfx950) parallel multi-scale reduction of a
+ * persistent-homology boundary matrix over F2.
+ *
+ * Method: Mendoza-Smith & Tanner, "Parallel multi-scale reduction of
+ * persistent homology filtrations" (arXiv 1708.04710).  The problem is the
+ * one of the paper's introduction and Sec. 2.3: given the boundary matrix
+ * d in F2^{m x m} of a compatibly ordered filtration (eq.
+ * "def:boundary_matrix"), compute low* (eq. "low": the entrywise minimum of
+ * low under left-to-right column additions), and from it the persistence
+ * pairs (low*(j), j) and the essential simplices (Sec. 2.3, sets Pos / Neg /
+ * Ess).
+ *
+ * Conventions for every entry point
+ *   - Indices are 0-based; -1 stands for the paper's 0 ("no entry").
+ *   - Every array argument is a DEVICE pointer unless stated otherwise, owned
+ *     by the caller, and is only read (inputs) or written (outputs) on the
+ *     context's HIP stream.  The library never frees caller memory.
+ *   - The library owns its scratch (column arena, tables, bitmasks).  It is
+ *     allocated on first use, kept in the context and grown when a larger
+ *     problem arrives; pms_destroy releases it.
+ *   - A context is bound to one device and one stream and is not thread
+ *     safe: use one context per host thread / stream.
+ *   - Errors are reported by the return status; no C++ exception crosses
+ *     the ABI.  pms_last_error() gives a message for the last failure.  On
+ *     error, output arrays hold unspecified values and counts are 0, except
+ *     PMS_ERR_CAPACITY (counts hold the required sizes) and
+ *     PMS_ERR_NOT_CONVERGED (low_star holds the pairs known so far).
+ *   - Every call returns after its results are complete on the stream and
+ *     its host-visible counts are filled in (one small device-to-host copy).
+ */
+#ifndef PMS_H
+#define PMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMS_OK = 0,
+    PMS_ERR_INVALID_ARG = -1,    /* null pointer, negative size, bad option */
+    PMS_ERR_NOT_COMPATIBLE = -2, /* rows not strictly ascending, row >= column,
+                                    or dim(row) != dim(column) - 1 */
+    PMS_ERR_OOM = -3,            /* device allocation failed */
+    PMS_ERR_HIP = -4,            /* a HIP runtime call failed */
+    PMS_ERR_NOT_CONVERGED = -5,  /* max_rounds reached before low was injective */
+    PMS_ERR_CAPACITY = -6        /* output buffers too small; counts hold the sizes */
+} pms_status;
+
+typedef struct pms_ctx pms_ctx;
+
+/* Create a context on `device` that issues all work on `stream` (a
+ * hipStream_t; NULL = the default stream).  *ctx receives the handle. */
+pms_status pms_create(pms_ctx **ctx, int device, void *stream);
+/* Release the context and the scratch it owns.  NULL is accepted. */
+void pms_destroy(pms_ctx *ctx);
+/* Message of the last failed call on ctx (owned by ctx, valid until the
+ * next call); "" when the last call succeeded.  NULL ctx -> static text. */
+const char *pms_last_error(const pms_ctx *ctx);
+/* Library version string (static). */
+const char *pms_version(void);
+
+/* Boundary matrix d of a filtration in filtration order, CSC:
+ *   column j (simplex sigma_j) holds rows[col_ptr[j] .. col_ptr[j+1]) -- the
+ *   filtration indices of the codimension-1 faces of sigma_j -- strictly
+ *   ascending and < j (eq. "def:boundary_matrix": sparse, binary, upper
+ *   triangular).  dim[j] is the dimension of sigma_j (eq. "Kp"); it may be
+ *   NULL, in which case the dimension checks are skipped and Phase I treats
+ *   all columns as one dimension (still exact, fewer early pivots). */
+typedef struct {
+    int64_t m;              /* number of simplices (columns), >= 0, < 2^31 - 1 */
+    const int64_t *col_ptr; /* [m+1], col_ptr[0] = 0, non-decreasing */
+    const int32_t *rows;    /* [col_ptr[m]] */
+    const int8_t *dim;      /* [m] or NULL */
+} pms_boundary;
+
+/* Options.  Zero-initialise and set what you need; pms_default_options()
+ * returns the recommended values. */
+typedef struct {
+    /* Source of each column addition in a round (Phase II, Sec. 3.1):
+     *   0 = a colliding column is added the leftmost column with the same low
+     *       (a pivot when one is known, else the leftmost unreduced column);
+     *   1 = only known pivots are added (Alg. "Parallel multi-scale
+     *       reduction" as printed).  Both give the same low* (Sec. 2.3). */
+    int32_t variant;
+    /* 1 = delete rows of simplices known to be negative (compression,
+     *     Sec. 2.4 and Sec. 3.2): such rows never hold a low*.  */
+    int32_t compression;
+    /* Rounds (outer iterations) before giving up; 0 = unbounded (the
+     * iteration converges, Thm. "Convergence"). */
+    int32_t max_rounds;
+    /* Pivot chaining: a column that is known negative (beta_j > 0, Thm.
+     * "Properties of beta_j" P.3) or of top dimension (can never be
+     * cleared) keeps adding known pivots within a round while its low has
+     * one.  0 = one addition per column per round. */
+    int32_t chain;
+    /* Below this many active columns every column chains (tail mode). */
+    int32_t tail_active;
+    /* 1 = check the CSC input (sorted rows, upper triangular, dims). */
+    int32_t validate;
+    /* Initial capacity of the column arena in int32 entries; 0 = automatic.
+     * A non-zero value reallocates the arena to exactly this size (the
+     * arena still grows when fill-in exceeds it). */
+    int64_t arena_entries;
+} pms_options;
+
+pms_options pms_default_options(void);
+
+/* Results.  low_star is required ([m], caller-allocated).  The pair and
+ * essential arrays are optional (NULL with capacity 0 = not wanted); when
+ * given they receive, in canonical order,
+ *   pairs: (pair_birth[k], pair_death[k]) = (low*(j), j) for every j with
+ *          low*(j) >= 0, ascending in j (Sec. 2.3: Neg paired with Pos);
+ *   essential: every i with low*(i) = -1 that is no column's low*,
+ *          ascending (set Ess of Sec. 2.3).
+ * Host-visible outputs are filled by the call. */
+typedef struct {
+    int32_t *low_star;      /* [m] device */
+    int32_t *pair_birth;    /* [cap_pairs] device or NULL */
+    int32_t *pair_death;    /* [cap_pairs] device or NULL */
+    int64_t cap_pairs;
+    int32_t *essential;     /* [cap_essential] device or NULL */
+    int64_t cap_essential;
+    /* host-visible outputs */
+    int64_t n_pairs;
+    int64_t n_essential;
+    int32_t rounds;         /* outer iterations run (Sec. 5: one Phase I + Phase II) */
+    int32_t phase0_pivots;  /* pivots known from beta before any addition (Phase 0) */
+    int64_t additions;      /* column additions performed (the paper's cost unit) */
+    int64_t xor_entries;    /* entries read by those additions */
+} pms_result;
+
+/* Reduce one boundary matrix (Alg. "Parallel multi-scale reduction":
+ * Phase 0 with beta of Def. "beta", then rounds of Phase I local injections
+ * (Alg. "Finding local injections", Thms. "Local injection I/II") and
+ * Phase II simultaneous column additions, with clearing and compression). */
+pms_status pms_reduce(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *opt, pms_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMS_H */

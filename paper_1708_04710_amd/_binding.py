@@ -1,0 +1,97 @@
+"""ctypes binding of ``libpms.so`` (the C ABI declared in ``include/pms.h``).
+
+Argument marshalling only: every step of the reduction runs in the HIP
+kernels of the library.  Loading fails loudly when the library has not been
+built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpms.so")
+
+PMS_OK = 0
+PMS_ERR_INVALID_ARG = -1
+PMS_ERR_NOT_COMPATIBLE = -2
+PMS_ERR_OOM = -3
+PMS_ERR_HIP = -4
+PMS_ERR_NOT_CONVERGED = -5
+PMS_ERR_CAPACITY = -6
+
+STATUS_NAMES = {
+    PMS_OK: "PMS_OK", PMS_ERR_INVALID_ARG: "PMS_ERR_INVALID_ARG",
+    PMS_ERR_NOT_COMPATIBLE: "PMS_ERR_NOT_COMPATIBLE", PMS_ERR_OOM: "PMS_ERR_OOM",
+    PMS_ERR_HIP: "PMS_ERR_HIP", PMS_ERR_NOT_CONVERGED: "PMS_ERR_NOT_CONVERGED",
+    PMS_ERR_CAPACITY: "PMS_ERR_CAPACITY",
+}
+
+# every symbol include/pms.h declares (checked by the CPU test suite)
+EXPORTED = [
+    "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_default_options",
+    "pms_reduce",
+]
+
+
+class PmsBoundary(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("col_ptr", ctypes.c_void_p), ("rows", ctypes.c_void_p),
+                ("dim", ctypes.c_void_p)]
+
+
+class PmsOptions(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("compression", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("chain", ctypes.c_int32),
+                ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("arena_entries", ctypes.c_int64)]
+
+
+class PmsResult(ctypes.Structure):
+    _fields_ = [("low_star", ctypes.c_void_p), ("pair_birth", ctypes.c_void_p),
+                ("pair_death", ctypes.c_void_p), ("cap_pairs", ctypes.c_int64),
+                ("essential", ctypes.c_void_p), ("cap_essential", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_essential", ctypes.c_int64),
+                ("rounds", ctypes.c_int32), ("phase0_pivots", ctypes.c_int32),
+                ("additions", ctypes.c_int64), ("xor_entries", ctypes.c_int64)]
+
+
+class PmsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_1708_04710_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.pms_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.pms_create.restype = ctypes.c_int
+    lib.pms_destroy.argtypes = [P]
+    lib.pms_destroy.restype = None
+    lib.pms_last_error.argtypes = [P]
+    lib.pms_last_error.restype = ctypes.c_char_p
+    lib.pms_version.argtypes = []
+    lib.pms_version.restype = ctypes.c_char_p
+    lib.pms_default_options.argtypes = []
+    lib.pms_default_options.restype = PmsOptions
+    lib.pms_reduce.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
+                               ctypes.POINTER(PmsResult)]
+    lib.pms_reduce.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(ctx, status: int):
+    if status != PMS_OK:
+        msg = load().pms_last_error(ctx)
+        raise PmsError(status, msg.decode() if msg else "")

@@ -1,0 +1,184 @@
+// Internal helpers shared by the library's HIP translation units (gfx950,
+// wave64).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pms.h"
+
+namespace pms {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------- context
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // named scratch buffers, grown on demand
+    Buf b[40];
+    int32_t *arena = nullptr;
+    uint64_t arena_cap = 0;  // entries
+    void *host_pinned = nullptr;
+};
+
+enum BufId {
+    B_OFF = 0, B_LEN, B_LOW, B_STATE, B_BETA, B_LEFT, B_PIV, B_T, B_NEG, B_ACT0, B_ACT1,
+    B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
+    B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
+    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11,
+    B_NUM
+};
+
+// Grow-only scratch: returns the buffer, reallocating (contents dropped) when
+// it is smaller than `bytes`.
+void *scratch(Ctx *c, int id, size_t bytes);
+
+pms_status set_err(Ctx *c, pms_status s, const std::string &msg);
+
+#define PMS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::pms::set_err(c, e_ == hipErrorOutOfMemory ? PMS_ERR_OOM : PMS_ERR_HIP, \
+                                  std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock, unsigned cap = 1u << 20)
+{
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- device
+struct I4 {
+    int32_t v[4];
+};
+
+__device__ inline I4 i4_max(const I4 &a, const I4 &b)
+{
+    I4 r;
+#pragma unroll
+    for (int k = 0; k < 4; k++) r.v[k] = a.v[k] > b.v[k] ? a.v[k] : b.v[k];
+    return r;
+}
+
+__device__ inline I4 i4_fill(int32_t x)
+{
+    I4 r;
+#pragma unroll
+    for (int k = 0; k < 4; k++) r.v[k] = x;
+    return r;
+}
+
+// Inclusive wave scans (wave64, __shfl_up).
+__device__ inline int64_t wave_incl_sum64(int64_t x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ inline int32_t wave_incl_sum32(int32_t x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ inline I4 wave_incl_max4(I4 x)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        I4 y;
+#pragma unroll
+        for (int k = 0; k < 4; k++) y.v[k] = __shfl_up(x.v[k], d, kWave);
+        if (lane >= d) x = i4_max(x, y);
+    }
+    return x;
+}
+
+// Block-wide exclusive sum over kBlock threads; *total receives the sum.
+// Must be reached by every thread of the block.
+__device__ inline int32_t block_excl_sum32(int32_t v, int32_t *total)
+{
+    __shared__ int32_t s_w[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int32_t inc = wave_incl_sum32(v);
+    if (lane == kWave - 1) s_w[wid] = inc;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; w++) {
+        int32_t t = s_w[w];
+        if (w < wid) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+__device__ inline int64_t block_sum64(int64_t v)
+{
+    __shared__ int64_t s_w64[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int64_t inc = wave_incl_sum64(v);
+    if (lane == kWave - 1) s_w64[wid] = inc;
+    __syncthreads();
+    int64_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; w++) tot += s_w64[w];
+    __syncthreads();
+    return tot;
+}
+
+// Block-wide exclusive max-scan of I4 (identity -1); *total = block max.
+__device__ inline I4 block_excl_max4(I4 v, I4 *total)
+{
+    __shared__ I4 s_w4[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    I4 inc = wave_incl_max4(v);
+    // exclusive within the wave: shift by one lane
+    I4 exc;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        int32_t y = __shfl_up(inc.v[k], 1, kWave);
+        exc.v[k] = lane == 0 ? -1 : y;
+    }
+    if (lane == kWave - 1) s_w4[wid] = inc;
+    __syncthreads();
+    I4 pre = i4_fill(-1), tot = i4_fill(-1);
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; w++) {
+        I4 t = s_w4[w];
+        if (w < wid) pre = i4_max(pre, t);
+        tot = i4_max(tot, t);
+    }
+    __syncthreads();
+    *total = tot;
+    return i4_max(pre, exc);
+}
+
+}  // namespace pms

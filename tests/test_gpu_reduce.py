@@ -1,0 +1,155 @@
+"""Parity of the HIP pms reduction (through the C ABI) with the CPU oracle.
+
+low*, the pairs and the essential simplices must match bit for bit: the
+arithmetic is F2 and low* is unique for a filtration (Sec. 2.3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1708_04710_amd import _binding, api, synth
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+def _dev(cp, rows, dim, device):
+    return (torch.as_tensor(np.asarray(cp, np.int64), device=device),
+            torch.as_tensor(np.asarray(rows, np.int32), device=device),
+            None if dim is None else torch.as_tensor(np.asarray(dim, np.int8), device=device))
+
+
+def _check(res, ref):
+    low = res.low_star.cpu().numpy()
+    bad = np.nonzero(low != ref)[0]
+    assert bad.size == 0, f"{bad.size} columns differ, first {bad[:5]}: got {low[bad[:5]]} want {ref[bad[:5]]}"
+    b, d = oracle.pairs(ref)
+    assert np.array_equal(res.pair_birth.cpu().numpy(), b)
+    assert np.array_equal(res.pair_death.cpu().numpy(), d)
+    assert np.array_equal(res.essential.cpu().numpy(), oracle.essential(ref))
+
+
+def _reduce(cp, rows, dim, device, **kw):
+    c, r, d = _dev(cp, rows, dim, device)
+    return api.reduce(c, r, d, **kw)
+
+
+def test_hand_examples(gpu):
+    for ex in json.load(open(GOLDEN))["examples"]:
+        for variant in (0, 1):
+            res = _reduce(ex["col_ptr"], ex["rows"], ex["dim"], gpu, variant=variant)
+            _check(res, np.array(ex["low_star"], np.int32))
+
+
+@pytest.mark.parametrize("facets", [
+    [(0, 1), (1, 2), (0, 2)],
+    [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)],
+    [tuple(sorted((i % 7, (i + 1) % 7, (i + 3) % 7))) for i in range(7)] +
+    [tuple(sorted((i % 7, (i + 2) % 7, (i + 3) % 7))) for i in range(7)],
+    [(1, 2, 3), (1, 3, 4), (1, 4, 5), (1, 5, 6), (1, 2, 6), (2, 3, 5), (2, 4, 5), (2, 4, 6), (3, 4, 6), (3, 5, 6)],
+], ids=["circle", "tetra_boundary", "torus7", "rp2"])
+def test_small_complexes(gpu, facets):
+    cp, rows, dim, _, _ = brute.complex_from_facets(facets)
+    ref = oracle.reduce_standard(cp, rows)
+    for kw in ({}, {"variant": 1}, {"compression": False}, {"chain": False}):
+        _check(_reduce(cp, rows, dim, gpu, **kw), ref)
+
+
+def test_fuzz_random_filtrations(gpu):
+    rng = np.random.default_rng(2024)
+    opts = [dict(), dict(variant=1), dict(compression=False), dict(chain=False), dict(tail_active=0),
+            dict(variant=1, compression=False, chain=False)]
+    for t in range(300):
+        cp, rows, dim, _, _ = brute.random_filtration(rng, n_vertices=int(rng.integers(2, 9)),
+                                                      n_facets=int(rng.integers(1, 9)),
+                                                      max_dim=int(rng.integers(1, 4)))
+        ref = oracle.reduce_standard(cp, rows)
+        kw = opts[t % len(opts)]
+        _check(_reduce(cp, rows, dim if t % 7 else None, gpu, **kw), ref)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(variant=1), dict(compression=False), dict(chain=False),
+                                dict(variant=1, chain=False, compression=False)],
+                         ids=["default", "pivot_gated", "no_compression", "no_chain", "paper_plain"])
+def test_vr_grid50_full(gpu, kw):
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    res = _reduce(f.col_ptr, f.rows, f.dim, gpu, **kw)
+    _check(res, ref)
+    assert res.rounds >= 1
+
+
+def test_vr_torus400(gpu):
+    pts, thr = synth.vr_torus()
+    f = oracle.build_vr_i32(pts, thr, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
+
+
+def test_vr_f32_circle_cloud(gpu):
+    x = synth.circle_batch()[0]
+    f = oracle.build_vr_f32(x, -1.0, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
+
+
+@pytest.mark.parametrize("shape,ties", [((8, 8, 8), False), ((13, 17, 11), False), ((9, 10, 12), True),
+                                        ((1, 30, 40), False), ((24, 24, 24), False)])
+def test_lowerstar_grids(gpu, shape, ties):
+    g = synth.random_grid(7, shape, ties=ties)
+    f = oracle.build_lowerstar(g)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    for kw in ({}, {"variant": 1}, {"chain": False}):
+        _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, **kw), ref)
+
+
+def test_lowerstar_gaussian_64(gpu):
+    """The full 64^3 Gaussian-field workload."""
+    f = oracle.build_lowerstar(synth.gaussian_field())
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    res = _reduce(f.col_ptr, f.rows, f.dim, gpu)
+    _check(res, ref)
+    assert res.essential.numel() == 1
+
+
+# ---------------------------------------------------------------- edges
+def test_empty_and_trivial(gpu):
+    res = _reduce([0], np.zeros(0, np.int32), np.zeros(0, np.int8), gpu)
+    assert res.low_star.numel() == 0 and res.pair_birth.numel() == 0 and res.essential.numel() == 0
+    res = _reduce([0, 0], np.zeros(0, np.int32), [0], gpu)  # one vertex
+    _check(res, np.array([-1], np.int32))
+    res = _reduce([0, 0, 0, 0], np.zeros(0, np.int32), [0, 0, 0], gpu)  # vertices only
+    _check(res, np.array([-1, -1, -1], np.int32))
+
+
+def test_rejects_incompatible(gpu):
+    with pytest.raises(_binding.PmsError) as e:
+        _reduce([0, 0, 0, 2], [1, 0], [0, 0, 1], gpu)  # unsorted rows
+    assert e.value.status == _binding.PMS_ERR_NOT_COMPATIBLE
+    with pytest.raises(_binding.PmsError) as e:
+        _reduce([0, 1], [0], [1], gpu)  # row >= column
+    assert e.value.status == _binding.PMS_ERR_NOT_COMPATIBLE
+    with pytest.raises(_binding.PmsError) as e:
+        _reduce([0, 0, 1], [0], [0, 2], gpu)  # facet of the wrong dimension
+    assert e.value.status == _binding.PMS_ERR_NOT_COMPATIBLE
+
+
+def test_max_rounds_not_converged(gpu):
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2)
+    with pytest.raises(_binding.PmsError) as e:
+        _reduce(f.col_ptr, f.rows, f.dim, gpu, max_rounds=1, chain=False)
+    assert e.value.status == _binding.PMS_ERR_NOT_CONVERGED
+
+
+def test_arena_regrowth(gpu):
+    """A 1024-entry arena forces several regrowths; the result is unchanged."""
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=1024), ref)
+    # the next call on the same context starts from a normal arena again
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
