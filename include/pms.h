@@ -138,6 +138,63 @@ typedef struct {
  * Phase II simultaneous column additions, with clearing and compression). */
 pms_status pms_reduce(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *opt, pms_result *res);
 
+/* ------------------------------------------------------------------------
+ * Filtrations built on the device.  A pms_filtration is library-owned
+ * device memory holding a filtration in compatible order (Sec. 2.2: the
+ * simplices of each sub-complex precede the rest, faces precede cofaces),
+ * ordered by the key (value, dimension, lexicographic vertex tuple), with its
+ * boundary matrix (eq. "def:boundary_matrix").  Pass *f = NULL to allocate a
+ * new one, or an existing one to rebuild in place (its buffers are reused
+ * when large enough).  Free it with pms_filtration_free.
+ * ------------------------------------------------------------------------ */
+typedef struct pms_filtration pms_filtration;
+
+typedef struct {
+    int64_t m, nnz;
+    const int64_t *col_ptr;   /* [m+1] device */
+    const int32_t *rows;      /* [nnz] device, ascending per column */
+    const int8_t *dim;        /* [m] device */
+    const float *value_f32;   /* [m] device, FP32 filtration values, or NULL */
+    const int64_t *value_i64; /* [m] device, int64 values (squared distances), or NULL */
+    const int32_t *crit;      /* [2m] device: the vertex (lower-star: the argmax vertex by
+                                 (value, id), then -1) or edge endpoints (Vietoris-Rips: the
+                                 edge whose length is the simplex's value, latest in the
+                                 filtration; -1 -1 for vertices) that fixes each value */
+    const int32_t *verts;     /* [4m] device, ascending vertex ids, -1 padded */
+} pms_filtration_view;
+
+/* Lower-star filtration of the Freudenthal triangulation of an
+ * nx x ny x nz grid of FP32 values (`grid` device, x fastest: vertex id =
+ * x + nx*(y + ny*z)).  Simplices are the chains of grid vertices whose steps
+ * are non-zero 0/1 vectors with disjoint supports (6 tetrahedra per cube);
+ * the value of a simplex is its largest vertex value.  -0 counts as +0;
+ * NaN -> PMS_ERR_INVALID_ARG.  Grids of 2^26 vertices or more are rejected. */
+pms_status pms_build_lowerstar(pms_ctx *ctx, const float *grid, int32_t nx, int32_t ny, int32_t nz,
+                               pms_filtration **f);
+/* Device pointers of a built filtration (valid until it is rebuilt or freed). */
+pms_status pms_filtration_view_get(const pms_filtration *f, pms_filtration_view *v);
+/* Copy a built filtration into caller-owned device buffers on ctx's stream
+ * (any pointer may be NULL to skip that array; value is float or int64 as
+ * the view says; crit holds 2m and verts 4m entries).  Returns after the
+ * copies complete. */
+pms_status pms_filtration_copy_out(pms_ctx *ctx, const pms_filtration *f, int64_t *col_ptr, int32_t *rows,
+                                   int8_t *dim, void *value, int32_t *crit, int32_t *verts);
+/* Release a filtration (synchronises its device).  NULL is accepted. */
+void pms_filtration_free(pms_filtration *f);
+
+/* Per-kernel timing, opt-in.  pms_profile_enable(ctx, 1) zeroes the totals
+ * and from then on records a HIP event pair on ctx's stream around every
+ * kernel launch of the library, with the launch's algorithmic bytes (the
+ * bytes the step must move: inputs read once, outputs written once).
+ * pms_profile_read() synchronises ctx's stream and returns, for kernel slot
+ * k (0 <= k < pms_profile_kernels()), the summed event time in ms, the
+ * number of launches and the summed algorithmic bytes.  Enabling adds
+ * event overhead; leave it off in production. */
+pms_status pms_profile_enable(pms_ctx *ctx, int enable);
+int pms_profile_kernels(void);
+const char *pms_profile_kernel_name(int k); /* static, NULL when out of range */
+pms_status pms_profile_read(pms_ctx *ctx, int k, double *total_ms, int64_t *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

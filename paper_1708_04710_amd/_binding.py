@@ -30,7 +30,9 @@ STATUS_NAMES = {
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_default_options",
-    "pms_reduce",
+    "pms_reduce", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
+    "pms_profile_read", "pms_build_lowerstar", "pms_filtration_view_get", "pms_filtration_copy_out",
+    "pms_filtration_free",
 ]
 
 
@@ -44,6 +46,12 @@ class PmsOptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("chain", ctypes.c_int32),
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("arena_entries", ctypes.c_int64)]
+
+
+class PmsFiltrationView(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("nnz", ctypes.c_int64), ("col_ptr", ctypes.c_void_p),
+                ("rows", ctypes.c_void_p), ("dim", ctypes.c_void_p), ("value_f32", ctypes.c_void_p),
+                ("value_i64", ctypes.c_void_p), ("crit", ctypes.c_void_p), ("verts", ctypes.c_void_p)]
 
 
 class PmsResult(ctypes.Structure):
@@ -87,6 +95,24 @@ def load(path: str = LIB_PATH):
     lib.pms_reduce.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                ctypes.POINTER(PmsResult)]
     lib.pms_reduce.restype = ctypes.c_int
+    lib.pms_profile_enable.argtypes = [P, ctypes.c_int]
+    lib.pms_profile_enable.restype = ctypes.c_int
+    lib.pms_profile_kernels.argtypes = []
+    lib.pms_profile_kernels.restype = ctypes.c_int
+    lib.pms_profile_kernel_name.argtypes = [ctypes.c_int]
+    lib.pms_profile_kernel_name.restype = ctypes.c_char_p
+    lib.pms_profile_read.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    lib.pms_profile_read.restype = ctypes.c_int
+    lib.pms_build_lowerstar.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(P)]
+    lib.pms_build_lowerstar.restype = ctypes.c_int
+    lib.pms_filtration_view_get.argtypes = [P, ctypes.POINTER(PmsFiltrationView)]
+    lib.pms_filtration_view_get.restype = ctypes.c_int
+    lib.pms_filtration_copy_out.argtypes = [P, P, P, P, P, P, P, P]
+    lib.pms_filtration_copy_out.restype = ctypes.c_int
+    lib.pms_filtration_free.argtypes = [P]
+    lib.pms_filtration_free.restype = None
     _lib = lib
     return lib
 

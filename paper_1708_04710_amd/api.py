@@ -43,6 +43,28 @@ def _destroy_all():
     _ctxs.clear()
 
 
+def profile_enable(enable: bool = True, device=None):
+    """Start (and zero) or stop the library's per-kernel event timing on the
+    context of ``device`` and its current stream."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    ctx = _ctx(dev)
+    B.check(ctx, B.load().pms_profile_enable(ctx, int(bool(enable))))
+
+
+def profile_read(device=None) -> dict:
+    """{kernel name: (total ms, launches, algorithmic bytes)} since profile_enable."""
+    lib = B.load()
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    ctx = _ctx(dev)
+    out = {}
+    for k in range(lib.pms_profile_kernels()):
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        B.check(ctx, lib.pms_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        if n.value:
+            out[lib.pms_profile_kernel_name(k).decode()] = (ms.value, n.value, by.value)
+    return out
+
+
 def default_options() -> dict:
     o = B.load().pms_default_options()
     return {f: getattr(o, f) for f, _ in B.PmsOptions._fields_}
@@ -60,31 +82,75 @@ class ReduceResult:
     xor_entries: int
 
 
+class Filtration:
+    """A filtration built on the device (library-owned memory, freed with the
+    object).  ``view`` holds its device pointers; ``to_torch`` copies it."""
+
+    def __init__(self, device: torch.device):
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        self.view = B.PmsFiltrationView()
+
+    def _refresh(self):
+        B.check(None, B.load().pms_filtration_view_get(self.handle, ctypes.byref(self.view)))
+
+    @property
+    def m(self) -> int:
+        return int(self.view.m)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.view.nnz)
+
+    @property
+    def value_dtype(self):
+        return torch.float32 if self.view.value_f32 else torch.int64
+
+    def to_torch(self) -> dict:
+        m, nnz, dev = self.m, self.nnz, self.device
+        out = {"col_ptr": torch.empty(m + 1, dtype=torch.int64, device=dev),
+               "rows": torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+               "dim": torch.empty(max(m, 1), dtype=torch.int8, device=dev),
+               "value": torch.empty(max(m, 1), dtype=self.value_dtype, device=dev),
+               "crit": torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev),
+               "verts": torch.empty(max(4 * m, 1), dtype=torch.int32, device=dev)}
+        ctx = _ctx(dev)
+        B.check(ctx, B.load().pms_filtration_copy_out(ctx, self.handle, *[out[k].data_ptr() for k in
+                                                                          ("col_ptr", "rows", "dim", "value",
+                                                                           "crit", "verts")]))
+        out["rows"] = out["rows"][:nnz]
+        out["dim"] = out["dim"][:m]
+        out["value"] = out["value"][:m]
+        out["crit"] = out["crit"][:2 * m].view(m, 2)
+        out["verts"] = out["verts"][:4 * m].view(m, 4)
+        return out
+
+    def __del__(self):
+        if self.handle and B._lib is not None:
+            B._lib.pms_filtration_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
+def build_lowerstar(grid: torch.Tensor, out: Filtration | None = None) -> Filtration:
+    """Lower-star filtration of the Freudenthal triangulation of a 3-D FP32
+    grid of shape (nz, ny, nx) (``pms_build_lowerstar``)."""
+    if not grid.is_cuda or grid.dtype != torch.float32 or grid.dim() != 3:
+        raise ValueError("grid must be a 3-D float32 device tensor (nz, ny, nx)")
+    grid = grid.contiguous()
+    nz, ny, nx = grid.shape
+    f = out if out is not None else Filtration(grid.device)
+    ctx = _ctx(grid.device)
+    B.check(ctx, B.load().pms_build_lowerstar(ctx, grid.data_ptr(), nx, ny, nz, ctypes.byref(f.handle)))
+    f._refresh()
+    return f
+
+
 def _dptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
 
 
-def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None = None, *,
-           variant: int = 0, compression: bool = True, max_rounds: int = 0, chain: bool = True,
-           tail_active: int = 1024, validate: bool = True, outputs: bool = True,
-           arena_entries: int = 0) -> ReduceResult:
-    """Reduce the boundary matrix given as CSC device tensors (``pms_reduce``).
-
-    col_ptr: int64 [m+1]; rows: int32 [nnz] ascending per column; dim: int8 [m]
-    or None.  All on the same CUDA (HIP) device."""
-    if not col_ptr.is_cuda or not rows.is_cuda or (dim is not None and not dim.is_cuda):
-        raise ValueError("col_ptr, rows and dim must be device tensors")
-    if col_ptr.dtype != torch.int64 or rows.dtype != torch.int32 or (dim is not None and dim.dtype != torch.int8):
-        raise TypeError("expected col_ptr int64, rows int32, dim int8")
-    col_ptr = col_ptr.contiguous()
-    rows = rows.contiguous()
-    dim = dim.contiguous() if dim is not None else None
-    m = col_ptr.numel() - 1
-    if m < 0:
-        raise ValueError("col_ptr must have m+1 >= 1 entries")
-    if dim is not None and dim.numel() != m:
-        raise ValueError("dim must have m entries")
-    dev = col_ptr.device
+def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=True, max_rounds=0,
+                 chain=True, tail_active=1024, validate=True, outputs=True, arena_entries=0) -> ReduceResult:
     lib = B.load()
     ctx = _ctx(dev)
     low_star = torch.empty(m, dtype=torch.int32, device=dev)
@@ -93,12 +159,7 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     birth = torch.empty(cap_p, dtype=torch.int32, device=dev)
     death = torch.empty(cap_p, dtype=torch.int32, device=dev)
     ess = torch.empty(cap_e, dtype=torch.int32, device=dev)
-    bnd = B.PmsBoundary(m, col_ptr.data_ptr() if m >= 0 else None, rows.data_ptr() if rows.numel() else None,
-                        dim.data_ptr() if dim is not None and m else None)
-    if bnd.rows is None and m > 0:
-        # an all-empty matrix still needs a valid pointer
-        rows = torch.zeros(1, dtype=torch.int32, device=dev)
-        bnd.rows = rows.data_ptr()
+    bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
     opt = B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
                        int(bool(validate)), arena_entries)
     res = B.PmsResult()
@@ -114,3 +175,34 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     return ReduceResult(low_star=low_star, pair_birth=birth[:res.n_pairs], pair_death=death[:res.n_pairs],
                         essential=ess[:res.n_essential], rounds=res.rounds, phase0_pivots=res.phase0_pivots,
                         additions=res.additions, xor_entries=res.xor_entries)
+
+
+def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None = None, **kw) -> ReduceResult:
+    """Reduce the boundary matrix given as CSC device tensors (``pms_reduce``).
+
+    col_ptr: int64 [m+1]; rows: int32 [nnz] ascending per column; dim: int8 [m]
+    or None.  All on the same device.  Keyword options as in ``pms_options``:
+    variant, compression, max_rounds, chain, tail_active, validate,
+    arena_entries; ``outputs=False`` skips the pair / essential lists."""
+    if not col_ptr.is_cuda or not rows.is_cuda or (dim is not None and not dim.is_cuda):
+        raise ValueError("col_ptr, rows and dim must be device tensors")
+    if col_ptr.dtype != torch.int64 or rows.dtype != torch.int32 or (dim is not None and dim.dtype != torch.int8):
+        raise TypeError("expected col_ptr int64, rows int32, dim int8")
+    col_ptr = col_ptr.contiguous()
+    rows = rows.contiguous()
+    dim = dim.contiguous() if dim is not None else None
+    m = col_ptr.numel() - 1
+    if m < 0:
+        raise ValueError("col_ptr must have m+1 >= 1 entries")
+    if dim is not None and dim.numel() != m:
+        raise ValueError("dim must have m entries")
+    if rows.numel() == 0:
+        rows = torch.zeros(1, dtype=torch.int32, device=col_ptr.device)  # a valid pointer
+    return _reduce_ptrs(col_ptr.device, m, col_ptr.data_ptr(), rows.data_ptr(),
+                        dim.data_ptr() if dim is not None and m else None, **kw)
+
+
+def reduce_filtration(f: Filtration, **kw) -> ReduceResult:
+    """Reduce a device-built filtration in place of its library-owned arrays."""
+    v = f.view
+    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, **kw)

@@ -1,0 +1,53 @@
+// Internal: library-owned filtrations produced by the GPU builders.
+#pragma once
+
+#include "pms_common.h"
+
+namespace pms {
+
+// Device arrays of one filtration in compatible order (owned by the library).
+struct Filtration {
+    int device = 0;
+    int64_t m = 0, nnz = 0;
+    int64_t cap_m = 0, cap_nnz = 0;
+    int64_t *col_ptr = nullptr;  // [m+1]
+    int32_t *rows = nullptr;     // [nnz]
+    int8_t *dim = nullptr;       // [m]
+    void *value = nullptr;       // [m] float or int64
+    int32_t *crit = nullptr;     // [2m] critical vertex / critical edge endpoints
+    int32_t *verts = nullptr;    // [4m] ascending vertex ids, -1 padded
+    int value_is_f32 = 1;
+};
+
+// (Re)allocate *f for m simplices and nnz facets; reuses it when big enough.
+pms_status filtration_reserve(Ctx *c, Filtration **f, int64_t m, int64_t nnz, int f32);
+
+pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, int32_t nz, Filtration **out);
+
+// Exclusive scan of n int64 in place, one block of 1024 threads.
+static __global__ void __launch_bounds__(1024) k_scan_i64(int64_t *a, int64_t n)
+{
+    __shared__ int64_t s_w[1024 / kWave];
+    __shared__ int64_t s_carry;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < n ? a[i] : 0;
+        const int64_t inc = wave_incl_sum64(v);
+        if (lane == kWave - 1) s_w[wid] = inc;
+        __syncthreads();
+        int64_t pre = s_carry, tot = s_carry;
+        for (int w = 0; w < 1024 / kWave; w++) {
+            if (w < wid) pre += s_w[w];
+            tot += s_w[w];
+        }
+        if (i < n) a[i] = pre + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = tot;
+        __syncthreads();
+    }
+}
+
+}  // namespace pms

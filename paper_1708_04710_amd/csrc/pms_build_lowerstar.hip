@@ -1,0 +1,313 @@
+// Lower-star filtration of the Freudenthal triangulation of a 3-D vertex
+// grid, built on the GPU.
+//
+// The simplices of the triangulation are the chains v0 < v1 < ... < vk of
+// grid vertices whose successive steps are non-zero 0/1 vectors with
+// disjoint supports (k <= 3).  A simplex is stored as (anchor v0, shape),
+// where the shape is the sequence of steps: 1 shape of dimension 0, 7 of
+// dimension 1, 12 of dimension 2 and 6 of dimension 3.  Its value is the
+// largest vertex value (lower-star filtration), and the filtration order is
+// compatible (Sec. 2.2): by value, then dimension, then the lexicographic
+// order of the ascending vertex tuple.  Because a simplex's vertices are the
+// anchor plus fixed offsets, the lexicographic order is (anchor, rank of the
+// shape's offset tuple), so the whole order is one 64-bit key:
+//
+//   [63:32] value, as order-preserving bits of the FP32 (-0 read as +0)
+//   [31:30] dimension
+//   [29: 4] anchor vertex id (26 bits)
+//   [ 3: 0] rank of the shape among the shapes of its dimension
+//
+// The boundary matrix (eq. "def:boundary_matrix") follows from a dense
+// (anchor, shape) -> filtration index table: the facets of (v, s) are
+// (v + delta, s') with delta and s' read from a per-shape table.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <new>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <vector>
+
+#include "pms_common.h"
+#include "pms_build.h"
+
+namespace pms {
+
+constexpr int kShapes = 26;
+
+struct ShapeTab {
+    int32_t nx, ny, nz;
+    int8_t dim[kShapes];
+    int8_t ext[kShapes];      // OR of the steps: axes the shape advances along
+    int8_t rank[kShapes];     // lexicographic rank within its dimension
+    int32_t cum[kShapes][4];  // vertex offsets from the anchor (cum[0] = 0)
+    int8_t by_rank[4][16];    // shape id of (dim, rank)
+    int8_t facet[kShapes][4]; // facet shape id after removing vertex k
+    int32_t fdelta[kShapes][4];  // anchor shift of that facet
+};
+
+__device__ inline uint32_t f32_order_bits(float x)
+{
+    if (x == 0.0f) x = 0.0f;  // -0 and +0 are one value
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ inline float f32_from_order_bits(uint32_t u)
+{
+    const uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    return __uint_as_float(b);
+}
+
+__device__ inline bool shape_fits(const ShapeTab &t, int32_t v, int s)
+{
+    const int32_t x = v % t.nx, y = (v / t.nx) % t.ny, z = v / (t.nx * t.ny);
+    const int e = t.ext[s];
+    return !((e & 1) && x + 1 >= t.nx) && !((e & 2) && y + 1 >= t.ny) && !((e & 4) && z + 1 >= t.nz);
+}
+
+// One key per (anchor, shape); shapes that leave the grid get ~0 (sorted last).
+__global__ void k_ls_keys(ShapeTab t, const float *__restrict__ grid, int64_t nv, unsigned long long *keys,
+                          int32_t *err)
+{
+    const int64_t n = nv * kShapes;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)(i / kShapes);
+        const int s = (int)(i - (int64_t)v * kShapes);
+        unsigned long long key = ~0ull;
+        if (shape_fits(t, v, s)) {
+            float val = grid[v];
+            for (int k = 1; k <= t.dim[s]; k++) val = fmaxf(val, grid[v + t.cum[s][k]]);
+            if (val != val) atomicExch(err, 1);  // NaN has no place in an order
+            key = ((unsigned long long)f32_order_bits(val) << 32) | ((unsigned long long)t.dim[s] << 30) |
+                  ((unsigned long long)v << 4) | (unsigned long long)t.rank[s];
+        }
+        keys[i] = key;
+    }
+}
+
+// Decode the sorted keys: index table, dimension, value, critical vertex,
+// vertex tuple, and the per-tile facet counts for col_ptr.
+__global__ void __launch_bounds__(kBlock) k_ls_index(ShapeTab t, const float *__restrict__ grid,
+                                                     const unsigned long long *__restrict__ keys, int64_t m, int64_t nv,
+                                                     int32_t *idx_tab, int8_t *dim, float *value, int32_t *crit,
+                                                     int32_t *verts, int64_t *tile_sum, int32_t *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t nf = 0;
+    const unsigned long long key = p < m ? keys[p] : ~0ull;
+    if (p < m && (key == ~0ull || (int64_t)((key >> 4) & 0x3FFFFFFu) >= nv)) atomicExch(err, 2);
+    else if (p < m) {
+        const int32_t v = (int32_t)((key >> 4) & 0x3FFFFFFu);
+        const int dm = (int)((key >> 30) & 3u);
+        const int s = t.by_rank[dm][key & 15u];
+        idx_tab[(int64_t)v * kShapes + s] = (int32_t)p;
+        dim[p] = (int8_t)dm;
+        value[p] = f32_from_order_bits((uint32_t)(key >> 32));
+        // argmax vertex by (value, id): the vertex whose value the simplex takes
+        int32_t best = v;
+        float bv = grid[v];
+        for (int k = 1; k <= dm; k++) {
+            const int32_t u = v + t.cum[s][k];
+            const float gu = grid[u];
+            if (gu > bv || (gu == bv && u > best)) { best = u; bv = gu; }
+        }
+        crit[2 * p] = best;
+        crit[2 * p + 1] = -1;
+        if (verts)
+            for (int k = 0; k < 4; k++) verts[4 * p + k] = k <= dm ? v + t.cum[s][k] : -1;
+        nf = dm > 0 ? dm + 1 : 0;
+    }
+    const int64_t tot = block_sum64(nf);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned long long *__restrict__ keys, int64_t m,
+                                                    int64_t nv, int64_t nnz, const int32_t *__restrict__ idx_tab,
+                                                    const int64_t *tile_off, int64_t *col_ptr, int32_t *rows)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t nf = 0;
+    int32_t v = 0;
+    int s = 0, dm = 0;
+    bool ok = false;
+    if (p < m) {
+        const unsigned long long key = keys[p];
+        ok = key != ~0ull && (int64_t)((key >> 4) & 0x3FFFFFFu) < nv;
+        v = (int32_t)((key >> 4) & 0x3FFFFFFu);
+        dm = (int)((key >> 30) & 3u);
+        s = t.by_rank[dm][key & 15u];
+        nf = (ok && dm > 0) ? dm + 1 : 0;
+    }
+    const int64_t start = tile_off[blockIdx.x] + block_excl_sum64(nf);
+    if (p < m && start + nf <= nnz) {
+        col_ptr[p] = start;
+        if (p == m - 1) col_ptr[m] = start + nf;
+        int32_t r[4];
+        for (int k = 0; k < nf; k++) r[k] = idx_tab[(int64_t)(v + t.fdelta[s][k]) * kShapes + t.facet[s][k]];
+        for (int a = 1; a < nf; a++) {  // ascending rows
+            const int32_t x = r[a];
+            int b = a - 1;
+            while (b >= 0 && r[b] > x) { r[b + 1] = r[b]; b--; }
+            r[b + 1] = x;
+        }
+        for (int k = 0; k < nf; k++) rows[start + k] = r[k];
+    }
+}
+
+// ---------------------------------------------------------------- host
+static int step_offset(int e, int nx, int ny)
+{
+    return (e & 1) + ((e >> 1) & 1) * nx + ((e >> 2) & 1) * nx * ny;
+}
+
+static void make_tables(ShapeTab &t, int nx, int ny, int nz)
+{
+    t.nx = nx;
+    t.ny = ny;
+    t.nz = nz;
+    std::vector<std::vector<int>> shapes;
+    shapes.push_back({});
+    for (int e = 1; e < 8; e++) shapes.push_back({e});
+    for (int e1 = 1; e1 < 8; e1++)
+        for (int e2 = 1; e2 < 8; e2++)
+            if (!(e1 & e2)) shapes.push_back({e1, e2});
+    const int perm[6][3] = {{1, 2, 4}, {1, 4, 2}, {2, 1, 4}, {2, 4, 1}, {4, 1, 2}, {4, 2, 1}};
+    for (auto &p : perm) shapes.push_back({p[0], p[1], p[2]});
+    auto find = [&](const std::vector<int> &st) {
+        for (size_t i = 0; i < shapes.size(); i++)
+            if (shapes[i] == st) return (int)i;
+        return -1;
+    };
+    for (int s = 0; s < kShapes; s++) {
+        const auto &st = shapes[s];
+        t.dim[s] = (int8_t)st.size();
+        int e = 0, c = 0;
+        t.cum[s][0] = 0;
+        for (size_t k = 0; k < st.size(); k++) {
+            e |= st[k];
+            c += step_offset(st[k], nx, ny);
+            t.cum[s][k + 1] = c;
+        }
+        for (size_t k = st.size() + 1; k < 4; k++) t.cum[s][k] = 0;
+        t.ext[s] = (int8_t)e;
+        for (int k = 0; k < 4; k++) { t.facet[s][k] = 0; t.fdelta[s][k] = 0; }
+        const int d = (int)st.size();
+        if (d >= 1)
+            for (int k = 0; k <= d; k++) {
+                std::vector<int> f;
+                int delta = 0;
+                if (k == 0) {
+                    f.assign(st.begin() + 1, st.end());
+                    delta = step_offset(st[0], nx, ny);
+                } else if (k < d) {
+                    for (int q = 0; q < d; q++) {
+                        if (q == k - 1) f.push_back(st[q] | st[q + 1]);
+                        else if (q != k) f.push_back(st[q]);
+                    }
+                } else {
+                    f.assign(st.begin(), st.end() - 1);
+                }
+                t.facet[s][k] = (int8_t)find(f);
+                t.fdelta[s][k] = delta;
+            }
+    }
+    // lexicographic rank of the offset tuple within each dimension
+    for (int d = 0; d < 4; d++) {
+        std::vector<int> ids;
+        for (int s = 0; s < kShapes; s++)
+            if (t.dim[s] == d) ids.push_back(s);
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+            for (int k = 1; k <= d; k++)
+                if (t.cum[a][k] != t.cum[b][k]) return t.cum[a][k] < t.cum[b][k];
+            return false;
+        });
+        for (int r = 0; r < 16; r++) t.by_rank[d][r] = 0;
+        for (size_t r = 0; r < ids.size(); r++) {
+            t.rank[ids[r]] = (int8_t)r;
+            t.by_rank[d][r] = (int8_t)ids[r];
+        }
+    }
+}
+
+// Number of simplices and facets (closed form: a shape fits at an anchor iff
+// every axis it advances along has room).
+static void ls_sizes(const ShapeTab &t, int64_t *m, int64_t *nnz)
+{
+    int64_t M = 0, Z = 0;
+    for (int mask = 0; mask < 8; mask++) {
+        int64_t anchors = 1;
+        const int32_t ext[3] = {t.nx, t.ny, t.nz};
+        for (int a = 0; a < 3; a++) anchors *= (mask >> a & 1) ? (int64_t)(ext[a] - 1) : 1;
+        if (anchors <= 0) continue;
+        for (int s = 0; s < kShapes; s++) {
+            if ((t.ext[s] & ~mask) != 0) continue;
+            // anchors whose availability mask is exactly `mask`
+            M += anchors;
+            Z += anchors * (t.dim[s] > 0 ? t.dim[s] + 1 : 0);
+        }
+    }
+    *m = M;
+    *nnz = Z;
+}
+
+pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, int32_t nz, Filtration **out)
+{
+    if (!grid || !out || nx < 1 || ny < 1 || nz < 1) return set_err(c, PMS_ERR_INVALID_ARG, "bad grid arguments");
+    const int64_t nv = (int64_t)nx * ny * nz;
+    if (nv >= (1ll << 26)) return set_err(c, PMS_ERR_INVALID_ARG, "grid too large for the 26-bit anchor field");
+    ShapeTab t;
+    make_tables(t, nx, ny, nz);
+    int64_t m = 0, nnz = 0;
+    ls_sizes(t, &m, &nnz);
+    Filtration *f = *out;
+    pms_status st = filtration_reserve(c, &f, m, nnz, /*f32*/ 1);
+    if (st != PMS_OK) return st;
+    *out = f;
+    f->m = m;
+    f->nnz = nnz;
+    f->value_is_f32 = 1;
+    hipStream_t s = c->stream;
+    const int64_t nk = nv * kShapes;
+    unsigned long long *keys = (unsigned long long *)scratch(c, B_BUILD0, nk * 8);
+    unsigned long long *keys2 = (unsigned long long *)scratch(c, B_BUILD1, nk * 8);
+    int32_t *idx = (int32_t *)scratch(c, B_BUILD2, nk * 4);
+    const int64_t tiles = (m + kBlock - 1) / kBlock;
+    int64_t *tsum = (int64_t *)scratch(c, B_BUILD3, (tiles + 1) * 8);
+    int32_t *err = (int32_t *)scratch(c, B_BUILD4, 64);
+    if (!keys || !keys2 || !idx || !tsum || !err) return set_err(c, PMS_ERR_OOM, "builder scratch");
+    size_t tmp_bytes = 0;
+    PMS_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys2, (size_t)nk, 0, 64, s));
+    void *tmp = scratch(c, B_BUILD5, tmp_bytes);
+    if (!tmp) return set_err(c, PMS_ERR_OOM, "sort scratch");
+    PMS_HIP(hipMemsetAsync(err, 0, 4, s));
+    // grid reads are cache resident; the key write is the stream
+    PMS_LAUNCH(c, K_LS_KEYS, 8.0 * nk + 4.0 * nv, k_ls_keys, grid_for(nk, kBlock, 1u << 16), kBlock, t, grid, nv, keys,
+               err);
+    {
+        hipEvent_t e0 = nullptr;
+        if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
+        PMS_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, keys, keys2, (size_t)nk, 0, 64, s));
+        if (c->prof_on) {
+            hipEvent_t e1 = prof_event(c);
+            (void)hipEventRecord(e1, s);
+            c->pend.push_back({K_SORT, e0, e1, 16.0 * nk});
+        }
+    }
+    PMS_LAUNCH(c, K_LS_INDEX, 8.0 * m + 4.0 * m + 1.0 * m + 4.0 * m + 8.0 * m + 16.0 * m, k_ls_index,
+               (unsigned)tiles, kBlock, t, grid, keys2, m, nv, idx, f->dim, (float *)f->value, f->crit, f->verts, tsum,
+               err);
+    PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * tiles, k_scan_i64, 1, 1024, tsum, tiles);
+    PMS_LAUNCH(c, K_LS_ROWS, 8.0 * m + 4.0 * nnz + 4.0 * nnz + 8.0 * m, k_ls_rows, (unsigned)tiles, kBlock, t, keys2,
+               m, nv, nnz, idx, tsum, f->col_ptr, f->rows);
+    PMS_HIP(hipGetLastError());
+    int32_t herr = 0;
+    PMS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+    PMS_HIP(hipStreamSynchronize(s));
+    if (c->prof_on) prof_flush(c);
+    if (herr == 1) return set_err(c, PMS_ERR_INVALID_ARG, "grid holds NaN");
+    if (herr) return set_err(c, PMS_ERR_HIP, "internal: simplex count mismatch in the lower-star builder");
+    return PMS_OK;
+}
+
+}  // namespace pms

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "pms.h"
 
@@ -21,10 +22,32 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// Kernels timed by the optional profiler (pms_profile_*): HIP events are
+// recorded on the context's stream around each launch of these kernels.
+enum KernelId {
+    K_INIT = 0, K_BETA, K_LOW, K_COLLIDE, K_SCAN, K_PIVOTS, K_XOR, K_COMPACT, K_FINAL, K_FILL, K_DEFRAG,
+    K_LS_KEYS, K_SORT, K_LS_INDEX, K_BUILD_SCAN, K_LS_ROWS, K_VR_EDGES, K_VR_TRI, K_VR_INDEX, K_VR_ROWS,
+    K_BACKWARD, K_CHAIN,
+    K_NUM
+};
+
+struct PendingEv {
+    int kid;
+    hipEvent_t e0, e1;
+    double bytes;  // algorithmic bytes of this launch (< 0: filled in later)
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // profiler
+    bool prof_on = false;
+    std::vector<PendingEv> pend;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[K_NUM] = {};
+    double prof_bytes[K_NUM] = {};
+    int64_t prof_launches[K_NUM] = {};
     // named scratch buffers, grown on demand
     Buf b[40];
     int32_t *arena = nullptr;
@@ -36,7 +59,7 @@ enum BufId {
     B_OFF = 0, B_LEN, B_LOW, B_STATE, B_BETA, B_LEFT, B_PIV, B_T, B_NEG, B_ACT0, B_ACT1,
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
-    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11,
+    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_STATS, B_PART, B_CQN,
     B_NUM
 };
 
@@ -45,6 +68,27 @@ enum BufId {
 void *scratch(Ctx *c, int id, size_t bytes);
 
 pms_status set_err(Ctx *c, pms_status s, const std::string &msg);
+
+hipEvent_t prof_event(Ctx *c);
+// Fold finished launches into the per-kernel totals (call after a sync).
+void prof_flush(Ctx *c);
+
+// Launch `kernel` on the context's stream; with the profiler on, bracket it
+// with events and remember its algorithmic bytes.
+#define PMS_LAUNCH(c, kid, bytes, kernel, grid, block, ...)                                    \
+    do {                                                                                        \
+        hipEvent_t e0_ = nullptr;                                                               \
+        if ((c)->prof_on) {                                                                     \
+            e0_ = ::pms::prof_event(c);                                                         \
+            (void)hipEventRecord(e0_, (c)->stream);                                             \
+        }                                                                                       \
+        kernel<<<(grid), (block), 0, (c)->stream>>>(__VA_ARGS__);                               \
+        if ((c)->prof_on) {                                                                     \
+            hipEvent_t e1_ = ::pms::prof_event(c);                                              \
+            (void)hipEventRecord(e1_, (c)->stream);                                             \
+            (c)->pend.push_back({(kid), e0_, e1_, (double)(bytes)});                            \
+        }                                                                                       \
+    } while (0)
 
 #define PMS_HIP(call)                                                                   \
     do {                                                                                \
@@ -137,6 +181,21 @@ __device__ inline int32_t block_excl_sum32(int32_t v, int32_t *total)
     }
     __syncthreads();
     *total = tot;
+    return pre + inc - v;
+}
+
+__device__ inline int64_t block_excl_sum64(int64_t v)
+{
+    __shared__ int64_t s_e64[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int64_t inc = wave_incl_sum64(v);
+    if (lane == kWave - 1) s_e64[wid] = inc;
+    __syncthreads();
+    int64_t pre = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; w++)
+        if (w < wid) pre += s_e64[w];
+    __syncthreads();
     return pre + inc - v;
 }
 

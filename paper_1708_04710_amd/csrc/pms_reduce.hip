@@ -53,18 +53,19 @@ constexpr int kScanThreads = 1024;
 
 // Device counters of one call (zeroed at its start).
 struct Counters {
-    unsigned long long arena_top;
-    unsigned long long additions;
-    unsigned long long xor_entries;
+    unsigned long long additions;    // column additions (folded from the stripes)
+    unsigned long long xor_entries;  // entries read by them
+    unsigned long long xor_bytes;    // algorithmic bytes moved by k_xor
+    unsigned long long chain_bytes;  // algorithmic bytes moved by k_chain
     int32_t error;       // 1 = not compatible
-    int32_t overflow;    // arena exhausted during k_xor
+    int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
     int32_t new_pivots;
     int32_t beta_pivots;
     int32_t topdim;
     int32_t n_pairs;
     int32_t n_ess;
-    int32_t bad_source;  // a source to the right of its target (never expected)
+    int32_t bad_source;  // internal invariant broken (never expected)
     int32_t pad[3];
 };
 
@@ -87,7 +88,35 @@ struct Dev {
     int32_t *arena;
     unsigned long long arena_cap;
     Counters *cnt;
+    // high-rate counters, striped over cache lines: stats[(id*kStripe + slot)*16]
+    unsigned long long *stats;
+    // arena bump pointers, one cache line each: part[p*16]; partition p owns
+    // [part_base + p*part_size, part_base + (p+1)*part_size) (the last one ends at arena_cap)
+    unsigned long long *part;
+    unsigned long long part_base, part_size;
+    int32_t *cq;       // chain queue, kPart slices of cq_slice entries
+    int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]
+    int64_t cq_slice;
 };
+
+constexpr int kStripe = 64;
+constexpr int kPart = 64;
+enum StatId { S_ADDS = 0, S_XE, S_XBYTES, S_CBYTES, S_NEWPIV, S_BETAPIV, S_NUM };
+
+__device__ inline void stat_add(const Dev &d, int id, unsigned long long v, unsigned slot)
+{
+    if (v) atomicAdd(&d.stats[((unsigned)id * kStripe + (slot & (kStripe - 1))) * 16], v);
+}
+
+// Bump allocation of n entries in partition p; -1 when the partition is full.
+__device__ inline int64_t arena_alloc(const Dev &d, unsigned p, int64_t n)
+{
+    p &= kPart - 1;
+    const unsigned long long end =
+        p == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(p + 1) * d.part_size;
+    const unsigned long long o = atomicAdd(&d.part[p * 16], (unsigned long long)n);
+    return o + (unsigned long long)n <= end ? (int64_t)o : -1;
+}
 
 __device__ inline bool is_neg(const uint32_t *neg, int32_t r)
 {
@@ -165,7 +194,12 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
         d.state[j] = n ? ST_ACTIVE : ST_ZERO;
         if (d.dim && d.dim[j] > top) top = d.dim[j];
     }
-    if (d.dim) atomicMax(&d.cnt->topdim, top);
+    if (d.dim) {
+        for (int o = kWave / 2; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, kWave));
+        // read first: once the maximum is in, almost no wave needs the atomic
+        if ((threadIdx.x & (kWave - 1)) == 0 && top > *(volatile int32_t *)&d.cnt->topdim)
+            atomicMax(&d.cnt->topdim, top);
+    }
 }
 
 // beta_j = max{i : left(i) = j} (Def. "beta"); beta_j >= 0 marks column j as
@@ -210,6 +244,7 @@ __global__ void k_low(Dev d, const int32_t *act, int32_t nA, uint32_t round)
 __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, int32_t nA, uint32_t round, I4 *agg)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < kPart) d.cq_n[q * 32] = 0;  // the chain queue of this round starts empty
     I4 e = i4_fill(-1);
     if (q < nA) {
         const int32_t j = act[q];
@@ -323,9 +358,9 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, in
     if (count_beta) {
         int32_t tnb;
         block_excl_sum32(nb, &tnb);
-        if (threadIdx.x == 0 && tnb) atomicAdd(&d.cnt->beta_pivots, tnb);
+        if (threadIdx.x == 0) stat_add(d, S_BETAPIV, (unsigned long long)tnb, blockIdx.x);
     }
-    if (threadIdx.x == 0 && tnp) atomicAdd(&d.cnt->new_pivots, tnp);
+    if (threadIdx.x == 0) stat_add(d, S_NEWPIV, (unsigned long long)tnp, blockIdx.x);
 }
 
 // Sorted symmetric difference of two ascending row lists (F2 column
@@ -358,9 +393,12 @@ __device__ inline int32_t merge_add(const int32_t *__restrict__ x, int32_t nx, c
     return k;
 }
 
-// Phase II.  Also counts, per tile, the positions that stay active.
+// Phase II, first addition of every colliding column (one lane per
+// column: most columns are a few entries long).  A column that may keep
+// adding known pivots (chaining) and whose new low has one is queued for
+// k_chain.
 __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32_t nA, uint32_t round, int variant,
-                                                int compression, int chain, int tail, int32_t *keep_cnt)
+                                                int compression, int chain, int tail)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int32_t j = -1, s = -1, tlen = 0, slen = 0;
@@ -385,80 +423,250 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
             }
         }
     }
-    // wave-aggregated arena allocation of a ping-pong region per target
-    int64_t need = target ? 2 * (int64_t)(tlen + slen) : 0;
-    int64_t inc = wave_incl_sum64(need);
-    int64_t wtot = __shfl(inc, kWave - 1, kWave);
-    unsigned long long wbase = 0;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (lane == 0 && wtot > 0) wbase = atomicAdd(&d.cnt->arena_top, (unsigned long long)wtot);
-    wbase = __shfl(wbase, 0, kWave);
-    bool fits = wbase + (unsigned long long)wtot <= d.arena_cap;
-    if (target && !fits) {
+    // block-aggregated arena allocation (at most tlen + slen - 2 entries
+    // survive), from this block's arena partition
+    __shared__ int64_t s_base;
+    const int64_t need = target ? (int64_t)tlen + slen : 0;
+    const int64_t excl = block_excl_sum64(need);
+    const int64_t btot = block_sum64(need);
+    if (threadIdx.x == 0) s_base = btot ? arena_alloc(d, blockIdx.x, btot) : 0;
+    __syncthreads();
+    const int64_t bbase = s_base;
+    if (target && bbase < 0) {
         atomicExch(&d.cnt->overflow, 1);
-        target = false;
+        target = false;  // the column stays as it is this round
     }
-    int64_t adds = 0, xe = 0;
+    int64_t adds = 0, xe = 0, by = q < nA ? 6 : 0;  // act, state, coll
+    bool push = false;
     if (target) {
-        int64_t reg = (int64_t)wbase + inc - need;  // region [reg, reg + rcap)
-        int64_t rcap = need;
-        int half = 0;
-        const bool chainable = chain && (d.beta[j] >= 0 || (d.dim && d.dim[j] == d.cnt->topdim) || nA < tail);
-        while (true) {
-            const int32_t *x = col_base(d, toff);
-            const int32_t *y = col_base(d, soff);
-            int64_t bound = (int64_t)tlen + slen;
-            int64_t dst;
-            if (bound <= rcap / 2) {
-                dst = reg + half * (rcap / 2);
-            } else {
-                // region too small for this step: take a fresh, larger one
-                int64_t nr = 2 * bound;
-                unsigned long long o = atomicAdd(&d.cnt->arena_top, (unsigned long long)nr);
-                if (o + (unsigned long long)nr > d.arena_cap) {
-                    atomicExch(&d.cnt->overflow, 1);
-                    break;  // header still describes a valid column
-                }
-                reg = (int64_t)o;
-                rcap = nr;
-                half = 0;
-                dst = reg;
-            }
-            int32_t *out = d.arena + dst;
-            const int32_t k = merge_add(x, tlen, y, slen, out, d.neg, compression);
-            adds++;
-            xe += (int64_t)tlen + slen;
-            toff = dst | (int64_t)kArenaBit;
-            tlen = k;
-            d.off[j] = toff;
-            d.len[j] = k;
-            if (k == 0) {
-                d.low[j] = -1;
-                d.state[j] = ST_ZERO;  // column j is positive
-                break;
-            }
+        const int64_t dst = bbase + excl;
+        int32_t *out = d.arena + dst;
+        const int32_t k = merge_add(col_base(d, toff), tlen, col_base(d, soff), slen, out, d.neg, compression);
+        adds = 1;
+        xe = (int64_t)tlen + slen;
+        by += 42 + 4 * ((int64_t)tlen + slen + k) + 16;  // headers, low, piv/T, beta, dim; data in and out
+        d.off[j] = dst | (int64_t)kArenaBit;
+        d.len[j] = k;
+        if (k == 0) {
+            d.low[j] = -1;
+            d.state[j] = ST_ZERO;  // column j is positive
+        } else {
             const int32_t nl = out[k - 1];
             d.low[j] = nl;
-            if (!chainable) break;
-            s = d.piv[nl];
-            if (s < 0) break;
-            soff = d.off[s];
-            slen = d.len[s];
-            half ^= 1;
+            const bool chainable = chain && (d.beta[j] >= 0 || (d.dim && d.dim[j] == d.cnt->topdim) || nA < tail);
+            push = chainable && d.piv[nl] >= 0;
         }
     }
-    const int keep = (q < nA && d.state[j] == ST_ACTIVE) ? 1 : 0;
+    // block-aggregated push onto this block's slice of the chain queue
+    __shared__ int32_t s_q;
+    int32_t npush;
+    const int32_t qpos = block_excl_sum32(push ? 1 : 0, &npush);
+    const unsigned qp = blockIdx.x & (kPart - 1);
+    if (threadIdx.x == 0) s_q = npush ? atomicAdd(&d.cq_n[qp * 32], npush) : 0;
+    __syncthreads();
+    if (push) d.cq[(int64_t)qp * d.cq_slice + s_q + qpos] = j;
+    const int64_t badds = block_sum64(adds);
+    const int64_t bxe = block_sum64(xe);
+    const int64_t bby = block_sum64(by);
+    if (threadIdx.x == 0) {
+        stat_add(d, S_XBYTES, (unsigned long long)bby, blockIdx.x);
+        stat_add(d, S_ADDS, (unsigned long long)badds, blockIdx.x);
+        stat_add(d, S_XE, (unsigned long long)bxe, blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------- chaining
+// One wavefront per queued column.  The working column W stays in LDS while
+// it fits; each step adds the known pivot of W's low (a column that never
+// changes again), so the steps of the standard reduction's inner loop run
+// back to back without leaving the kernel.  A step merges the pivot column
+// S into W cooperatively: an entry's output position is its own index plus
+// its rank in the other list minus twice the number of cancelled pairs
+// below it.
+constexpr int kChainWaves = 4;
+constexpr unsigned kChainBlocks = 512;  // 2 per CU; waves take queue entries dynamically
+constexpr int kCapW = 1536;  // LDS entries per working buffer (two per wave)
+constexpr int kCapS = 512;   // LDS entries for the pivot column
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int32_t lower_bound_i32(const int32_t *a, int32_t n, int32_t x)
+{
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression)
+{
+    __shared__ int32_t sW[kChainWaves][2][kCapW];
+    __shared__ int32_t sS[kChainWaves][kCapS];
+    __shared__ int32_t sE[kChainWaves][kCapS + 1];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
+    // queue slice sizes -> inclusive prefix (lane p holds slices 0..p)
+    const int32_t my_n = lane < kPart ? d.cq_n[lane * 32] : 0;
+    const int32_t pre = wave_incl_sum32(my_n);
+    const int32_t total = __shfl(pre, kWave - 1, kWave);
+    int64_t adds = 0, xe = 0, by = 0;
+    for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
+        // static assignment: ticket t lives in the first slice whose prefix exceeds it
+        const unsigned long long over = __ballot(pre > t);
+        const int p = __ffsll((long long)over) - 1;
+        const int32_t before = p > 0 ? __shfl(pre, p - 1, kWave) : 0;
+        const int32_t j = d.cq[(int64_t)p * d.cq_slice + (t - before)];
+        int32_t L = d.len[j];
+        by += 4 + 12 + 4 * (int64_t)L;  // queue entry, header, column in
+        const int32_t *g = col_base(d, d.off[j]);
+        // W in LDS when it fits, else the current global column (read only)
+        int cur = 0;
+        bool in_lds = L <= kCapW;
+        const int32_t *Wg = g;
+        if (in_lds)
+            for (int32_t a = lane; a < L; a += kWave) sW[w][0][a] = g[a];
+        wave_sync();
+        bool dirty = false;  // W differs from the stored column
+        bool failed = false;
+        while (L > 0) {
+            const int32_t *W = in_lds ? sW[w][cur] : Wg;
+            const int32_t i = W[L - 1];
+            const int32_t s = d.piv[i];
+            if (s < 0) break;
+            const int32_t k = d.len[s];
+            const int32_t *Sg = col_base(d, d.off[s]);
+            adds++;
+            xe += (int64_t)L + k;
+            by += 4 * (int64_t)k + 16;  // pivot lookup, its header and entries
+            if (in_lds && L + k <= kCapW && k <= kCapS) {
+                for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
+                wave_sync();
+                const int32_t *S = sS[w];
+                int32_t *Wn = sW[w][cur ^ 1];
+                // cancelled pairs: exclusive prefix count over S
+                int32_t carry = 0;
+                for (int32_t base = 0; base < k; base += kWave) {
+                    const int32_t b = base + lane;
+                    int32_t e = 0;
+                    if (b < k) {
+                        const int32_t p = lower_bound_i32(W, L, S[b]);
+                        e = (p < L && W[p] == S[b]) ? 1 : 0;
+                    }
+                    const int32_t incl = wave_incl_sum32(e);
+                    if (b < k) sE[w][b] = carry + incl - e;
+                    carry += __shfl(incl, kWave - 1, kWave);
+                }
+                if (lane == 0) sE[w][k] = carry;
+                wave_sync();
+                for (int32_t a = lane; a < L; a += kWave) {
+                    const int32_t x = W[a];
+                    const int32_t r = lower_bound_i32(S, k, x);
+                    if (!(r < k && S[r] == x)) Wn[a + r - 2 * sE[w][r]] = x;
+                }
+                for (int32_t b = lane; b < k; b += kWave) {
+                    const int32_t x = S[b];
+                    const int32_t p = lower_bound_i32(W, L, x);
+                    if (!(p < L && W[p] == x)) Wn[b + p - 2 * sE[w][b]] = x;
+                }
+                int32_t nL = L + k - 2 * carry;
+                wave_sync();
+                // rows of known-negative simplices at the bottom are deleted
+                if (compression)
+                    while (nL > 0 && is_neg(d.neg, Wn[nL - 1])) nL--;
+                if (nL > 0 && Wn[nL - 1] >= i) {  // the low must drop; stop rather than spin
+                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);
+                    failed = true;
+                    break;
+                }
+                L = nL;
+                cur ^= 1;
+                dirty = true;
+            } else {
+                // too long for LDS: lane 0 merges in global memory
+                long long o = 0;
+                const int64_t need = (int64_t)L + k;
+                if (lane == 0) o = arena_alloc(d, gw, need);
+                o = __shfl(o, 0, kWave);
+                if (o < 0) {
+                    if (lane == 0) atomicExch(&d.cnt->overflow, 1);
+                    failed = true;  // keep the stored column; redo next round
+                    break;
+                }
+                int32_t *out = d.arena + o;
+                int32_t nL = 0;
+                if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
+                nL = __shfl(nL, 0, kWave);
+                __threadfence();  // lane 0's global writes, then every lane reads them
+                wave_sync();
+                if (nL > 0 && out[nL - 1] >= i) {  // the low must drop; stop rather than spin
+                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);
+                    failed = true;
+                    break;
+                }
+                Wg = out;
+                L = nL;
+                in_lds = false;
+                dirty = true;
+                // an in-LDS column that shrinks back is fine to keep global
+            }
+        }
+        if (failed || !dirty) continue;
+        // write the result back
+        if (L == 0) {
+            if (lane == 0) {
+                d.len[j] = 0;
+                d.low[j] = -1;
+                d.state[j] = ST_ZERO;
+            }
+            continue;
+        }
+        int64_t dst;
+        if (in_lds) {
+            long long o = 0;
+            if (lane == 0) o = arena_alloc(d, gw, L);
+            o = __shfl(o, 0, kWave);
+            if (o < 0) {
+                if (lane == 0) atomicExch(&d.cnt->overflow, 1);
+                continue;  // progress of this chain is dropped; the stored column is still valid
+            }
+            const int32_t *W = sW[w][cur];
+            for (int32_t a = lane; a < L; a += kWave) d.arena[o + a] = W[a];
+            dst = (int64_t)o;
+        } else {
+            dst = (int64_t)(Wg - d.arena);
+        }
+        by += 4 * (int64_t)L + 16;  // column and header out
+        if (lane == 0) {
+            d.off[j] = dst | (int64_t)kArenaBit;
+            d.len[j] = L;
+            d.low[j] = in_lds ? sW[w][cur][L - 1] : Wg[L - 1];
+        }
+        wave_sync();
+    }
+    // per-wave counters (lane 0 holds them)
+    if (lane == 0) {
+        stat_add(d, S_ADDS, (unsigned long long)adds, gw);
+        stat_add(d, S_XE, (unsigned long long)xe, gw);
+        stat_add(d, S_CBYTES, (unsigned long long)by, gw);
+    }
+}
+
+// Per-tile count of the positions that stay active.
+__global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act, int32_t nA, int32_t *keep_cnt)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int keep = (q < nA && d.state[act[q]] == ST_ACTIVE) ? 1 : 0;
     int32_t tk;
     block_excl_sum32(keep, &tk);
-    int64_t badds = block_sum64(adds);
-    int64_t bxe = block_sum64(xe);
-    if (threadIdx.x == 0) {
-        keep_cnt[blockIdx.x] = tk;
-        if (badds) {
-            atomicAdd(&d.cnt->additions, (unsigned long long)badds);
-            atomicAdd(&d.cnt->xor_entries, (unsigned long long)bxe);
-        }
-    }
+    if (threadIdx.x == 0) keep_cnt[blockIdx.x] = tk;
 }
 
 // Stable compaction of the active list; finalises cleared columns.
@@ -547,6 +755,33 @@ __global__ void __launch_bounds__(kBlock) k_fin_scatter(Dev d, const int32_t *of
     if (de && ess) ess[off_ess[blockIdx.x] + pe] = (int32_t)j;
 }
 
+// Partition bump pointers after (re)allocation: partition p starts at
+// part_base + p * part_size.
+__global__ void k_part_init(Dev d)
+{
+    const int p = threadIdx.x;
+    if (p < kPart) d.part[p * 16] = d.part_base + (unsigned long long)p * d.part_size;
+}
+
+// Fold the striped counters into the call's Counters.
+__global__ void k_stats_fold(Dev d)
+{
+    __shared__ unsigned long long s_sum[S_NUM];
+    if (threadIdx.x < S_NUM) s_sum[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < S_NUM * kStripe; i += blockDim.x)
+        atomicAdd(&s_sum[i / kStripe], d.stats[(unsigned)i * 16]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.cnt->additions = s_sum[S_ADDS];
+        d.cnt->xor_entries = s_sum[S_XE];
+        d.cnt->xor_bytes = s_sum[S_XBYTES];
+        d.cnt->chain_bytes = s_sum[S_CBYTES];
+        d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
+        d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
+    }
+}
+
 // ---------------------------------------------------------------- host
 void *scratch(Ctx *c, int id, size_t bytes)
 {
@@ -574,16 +809,50 @@ pms_status set_err(Ctx *c, pms_status s, const std::string &msg)
     return s;
 }
 
-static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, bool defrag_only_if_needed)
+hipEvent_t prof_event(Ctx *c)
 {
-    (void)defrag_only_if_needed;
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_flush(Ctx *c)
+{
+    for (auto &p : c->pend) {
+        float ms = 0.f;
+        if (p.e0 && p.e1 && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+            c->prof_ms[p.kid] += ms;
+            c->prof_launches[p.kid] += 1;
+            if (p.bytes > 0) c->prof_bytes[p.kid] += p.bytes;
+        }
+        if (p.e0) c->ev_pool.push_back(p.e0);
+        if (p.e1) c->ev_pool.push_back(p.e1);
+    }
+    c->pend.clear();
+}
+
+static void set_partitions(Dev &d, unsigned long long used)
+{
+    d.part_base = used;
+    d.part_size = (d.arena_cap - used) / kPart;
+}
+
+// Arena regrowth: copy the live columns into an arena twice as large, then
+// split the free space into fresh partitions.
+static pms_status grow_arena(Ctx *c, Dev &d, Counters *h)
+{
     unsigned long long new_cap = c->arena_cap * 2;
     int32_t *na = nullptr;
     PMS_HIP(hipMalloc(&na, new_cap * sizeof(int32_t)));
     unsigned long long *top = (unsigned long long *)scratch(c, B_TMP1, 64);
     if (!top) { (void)hipFree(na); return set_err(c, PMS_ERR_OOM, "scratch alloc"); }
     PMS_HIP(hipMemsetAsync(top, 0, sizeof(unsigned long long), c->stream));
-    k_defrag<<<grid_for(d.m, kBlock, 65536), kBlock, 0, c->stream>>>(d, na, top);
+    PMS_LAUNCH(c, K_DEFRAG, 0, k_defrag, grid_for(d.m, kBlock, 65536), kBlock, d, na, top);
     PMS_HIP(hipGetLastError());
     unsigned long long ntop = 0;
     PMS_HIP(hipMemcpyAsync(&ntop, top, sizeof(ntop), hipMemcpyDeviceToHost, c->stream));
@@ -593,9 +862,9 @@ static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, bool defrag_only_if_ne
     c->arena_cap = new_cap;
     d.arena = na;
     d.arena_cap = new_cap;
-    h->arena_top = ntop;
+    set_partitions(d, ntop);
+    PMS_LAUNCH(c, K_FILL, 0, k_part_init, 1, kPart, d);
     h->overflow = 0;
-    PMS_HIP(hipMemcpyAsync(&d.cnt->arena_top, &h->arena_top, sizeof(unsigned long long), hipMemcpyHostToDevice, c->stream));
     PMS_HIP(hipMemsetAsync(&d.cnt->overflow, 0, sizeof(int32_t), c->stream));
     return PMS_OK;
 }
@@ -639,8 +908,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     I4 *agg = (I4 *)scratch(c, B_AGG, nblk * sizeof(I4));
     int32_t *keep = (int32_t *)scratch(c, B_AGG2, (nblk + 1) * 4);
     int32_t *keep2 = (int32_t *)scratch(c, B_FLAGS, (nblk + 1) * 4);
+    d.cq_slice = (nblk + kPart - 1) / kPart * kBlock;  // a slice takes every kPart-th tile
+    d.cq = (int32_t *)scratch(c, B_TMP0, (size_t)kPart * d.cq_slice * 4);
+    d.cq_n = (int32_t *)scratch(c, B_CQN, kPart * 32 * 4);
+    d.stats = (unsigned long long *)scratch(c, B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
+    d.part = (unsigned long long *)scratch(c, B_PART, kPart * 16 * 8);
     if (!d.off || !d.len || !d.low || !d.state || !d.beta || !d.left || !d.piv || !d.T || !d.neg || !d.coll ||
-        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2)
+        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part)
         return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
 
     // arena: sized for the first rounds' fill-in, grown on demand
@@ -655,18 +929,26 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     }
     d.arena = c->arena;
     d.arena_cap = c->arena_cap;
+    set_partitions(d, 0);
 
     hipStream_t st = c->stream;
     const unsigned gm = grid_for(m, kBlock, 65536);
     PMS_HIP(hipMemsetAsync(d.cnt, 0, sizeof(Counters), st));
-    k_fill_i32<<<gm, kBlock, 0, st>>>(d.left, m, 0x7FFFFFFF);
-    k_fill_i32<<<gm, kBlock, 0, st>>>(d.piv, m, -1);
-    k_fill_i32<<<gm, kBlock, 0, st>>>(d.low_star, m, -1);
-    k_fill_i32<<<grid_for(nwords, kBlock, 65536), kBlock, 0, st>>>((int32_t *)d.neg, nwords, 0);
-    k_fill_u64<<<gm, kBlock, 0, st>>>(d.T, m, ~0ull);
-    k_init<<<gm, kBlock, 0, st>>>(d, nnz, opt->validate);
-    k_beta<<<gm, kBlock, 0, st>>>(d, opt->compression);
-    k_iota<<<gm, kBlock, 0, st>>>(act0, m);
+    PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, grid_for(S_NUM * kStripe * 16), kBlock, d.stats,
+               (int64_t)S_NUM * kStripe * 16, 0ull);
+    PMS_LAUNCH(c, K_FILL, 0, k_part_init, 1, kPart, d);
+    const double dm = (double)m, dz = (double)nnz;
+    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.left, m, 0x7FFFFFFF);
+    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.piv, m, -1);
+    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.low_star, m, -1);
+    PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_fill_i32, grid_for(nwords, kBlock, 65536), kBlock, (int32_t *)d.neg, nwords, 0);
+    PMS_LAUNCH(c, K_FILL, 8 * dm, k_fill_u64, gm, kBlock, d.T, m, ~0ull);
+    // col_ptr, rows, left updates, dims (facets and columns), headers out
+    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 17 * dm, k_init, gm, kBlock, d, nnz,
+               opt->validate);
+    // col_ptr, len, rows, left, beta out, neg bits
+    PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
+    PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act0, m);
     PMS_HIP(hipGetLastError());
 
     Counters *h = (Counters *)c->host_pinned;
@@ -677,6 +959,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
+    unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0;
     int32_t *act = act0, *act_next = act1;
     while (nA > 0) {
         if (opt->max_rounds > 0 && (int32_t)round >= opt->max_rounds) {
@@ -685,26 +968,49 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         }
         const int64_t tiles = (nA + kBlock - 1) / kBlock;
         const unsigned gA = grid_for(nA, kBlock, 65536);
-        k_low<<<gA, kBlock, 0, st>>>(d, act, nA, round);
-        k_collide<<<(unsigned)tiles, kBlock, 0, st>>>(d, act, nA, round, agg);
-        k_scan_max4<<<1, kScanThreads, 0, st>>>(agg, tiles);
-        k_pivots<<<(unsigned)tiles, kBlock, 0, st>>>(d, act, nA, agg, opt->compression, round == 0);
-        k_xor<<<(unsigned)tiles, kBlock, 0, st>>>(d, act, nA, round, opt->variant, opt->compression, opt->chain,
-                                                  opt->tail_active, keep);
-        k_scan_sum<<<1, kScanThreads, 0, st>>>(keep, tiles, &d.cnt->n_next);
-        k_compact<<<(unsigned)tiles, kBlock, 0, st>>>(d, act, nA, keep, act_next);
+        const double dA = (double)nA, dt = (double)tiles;
+        // act, len, off, last row, low out, T atomic
+        PMS_LAUNCH(c, K_LOW, 32 * dA, k_low, gA, kBlock, d, act, nA, round);
+        // act, state, low, T, piv, coll out, dim; block aggregates
+        PMS_LAUNCH(c, K_COLLIDE, 23 * dA + 16 * dt, k_collide, (unsigned)tiles, kBlock, d, act, nA, round, agg);
+        PMS_LAUNCH(c, K_SCAN, 32 * dt, k_scan_max4, 1, kScanThreads, agg, tiles);
+        // act, state, low, coll, dim, beta; aggregates
+        PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, (unsigned)tiles, kBlock, d, act, nA, agg,
+                   opt->compression, round == 0);
+        PMS_LAUNCH(c, K_XOR, -1.0, k_xor, (unsigned)tiles, kBlock, d, act, nA, round, opt->variant,
+                   opt->compression, opt->chain, opt->tail_active);
+        const size_t xor_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+        const size_t chain_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
+        PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
+        // act, state, act_next
+        PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, (unsigned)tiles, kBlock, d, act, nA, keep, act_next);
+        if (c->prof_on) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
         PMS_HIP(hipStreamSynchronize(st));
         round++;
-        if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a column was added a column to its right");
+        if (c->prof_on) {
+            c->pend[xor_slot].bytes = (double)(h->xor_bytes - xor_bytes_prev);
+            xor_bytes_prev = h->xor_bytes;
+            c->pend[chain_slot].bytes = (double)(h->chain_bytes - chain_bytes_prev);
+            chain_bytes_prev = h->chain_bytes;
+            prof_flush(c);
+        }
+        if (h->bad_source)
+            return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
+                                                                : "internal: a chained addition did not lower the low");
         if (h->overflow) {
-            pms_status s = grow_arena(c, d, h, true);
+            pms_status s = grow_arena(c, d, h);
             if (s != PMS_OK) return s;
         }
         nA = h->n_next;
         std::swap(act, act_next);
     }
+    PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+    PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    PMS_HIP(hipStreamSynchronize(st));
     res->rounds = (int32_t)round;
     res->additions = (int64_t)h->additions;
     res->xor_entries = (int64_t)h->xor_entries;
@@ -712,9 +1018,9 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
     // pairs and essential simplices, canonical order
     int32_t *cp = keep, *ce = keep2;
-    k_fin_count<<<(unsigned)nblk, kBlock, 0, st>>>(d, cp, ce);
-    k_scan_sum<<<1, kScanThreads, 0, st>>>(cp, nblk, &d.cnt->n_pairs);
-    k_scan_sum<<<1, kScanThreads, 0, st>>>(ce, nblk, &d.cnt->n_ess);
+    PMS_LAUNCH(c, K_FINAL, 8 * dm, k_fin_count, (unsigned)nblk, kBlock, d, cp, ce);
+    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, cp, nblk, &d.cnt->n_pairs);
+    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, ce, nblk, &d.cnt->n_ess);
     PMS_HIP(hipGetLastError());
     PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     PMS_HIP(hipStreamSynchronize(st));
@@ -725,12 +1031,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     if ((want_pairs && res->cap_pairs < res->n_pairs) || (want_ess && res->cap_essential < res->n_essential))
         return set_err(c, PMS_ERR_CAPACITY, "output capacity too small (n_pairs / n_essential hold the sizes)");
     if (want_pairs || want_ess) {
-        k_fin_scatter<<<(unsigned)nblk, kBlock, 0, st>>>(d, cp, ce, want_pairs ? res->pair_birth : nullptr,
-                                                         want_pairs ? res->pair_death : nullptr,
-                                                         want_ess ? res->essential : nullptr);
+        PMS_LAUNCH(c, K_FINAL, 8 * dm + 8.0 * res->n_pairs + 4.0 * res->n_essential, k_fin_scatter,
+                   (unsigned)nblk, kBlock, d, cp, ce, want_pairs ? res->pair_birth : nullptr,
+                   want_pairs ? res->pair_death : nullptr, want_ess ? res->essential : nullptr);
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipStreamSynchronize(st));
     }
+    if (c->prof_on) prof_flush(c);
     return PMS_OK;
 }
 
@@ -780,11 +1087,47 @@ void pms_destroy(pms_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    pms::prof_flush(c);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto &b : c->b)
         if (b.p) (void)hipFree(b.p);
     if (c->arena) (void)hipFree(c->arena);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     delete c;
+}
+
+static const char *const kKernelNames[pms::K_NUM] = {
+    "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
+    "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
+    "k_vr_index", "k_vr_rows", "k_backward", "k_chain"};
+
+pms_status pms_profile_enable(pms_ctx *c, int enable)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    pms::prof_flush(c);
+    for (int k = 0; k < pms::K_NUM; k++) {
+        c->prof_ms[k] = 0;
+        c->prof_bytes[k] = 0;
+        c->prof_launches[k] = 0;
+    }
+    c->prof_on = enable != 0;
+    return PMS_OK;
+}
+
+int pms_profile_kernels(void) { return pms::K_NUM; }
+
+const char *pms_profile_kernel_name(int k) { return (k >= 0 && k < pms::K_NUM) ? kKernelNames[k] : nullptr; }
+
+pms_status pms_profile_read(pms_ctx *c, int k, double *total_ms, int64_t *launches, double *bytes)
+{
+    if (!c || k < 0 || k >= pms::K_NUM) return PMS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PMS_ERR_HIP;
+    pms::prof_flush(c);
+    if (total_ms) *total_ms = c->prof_ms[k];
+    if (launches) *launches = c->prof_launches[k];
+    if (bytes) *bytes = c->prof_bytes[k];
+    return PMS_OK;
 }
 
 const char *pms_last_error(const pms_ctx *c)
