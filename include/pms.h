@@ -61,6 +61,9 @@ void pms_destroy(pms_ctx *ctx);
 const char *pms_last_error(const pms_ctx *ctx);
 /* Library version string (static). */
 const char *pms_version(void);
+/* Checks the device's wave-level primitives (DPP reductions) against
+ * reference shuffles on ctx's device; PMS_OK when they agree. */
+pms_status pms_selftest(pms_ctx *ctx);
 
 /* Boundary matrix d of a filtration in filtration order, CSC:
  *   column j (simplex sigma_j) holds rows[col_ptr[j] .. col_ptr[j+1]) -- the

@@ -29,7 +29,7 @@ STATUS_NAMES = {
 
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
-    "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_default_options",
+    "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
     "pms_reduce", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_build_lowerstar", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free",
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.pms_last_error.restype = ctypes.c_char_p
     lib.pms_version.argtypes = []
     lib.pms_version.restype = ctypes.c_char_p
+    lib.pms_selftest.argtypes = [P]
+    lib.pms_selftest.restype = ctypes.c_int
     lib.pms_default_options.argtypes = []
     lib.pms_default_options.restype = PmsOptions
     lib.pms_reduce.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),

@@ -43,6 +43,13 @@ def _destroy_all():
     _ctxs.clear()
 
 
+def selftest(device=None):
+    """Run the library's check of its wave-level primitives on ``device``."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    ctx = _ctx(dev)
+    B.check(ctx, B.load().pms_selftest(ctx))
+
+
 def profile_enable(enable: bool = True, device=None):
     """Start (and zero) or stop the library's per-kernel event timing on the
     context of ``device`` and its current stream."""

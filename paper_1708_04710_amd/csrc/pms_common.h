@@ -59,7 +59,7 @@ enum BufId {
     B_OFF = 0, B_LEN, B_LOW, B_STATE, B_BETA, B_LEFT, B_PIV, B_T, B_NEG, B_ACT0, B_ACT1,
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
-    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_STATS, B_PART, B_CQN,
+    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_STATS, B_PART, B_CQN, B_PREC,
     B_NUM
 };
 
@@ -125,6 +125,40 @@ __device__ inline I4 i4_fill(int32_t x)
 #pragma unroll
     for (int k = 0; k < 4; k++) r.v[k] = x;
     return r;
+}
+
+// Wave64 reductions on DPP row operations (no LDS crossbar): within each
+// row of 16 lanes, quad_perm [1,0,3,2] and [2,3,0,1] then row_ror 4 and 8
+// leave the row total in every lane; row_bcast 15 / 31 then carry rows 0..2
+// into row 3, whose lane 63 ends with the wave total.
+template <int CTRL, int ROW_MASK>
+__device__ inline int32_t dpp_i32(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+__device__ inline int32_t wave_sum_dpp(int32_t v)
+{
+    v += dpp_i32<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_i32<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_i32<0x124, 0xF>(v);  // row_ror 4
+    v += dpp_i32<0x128, 0xF>(v);  // row_ror 8
+    v += dpp_i32<0x142, 0xA>(v);  // row_bcast 15 -> rows 1, 3
+    v += dpp_i32<0x143, 0xC>(v);  // row_bcast 31 -> rows 2, 3
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+// Max over the wave of non-negative values (rows left out of a bcast get 0
+// from update_dpp's "old" operand, which must not exceed any input).
+__device__ inline int32_t wave_max_dpp(int32_t v)
+{
+    v = max(v, dpp_i32<0xB1, 0xF>(v));
+    v = max(v, dpp_i32<0x4E, 0xF>(v));
+    v = max(v, dpp_i32<0x124, 0xF>(v));
+    v = max(v, dpp_i32<0x128, 0xF>(v));
+    v = max(v, dpp_i32<0x142, 0xA>(v));
+    v = max(v, dpp_i32<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, kWave - 1);
 }
 
 // Inclusive wave scans (wave64, __shfl_up).

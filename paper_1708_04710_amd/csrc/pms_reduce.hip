@@ -38,6 +38,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
 #include <new>
 #include <string>
@@ -50,6 +52,14 @@ enum : uint8_t { ST_ACTIVE = 0, ST_PIVOT = 1, ST_ZERO = 2, ST_CLEARED = 3 };
 
 constexpr uint64_t kArenaBit = 1ull << 62;
 constexpr int kScanThreads = 1024;
+
+enum StatId {
+    S_ADDS = 0, S_XE, S_XBYTES, S_CBYTES, S_NEWPIV, S_BETAPIV,
+    // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
+    // length, and shader cycles per phase of a short-pivot step
+    S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CWAIT, S_T_CPASS1, S_T_CNEXT, S_T_CPASS2, S_T_QUEUED,
+    S_NUM
+};
 
 // Device counters of one call (zeroed at its start).
 struct Counters {
@@ -67,6 +77,17 @@ struct Counters {
     int32_t n_ess;
     int32_t bad_source;  // internal invariant broken (never expected)
     int32_t pad[3];
+    unsigned long long trace[S_NUM];  // folded stripes (trace output)
+};
+
+// Written once, when column s becomes the pivot of row i (its low is i and
+// stays i): the pivot and, when short, the entries below its low, so a
+// chained addition needs one load instead of three dependent ones.
+constexpr int kRecInline = 6;
+struct __align__(32) PivRec {
+    int32_t s;                // the pivot column
+    int32_t k;                // its length, low included
+    int32_t e[kRecInline];    // the k-1 entries below the low, ascending, when k-1 <= kRecInline
 };
 
 struct Dev {
@@ -94,6 +115,7 @@ struct Dev {
     // [part_base + p*part_size, part_base + (p+1)*part_size) (the last one ends at arena_cap)
     unsigned long long *part;
     unsigned long long part_base, part_size;
+    PivRec *prec;      // [m] pivot records by row
     int32_t *cq;       // chain queue, kPart slices of cq_slice entries
     int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]
     int64_t cq_slice;
@@ -101,7 +123,6 @@ struct Dev {
 
 constexpr int kStripe = 64;
 constexpr int kPart = 64;
-enum StatId { S_ADDS = 0, S_XE, S_XBYTES, S_CBYTES, S_NEWPIV, S_BETAPIV, S_NUM };
 
 __device__ inline void stat_add(const Dev &d, int id, unsigned long long v, unsigned slot)
 {
@@ -345,6 +366,14 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, in
         const bool by_li = i > mc.v[slot_of(d, j)];           // low(j) > maxCollision
         if (by_beta || by_li) {
             d.piv[i] = j;
+            PivRec r;
+            r.s = j;
+            r.k = d.len[j];
+            if (r.k - 1 <= kRecInline) {
+                const int32_t *c = col_base(d, d.off[j]);
+                for (int t = 0; t < r.k - 1; t++) r.e[t] = c[t];
+            }
+            d.prec[i] = r;
             d.state[j] = ST_PIVOT;
             d.low_star[j] = i;
             if (compression) atomicOr(&d.neg[j >> 5], 1u << (j & 31));
@@ -506,7 +535,42 @@ __device__ inline int32_t lower_bound_i32(const int32_t *a, int32_t n, int32_t x
     return lo;
 }
 
-__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression)
+// Everything a chain step needs about row i, fetched in one go (the three
+// loads are independent, so they share one memory latency).
+struct Look {
+    int32_t s, k;
+    int32_t e[kRecInline];
+    bool neg;
+};
+
+__device__ inline Look look_up(const Dev &d, int32_t i)
+{
+    Look r;
+    r.s = d.piv[i];
+    const PivRec rec = d.prec[i];  // meaningful only when piv[i] >= 0
+    const uint32_t nw = d.neg[i >> 5];
+    r.k = rec.k;
+#pragma unroll
+    for (int t = 0; t < kRecInline; t++) r.e[t] = rec.e[t];
+    r.neg = (nw >> (i & 31)) & 1u;
+    return r;
+}
+
+__device__ inline int32_t wave_sum32(int32_t x)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ inline uint32_t wave_or32(uint32_t x)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x |= __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression, int trace)
 {
     __shared__ int32_t sW[kChainWaves][2][kCapW];
     __shared__ int32_t sS[kChainWaves][kCapS];
@@ -518,6 +582,8 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     const int32_t pre = wave_incl_sum32(my_n);
     const int32_t total = __shfl(pre, kWave - 1, kWave);
     int64_t adds = 0, xe = 0, by = 0;
+    unsigned long long tr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // trace: short, long, global, sumL, 4 phases, queued
+    if (trace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
         // static assignment: ticket t lives in the first slice whose prefix exceeds it
         const unsigned long long over = __ballot(pre > t);
@@ -536,16 +602,130 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         wave_sync();
         bool dirty = false;  // W differs from the stored column
         bool failed = false;
+        int32_t i = L > 0 ? (in_lds ? sW[w][0][L - 1] : Wg[L - 1]) : -1;
+        Look lk = look_up(d, i >= 0 ? i : 0);
         while (L > 0) {
+            const int64_t c0 = trace ? clock64() : 0;
             const int32_t *W = in_lds ? sW[w][cur] : Wg;
-            const int32_t i = W[L - 1];
-            const int32_t s = d.piv[i];
-            if (s < 0) break;
-            const int32_t k = d.len[s];
-            const int32_t *Sg = col_base(d, d.off[s]);
+            if (lk.s < 0) {
+                // no pivot owns this low: a known-negative row is deleted
+                // (compression), anything else ends the chain
+                if (compression && lk.neg) {
+                    L--;
+                    dirty = true;
+                    if (L == 0) break;
+                    i = W[L - 1];
+                    lk = look_up(d, i);
+                    continue;
+                }
+                break;
+            }
+            const int32_t k = lk.k;
             adds++;
             xe += (int64_t)L + k;
-            by += 4 * (int64_t)k + 16;  // pivot lookup, its header and entries
+            if (in_lds && k - 1 <= kRecInline && L + k <= kCapW) {
+                // short pivot: its entries below the low are in registers;
+                // merge W[0, L-1) with them (the two lows cancel)
+                by += 40;  // piv, record, neg word
+                const int32_t kk = k - 1, Lp = L - 1;
+                int32_t sv[kRecInline];
+#pragma unroll
+                for (int q = 0; q < kRecInline; q++) sv[q] = q < kk ? lk.e[q] : 0x7FFFFFFF;
+                int64_t c1 = 0;
+                if (trace) {
+                    c1 = clock64() + (sv[0] & 0);  // after the record arrived
+                    tr[0]++;
+                    tr[3] += L;
+                    tr[4] += c1 - c0;
+                }
+                // pass 1: ranks of the pivot's entries in W' (packed two per
+                // word: they are below 2^11), the cancellation mask (each bit
+                // is set by at most one lane, so a sum is an or), and the
+                // largest entry of W' that survives
+                int32_t pk0 = 0, pk1 = 0, pk2 = 0, eqm_l = 0, topw = -1;
+                for (int32_t a = lane; a < Lp; a += kWave) {
+                    const int32_t x = W[a];
+                    bool e = false;
+#pragma unroll
+                    for (int q = 0; q < kRecInline; q++) {
+                        const int32_t lt = x < sv[q] ? 1 : 0;
+                        if (q == 0) pk0 += lt;
+                        if (q == 1) pk0 += lt << 16;
+                        if (q == 2) pk1 += lt;
+                        if (q == 3) pk1 += lt << 16;
+                        if (q == 4) pk2 += lt;
+                        if (q == 5) pk2 += lt << 16;
+                        const bool eq = x == sv[q];
+                        eqm_l |= (eq ? 1 : 0) << q;
+                        e |= eq;
+                    }
+                    if (!e) topw = x;  // ascending stripe: the last survivor is the largest
+                }
+                pk0 = wave_sum_dpp(pk0);
+                pk1 = wave_sum_dpp(pk1);
+                pk2 = wave_sum_dpp(pk2);
+                const uint32_t eqm = (uint32_t)wave_sum_dpp(eqm_l);
+                const int32_t cand_w = wave_max_dpp(topw + 1) - 1;
+                int32_t cnt[kRecInline] = {pk0 & 0xFFFF, pk0 >> 16, pk1 & 0xFFFF, pk1 >> 16, pk2 & 0xFFFF, pk2 >> 16};
+                int64_t c2 = 0;
+                if (trace) {
+                    c2 = clock64() + (eqm & 0);
+                    tr[5] += c2 - c1;
+                }
+                // next low: the larger of the two surviving tops
+                int32_t ts = kk - 1;
+                while (ts >= 0 && ((eqm >> ts) & 1u)) ts--;
+                const int32_t cand_s = ts >= 0 ? sv[ts] : -1;
+                const int32_t nxt = cand_s > cand_w ? cand_s : cand_w;
+                const Look nlk = look_up(d, nxt >= 0 ? nxt : 0);  // in flight during the writes
+                int64_t c3 = 0;
+                if (trace) {
+                    c3 = clock64() + (nxt & 0);
+                    tr[6] += c3 - c2;
+                }
+                int32_t *Wn = sW[w][cur ^ 1];
+                for (int32_t a = lane; a < Lp; a += kWave) {
+                    const int32_t x = W[a];
+                    int32_t r = 0;
+                    bool e = false;
+#pragma unroll
+                    for (int q = 0; q < kRecInline; q++) {
+                        r += sv[q] < x ? 1 : 0;
+                        e |= (x == sv[q]);
+                    }
+                    if (!e) Wn[a + r - 2 * __popc(eqm & ((1u << r) - 1u))] = x;
+                }
+                if (lane < kk && !((eqm >> lane) & 1u)) {
+                    int32_t c = 0;
+#pragma unroll
+                    for (int q = 0; q < kRecInline; q++)
+                        if (q == lane) c = cnt[q];
+                    const int32_t o = lane + c - 2 * __popc(eqm & ((1u << lane) - 1u));
+                    if (o >= 0 && o < kCapW) Wn[o] = sv[lane];  // always true; checked by the nxt test below
+                }
+                const int32_t nL = Lp + kk - 2 * __popc(eqm);
+                wave_sync();
+                if (trace) tr[7] += clock64() - c3;
+                if (nxt >= i || (nL > 0 && Wn[nL - 1] != nxt) || (nL == 0) != (nxt < 0)) {
+                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);  // never expected
+                    failed = true;
+                    break;
+                }
+                L = nL;
+                cur ^= 1;
+                dirty = true;
+                i = nxt;
+                lk = nlk;
+                continue;
+            }
+            // long pivot: its column comes from the arena / the input
+            by += 40 + 12 + 4 * (int64_t)k;
+            if (trace) {
+                tr[3] += L;
+                if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
+                else tr[2]++;
+            }
+            const int32_t *Sg = col_base(d, d.off[lk.s]);
             if (in_lds && L + k <= kCapW && k <= kCapS) {
                 for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
                 wave_sync();
@@ -557,8 +737,8 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                     const int32_t b = base + lane;
                     int32_t e = 0;
                     if (b < k) {
-                        const int32_t p = lower_bound_i32(W, L, S[b]);
-                        e = (p < L && W[p] == S[b]) ? 1 : 0;
+                        const int32_t q = lower_bound_i32(W, L, S[b]);
+                        e = (q < L && W[q] == S[b]) ? 1 : 0;
                     }
                     const int32_t incl = wave_incl_sum32(e);
                     if (b < k) sE[w][b] = carry + incl - e;
@@ -573,14 +753,11 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                 }
                 for (int32_t b = lane; b < k; b += kWave) {
                     const int32_t x = S[b];
-                    const int32_t p = lower_bound_i32(W, L, x);
-                    if (!(p < L && W[p] == x)) Wn[b + p - 2 * sE[w][b]] = x;
+                    const int32_t q = lower_bound_i32(W, L, x);
+                    if (!(q < L && W[q] == x)) Wn[b + q - 2 * sE[w][b]] = x;
                 }
-                int32_t nL = L + k - 2 * carry;
+                const int32_t nL = L + k - 2 * carry;
                 wave_sync();
-                // rows of known-negative simplices at the bottom are deleted
-                if (compression)
-                    while (nL > 0 && is_neg(d.neg, Wn[nL - 1])) nL--;
                 if (nL > 0 && Wn[nL - 1] >= i) {  // the low must drop; stop rather than spin
                     if (lane == 0) atomicExch(&d.cnt->bad_source, 2);
                     failed = true;
@@ -615,8 +792,10 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                 L = nL;
                 in_lds = false;
                 dirty = true;
-                // an in-LDS column that shrinks back is fine to keep global
             }
+            if (L == 0) break;
+            i = (in_lds ? sW[w][cur] : Wg)[L - 1];
+            lk = look_up(d, i);
         }
         if (failed || !dirty) continue;
         // write the result back
@@ -642,6 +821,13 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             dst = (int64_t)o;
         } else {
             dst = (int64_t)(Wg - d.arena);
+            if (Wg == g) {  // only trailing deletions: the stored column, shortened
+                if (lane == 0) {
+                    d.len[j] = L;
+                    d.low[j] = Wg[L - 1];
+                }
+                continue;
+            }
         }
         by += 4 * (int64_t)L + 16;  // column and header out
         if (lane == 0) {
@@ -651,11 +837,13 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         }
         wave_sync();
     }
-    // per-wave counters (lane 0 holds them)
+    // per-wave counters (every lane holds the same values)
     if (lane == 0) {
         stat_add(d, S_ADDS, (unsigned long long)adds, gw);
         stat_add(d, S_XE, (unsigned long long)xe, gw);
         stat_add(d, S_CBYTES, (unsigned long long)by, gw);
+        if (trace)
+            for (int q = 0; q < 9; q++) stat_add(d, S_T_SHORT + q, tr[q], gw);
     }
 }
 
@@ -779,7 +967,35 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->chain_bytes = s_sum[S_CBYTES];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
+        for (int q = 0; q < S_NUM; q++) d.cnt->trace[q] = s_sum[q];
     }
+}
+
+// Self-test of the DPP wave reductions against __shfl-based ones on a few
+// patterns; writes the number of mismatches.
+__global__ void k_selftest(int32_t *bad)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t nbad = 0;
+    for (int pat = 0; pat < 6; pat++) {
+        int32_t v;
+        switch (pat) {
+        case 0: v = lane; break;
+        case 1: v = (lane * 37 + 11) & 1023; break;
+        case 2: v = lane == 63 ? 5000 : 0; break;
+        case 3: v = lane == 0 ? 7 : 0; break;
+        case 4: v = (lane & 15) == 15 ? lane : 1; break;
+        default: v = 1 << (lane % 20); break;
+        }
+        int32_t ref_sum = v, ref_max = v;
+        for (int o = 1; o < kWave; o <<= 1) {
+            ref_sum += __shfl_xor(ref_sum, o, kWave);
+            ref_max = max(ref_max, __shfl_xor(ref_max, o, kWave));
+        }
+        if (wave_sum_dpp(v) != ref_sum) nbad++;
+        if (wave_max_dpp(v) != ref_max) nbad++;
+    }
+    if (lane == 0) atomicAdd(bad, nbad);
 }
 
 // ---------------------------------------------------------------- host
@@ -913,8 +1129,9 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     d.cq_n = (int32_t *)scratch(c, B_CQN, kPart * 32 * 4);
     d.stats = (unsigned long long *)scratch(c, B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
     d.part = (unsigned long long *)scratch(c, B_PART, kPart * 16 * 8);
+    d.prec = (PivRec *)scratch(c, B_PREC, (size_t)m * sizeof(PivRec));
     if (!d.off || !d.len || !d.low || !d.state || !d.beta || !d.left || !d.piv || !d.T || !d.neg || !d.coll ||
-        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part)
+        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec)
         return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
 
     // arena: sized for the first rounds' fill-in, grown on demand
@@ -960,12 +1177,17 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
     unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0;
+    const char *tr_env = getenv("PMS_TRACE");
+    const int trace = tr_env && tr_env[0] == '1';
+    unsigned long long tprev[S_NUM] = {};
+    int32_t nA_prev = 0;
     int32_t *act = act0, *act_next = act1;
     while (nA > 0) {
         if (opt->max_rounds > 0 && (int32_t)round >= opt->max_rounds) {
             res->rounds = (int32_t)round;
             return set_err(c, PMS_ERR_NOT_CONVERGED, "max_rounds reached before the reduction converged");
         }
+        nA_prev = nA;
         const int64_t tiles = (nA + kBlock - 1) / kBlock;
         const unsigned gA = grid_for(nA, kBlock, 65536);
         const double dA = (double)nA, dt = (double)tiles;
@@ -980,13 +1202,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, (unsigned)tiles, kBlock, d, act, nA, round, opt->variant,
                    opt->compression, opt->chain, opt->tail_active);
         const size_t xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
         const size_t chain_slot = c->pend.size() - 1;
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
         // act, state, act_next
         PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, (unsigned)tiles, kBlock, d, act, nA, keep, act_next);
-        if (c->prof_on) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+        if (c->prof_on || trace) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
         PMS_HIP(hipStreamSynchronize(st));
@@ -998,6 +1220,19 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             chain_bytes_prev = h->chain_bytes;
             prof_flush(c);
         }
+        if (trace) {
+            unsigned long long dl[S_NUM];
+            for (int q = 0; q < S_NUM; q++) { dl[q] = h->trace[q] - tprev[q]; tprev[q] = h->trace[q]; }
+            const double st = (double)(dl[S_T_SHORT] ? dl[S_T_SHORT] : 1);
+            fprintf(stderr,
+                    "pms round %u: active %d -> %d, new pivots %llu, additions %llu, chain queue %llu, chain steps "
+                    "short %llu long %llu global %llu, mean L %.1f, cycles/short step: wait %.0f pass1 %.0f next %.0f "
+                    "pass2 %.0f\n",
+                    round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_QUEUED], dl[S_T_SHORT], dl[S_T_LONG],
+                    dl[S_T_GLOBAL],
+                    (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
+                    dl[S_T_CWAIT] / st, dl[S_T_CPASS1] / st, dl[S_T_CNEXT] / st, dl[S_T_CPASS2] / st);
+        }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
                                                                 : "internal: a chained addition did not lower the low");
@@ -1005,6 +1240,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             pms_status s = grow_arena(c, d, h);
             if (s != PMS_OK) return s;
         }
+        nA_prev = h->n_next;
         nA = h->n_next;
         std::swap(act, act_next);
     }
@@ -1116,6 +1352,23 @@ pms_status pms_profile_enable(pms_ctx *c, int enable)
 }
 
 int pms_profile_kernels(void) { return pms::K_NUM; }
+
+pms_status pms_selftest(pms_ctx *c)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    int32_t *bad = (int32_t *)pms::scratch(c, pms::B_TMP1, 64);
+    if (!bad) return pms::set_err(c, PMS_ERR_OOM, "scratch");
+    PMS_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
+    pms::k_selftest<<<4, 256, 0, c->stream>>>(bad);
+    PMS_HIP(hipGetLastError());
+    int32_t h = -1;
+    PMS_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
+    PMS_HIP(hipStreamSynchronize(c->stream));
+    if (h != 0) return pms::set_err(c, PMS_ERR_HIP, "wave reduction self-test failed");
+    return PMS_OK;
+}
 
 const char *pms_profile_kernel_name(int k) { return (k >= 0 && k < pms::K_NUM) ? kKernelNames[k] : nullptr; }
 

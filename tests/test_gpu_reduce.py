@@ -39,6 +39,10 @@ def _reduce(cp, rows, dim, device, **kw):
     return api.reduce(c, r, d, **kw)
 
 
+def test_wave_primitives_selftest(gpu):
+    api.selftest(gpu)
+
+
 def test_hand_examples(gpu):
     for ex in json.load(open(GOLDEN))["examples"]:
         for variant in (0, 1):
