@@ -174,6 +174,29 @@ typedef struct {
  * NaN -> PMS_ERR_INVALID_ARG.  Grids of 2^26 vertices or more are rejected. */
 pms_status pms_build_lowerstar(pms_ctx *ctx, const float *grid, int32_t nx, int32_t ny, int32_t nz,
                                pms_filtration **f);
+/* Vietoris-Rips filtrations to dimension maxdim (0..2) of `count` point
+ * clouds at once (Sec. 2.2: a simplex enters when its diameter is at most
+ * 2r, i.e. the value of a simplex is its squared diameter).  Cloud b has
+ * n[b] points of D[b] coordinates stored row-major at pts + pt_off[b]
+ * (pts: device; n, D, pt_off, thr_sqd: host arrays of `count` entries).
+ * thr_sqd[b] < 0 keeps every simplex, else simplices with squared
+ * diameter <= thr_sqd[b].  The clouds' filtrations are concatenated
+ * block-diagonally: cloud b owns the columns [inst_col_off[b],
+ * inst_col_off[b+1]) (host output of count+1 entries, may be NULL), and
+ * its rows stay in that range, so one pms_reduce of the whole matrix
+ * reduces every cloud exactly.  Vertices ids in `verts` / `crit` are global
+ * point numbers (cloud b's point a is sum_{b'<b} n[b'] + a).
+ *   _i32: integer coordinates, exact int64 squared distances (< 2^35),
+ *         n[b] <= 511;
+ *   _f32: FP32 coordinates; the squared distance is rounded step by step
+ *         in coordinate order (d = x_a - x_b; s = s + d*d, no fused
+ *         multiply-add); n[b] <= 1023. */
+pms_status pms_build_vr_i32(pms_ctx *ctx, const int32_t *pts, int32_t count, const int32_t *n, const int32_t *D,
+                            const int64_t *pt_off, const int64_t *thr_sqd, int32_t maxdim, pms_filtration **f,
+                            int64_t *inst_col_off);
+pms_status pms_build_vr_f32(pms_ctx *ctx, const float *pts, int32_t count, const int32_t *n, const int32_t *D,
+                            const int64_t *pt_off, const float *thr_sqd, int32_t maxdim, pms_filtration **f,
+                            int64_t *inst_col_off);
 /* Device pointers of a built filtration (valid until it is rebuilt or freed). */
 pms_status pms_filtration_view_get(const pms_filtration *f, pms_filtration_view *v);
 /* Copy a built filtration into caller-owned device buffers on ctx's stream

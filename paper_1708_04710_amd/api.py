@@ -152,6 +152,53 @@ def build_lowerstar(grid: torch.Tensor, out: Filtration | None = None) -> Filtra
     return f
 
 
+def build_vr(clouds, thresholds=None, maxdim: int = 2, out: Filtration | None = None):
+    """Vietoris-Rips filtrations of one or more point clouds, concatenated
+    block-diagonally (``pms_build_vr_i32`` / ``pms_build_vr_f32``).
+
+    clouds: a device tensor [n, D] or a list of them, all int32 or all
+    float32.  thresholds: None (keep every simplex) or one squared-distance
+    threshold per cloud (< 0 = none).  Returns (filtration, col_off) where
+    cloud b owns the columns col_off[b]:col_off[b+1] (a host list)."""
+    if isinstance(clouds, torch.Tensor):
+        clouds = [clouds]
+    clouds = list(clouds)
+    if not clouds:
+        raise ValueError("no clouds")
+    dtype = clouds[0].dtype
+    if dtype not in (torch.int32, torch.float32) or any(c.dtype != dtype for c in clouds):
+        raise TypeError("clouds must all be int32 or all float32")
+    if any(not c.is_cuda or c.dim() != 2 for c in clouds):
+        raise ValueError("clouds must be 2-D device tensors [n, D]")
+    dev = clouds[0].device
+    nb = len(clouds)
+    n = (ctypes.c_int32 * nb)(*[int(c.shape[0]) for c in clouds])
+    D = (ctypes.c_int32 * nb)(*[int(c.shape[1]) for c in clouds])
+    offs, o = [], 0
+    for c in clouds:
+        offs.append(o)
+        o += c.numel()
+    pt_off = (ctypes.c_int64 * nb)(*offs)
+    flat = torch.cat([c.reshape(-1) for c in clouds]) if o else torch.zeros(1, dtype=dtype, device=dev)
+    f32 = dtype == torch.float32
+    if thresholds is None:
+        thresholds = [-1] * nb
+    thr = (ctypes.c_float * nb)(*[float(t) for t in thresholds]) if f32 else \
+        (ctypes.c_int64 * nb)(*[int(t) for t in thresholds])
+    col_off = (ctypes.c_int64 * (nb + 1))()
+    f = out if out is not None else Filtration(dev)
+    ctx = _ctx(dev)
+    fn = B.load().pms_build_vr_f32 if f32 else B.load().pms_build_vr_i32
+    st = fn(ctx, flat.data_ptr(), nb, n, D, pt_off, thr, maxdim, ctypes.byref(f.handle), col_off)
+    _binding_check(ctx, st)
+    f._refresh()
+    return f, [int(x) for x in col_off]
+
+
+def _binding_check(ctx, st):
+    B.check(ctx, st)
+
+
 def _dptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
 

@@ -23,6 +23,12 @@ struct Filtration {
 pms_status filtration_reserve(Ctx *c, Filtration **f, int64_t m, int64_t nnz, int f32);
 
 pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, int32_t nz, Filtration **out);
+pms_status build_vr_batch(Ctx *c, const void *pts, bool f32, const int32_t *n, const int32_t *D, const int64_t *pt_off,
+                          const void *thr, int32_t B, int32_t maxdim, Filtration **out, int64_t *inst_col_off);
+
+// In-place exclusive scan of n int64 on ctx's stream; *total receives the
+// sum (the call synchronises).  tmp holds ceil(n / kBlock) + 2 entries.
+pms_status scan_i64(Ctx *c, int64_t *data, int64_t n, int64_t *tmp, int64_t *total);
 
 // Exclusive scan of n int64 in place, one block of 1024 threads.
 static __global__ void __launch_bounds__(1024) k_scan_i64(int64_t *a, int64_t n)

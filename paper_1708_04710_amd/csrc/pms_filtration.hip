@@ -52,6 +52,36 @@ pms_status filtration_reserve(Ctx *c, Filtration **pf, int64_t m, int64_t nnz, i
     return PMS_OK;
 }
 
+__global__ void __launch_bounds__(kBlock) k_tile_sums(const int64_t *data, int64_t n, int64_t *tmp)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = block_sum64(i < n ? data[i] : 0);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_tile_apply(int64_t *data, int64_t n, const int64_t *tmp, int64_t *total)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t v = i < n ? data[i] : 0;
+    const int64_t e = tmp[blockIdx.x] + block_excl_sum64(v);
+    if (i < n) data[i] = e;
+    if (i == n - 1) *total = e + v;
+}
+
+pms_status scan_i64(Ctx *c, int64_t *data, int64_t n, int64_t *tmp, int64_t *total)
+{
+    *total = 0;
+    if (n <= 0) return PMS_OK;
+    const int64_t tiles = (n + kBlock - 1) / kBlock;
+    PMS_LAUNCH(c, K_BUILD_SCAN, 8.0 * n, k_tile_sums, (unsigned)tiles, kBlock, data, n, tmp);
+    PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * tiles, k_scan_i64, 1, 1024, tmp, tiles);
+    PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * n, k_tile_apply, (unsigned)tiles, kBlock, data, n, tmp, tmp + tiles + 1);
+    PMS_HIP(hipGetLastError());
+    PMS_HIP(hipMemcpyAsync(total, tmp + tiles + 1, 8, hipMemcpyDeviceToHost, c->stream));
+    PMS_HIP(hipStreamSynchronize(c->stream));
+    return PMS_OK;
+}
+
 }  // namespace pms
 
 
@@ -69,6 +99,35 @@ pms_status pms_build_lowerstar(pms_ctx *ctx, const float *grid, int32_t nx, int3
     pms_status s = pms::build_lowerstar(c, grid, nx, ny, nz, &pf);
     *f = reinterpret_cast<pms_filtration *>(pf);
     return s;
+}
+
+static pms_status vr_entry(pms_ctx *ctx, const void *pts, bool f32, int32_t count, const int32_t *n,
+                           const int32_t *D, const int64_t *pt_off, const void *thr, int32_t maxdim, pms_filtration **f,
+                           int64_t *inst_col_off)
+{
+    pms::Ctx *c = reinterpret_cast<pms::Ctx *>(ctx);
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!f) return pms::set_err(c, PMS_ERR_INVALID_ARG, "null filtration handle");
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    pms::Filtration *pf = reinterpret_cast<pms::Filtration *>(*f);
+    pms_status s = pms::build_vr_batch(c, pts, f32, n, D, pt_off, thr, count, maxdim, &pf, inst_col_off);
+    *f = reinterpret_cast<pms_filtration *>(pf);
+    return s;
+}
+
+pms_status pms_build_vr_i32(pms_ctx *ctx, const int32_t *pts, int32_t count, const int32_t *n, const int32_t *D,
+                            const int64_t *pt_off, const int64_t *thr_sqd, int32_t maxdim, pms_filtration **f,
+                            int64_t *inst_col_off)
+{
+    return vr_entry(ctx, pts, false, count, n, D, pt_off, thr_sqd, maxdim, f, inst_col_off);
+}
+
+pms_status pms_build_vr_f32(pms_ctx *ctx, const float *pts, int32_t count, const int32_t *n, const int32_t *D,
+                            const int64_t *pt_off, const float *thr_sqd, int32_t maxdim, pms_filtration **f,
+                            int64_t *inst_col_off)
+{
+    return vr_entry(ctx, pts, true, count, n, D, pt_off, thr_sqd, maxdim, f, inst_col_off);
 }
 
 pms_status pms_filtration_view_get(const pms_filtration *fh, pms_filtration_view *v)

@@ -66,3 +66,113 @@ def test_lowerstar_builder_rejects_nan(gpu):
     with pytest.raises(_binding.PmsError) as e:
         api.build_lowerstar(torch.as_tensor(g, device=gpu))
     assert e.value.status == _binding.PMS_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------- Vietoris-Rips
+def _vr_ref(cloud, thr, maxdim):
+    if cloud.dtype == np.float32:
+        return oracle.build_vr_f32(cloud, float(thr), maxdim)
+    return oracle.build_vr_i32(cloud, int(thr), maxdim)
+
+
+def _check_vr_segment(got, off, b, pbase, ref):
+    lo, hi = off[b], off[b + 1]
+    assert hi - lo == ref.m
+    cp = got["col_ptr"][lo:hi + 1]
+    assert np.array_equal(cp - cp[0], ref.col_ptr)
+    rows = got["rows"][cp[0]:cp[-1]]
+    assert np.array_equal(rows - lo, ref.rows)
+    assert np.array_equal(got["dim"][lo:hi], ref.dim)
+    gv = got["value"][lo:hi]
+    if ref.value.dtype == np.float32:
+        assert np.array_equal(gv.view(np.uint32), ref.value.view(np.uint32))
+    else:
+        assert np.array_equal(gv, ref.value)
+    verts = got["verts"][lo:hi]
+    assert np.array_equal(np.where(verts >= 0, verts - pbase, -1), ref.verts)
+    # critical edge: the facet edge latest in the filtration (edges: themselves)
+    crit = got["crit"][lo:hi]
+    want = np.full((ref.m, 2), -1, np.int64)
+    e = ref.dim == 1
+    want[e] = ref.verts[e][:, :2]
+    t = np.nonzero(ref.dim == 2)[0]
+    if t.size:
+        last = ref.rows[ref.col_ptr[t + 1] - 1]
+        want[t] = ref.verts[last][:, :2]
+    assert np.array_equal(np.where(crit >= 0, crit - pbase, -1), want)
+
+
+def _compare_vr(clouds, thrs, maxdim, dev):
+    f, off = api.build_vr([torch.as_tensor(c, device=dev) for c in clouds], thrs, maxdim)
+    got = {k: v.cpu().numpy() for k, v in f.to_torch().items()}
+    refs = [_vr_ref(c, t, maxdim) for c, t in zip(clouds, thrs)]
+    pbase = 0
+    for b, (c, ref) in enumerate(zip(clouds, refs)):
+        _check_vr_segment(got, off, b, pbase, ref)
+        pbase += len(c)
+    return f, off, refs
+
+
+def test_vr_builder_grid50_full(gpu):
+    _compare_vr([synth.vr_grid_cloud()], [-1], 2, gpu)
+
+
+def test_vr_builder_torus400_threshold(gpu):
+    pts, thr = synth.vr_torus()
+    _compare_vr([pts], [thr], 2, gpu)
+
+
+def test_vr_builder_f32_circle(gpu):
+    _compare_vr([synth.circle_batch(clouds=1)[0]], [-1.0], 2, gpu)
+
+
+@pytest.mark.parametrize("maxdim", [0, 1, 2])
+def test_vr_builder_batch_mixed(gpu, maxdim):
+    inst = synth.vr_batch(seed=31, count=6, n_range=(3, 40))
+    clouds = [p for p, _ in inst] + [np.zeros((0, 3), np.int32), np.array([[5, 5, 5]], np.int32),
+                                     np.array([[0, 0], [3, 4]], np.int32)]
+    thrs = [t for _, t in inst] + [-1, -1, 24]
+    _compare_vr(clouds, thrs, maxdim, gpu)
+
+
+def test_vr_builder_ties(gpu):
+    # many equal distances: the (value, dim, lex) tie-break decides the order
+    g = np.array([[x, y] for x in range(5) for y in range(4)], np.int32)
+    _compare_vr([g, g[:7]], [4, -1], 2, gpu)
+
+
+def test_vr_batch_reduce_f32_circles(gpu):
+    x = synth.circle_batch(seed=41, clouds=5, n=36)
+    f, off, refs = _compare_vr(list(x), [-1.0] * 5, 2, gpu)
+    res = api.reduce_filtration(f)
+    low = res.low_star.cpu().numpy()
+    for b, ref in enumerate(refs):
+        want = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        seg = low[off[b]:off[b + 1]]
+        assert np.array_equal(np.where(seg >= 0, seg - off[b], -1), want)
+
+
+def test_vr_batch512_sampled(gpu):
+    """The 512-cloud batch at full size: build and reduce on the device in one
+    go, then check a sample of clouds (the largest, the smallest and a few
+    others) against the oracle one by one."""
+    inst = synth.vr_batch()
+    clouds = [p for p, _ in inst]
+    thrs = [t for _, t in inst]
+    f, off = api.build_vr([torch.as_tensor(c, device=gpu) for c in clouds], thrs, 2)
+    res = api.reduce_filtration(f)
+    low = res.low_star.cpu().numpy()
+    sizes = np.diff(off)
+    rng = np.random.default_rng(0)
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} | set(rng.choice(len(clouds), 4, replace=False).tolist()))
+    for b in pick:
+        ref = oracle.build_vr_i32(clouds[b], thrs[b], 2)
+        assert off[b + 1] - off[b] == ref.m
+        want = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        seg = low[off[b]:off[b + 1]]
+        assert np.array_equal(np.where(seg >= 0, seg - off[b], -1), want), b
+
+
+def test_vr_builder_rejects_large_cloud(gpu):
+    with pytest.raises(_binding.PmsError):
+        api.build_vr([torch.zeros((600, 2), dtype=torch.int32, device=gpu)], [-1], 2)
