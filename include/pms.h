@@ -208,6 +208,30 @@ pms_status pms_filtration_copy_out(pms_ctx *ctx, const pms_filtration *f, int64_
 /* Release a filtration (synchronises its device).  NULL is accepted. */
 void pms_filtration_free(pms_filtration *f);
 
+/* ------------------------------------------------------------------------
+ * Values of simplices and the backward pass through a fixed pairing.
+ * With the pairs fixed, a persistence loss depends on the input only through
+ * the values of the paired simplices; each value is the value of one
+ * critical vertex (lower-star: the argmax vertex by (value, id)) or the
+ * squared length of one critical edge (Vietoris-Rips: the simplex's latest
+ * facet edge).  All arrays are device arrays of n entries.
+ * ------------------------------------------------------------------------ */
+/* values[k] = value of simplex[k] (float or int64 as the filtration's
+ * view says; NULL to skip); dims[k] = its dimension (NULL to skip). */
+pms_status pms_gather(pms_ctx *ctx, const pms_filtration *f, int64_t n, const int32_t *simplex, void *values,
+                      int8_t *dims);
+/* grad_grid[v] += sum of grad[k] over the k whose simplex has critical
+ * vertex v (grad_grid: n_vertices floats, zeroed by the caller). */
+pms_status pms_backward_lowerstar(pms_ctx *ctx, const pms_filtration *f, int64_t n, const int32_t *simplex,
+                                  const float *grad, float *grad_grid, int64_t n_vertices);
+/* For a filtration built by pms_build_vr_f32 from clouds whose points are
+ * stored contiguously (point g at pts + g*D): with (a, b) the critical edge
+ * of simplex[k], grad_pts[a] += 2 grad[k] (x_a - x_b) and grad_pts[b] -= the
+ * same (grad_pts: n_points * D floats, zeroed by the caller).  Vertices
+ * (value 0) contribute nothing.  FP32 atomics: the summation order varies. */
+pms_status pms_backward_vr_f32(pms_ctx *ctx, const pms_filtration *f, int64_t n, const int32_t *simplex,
+                               const float *grad, const float *pts, int32_t D, int64_t n_points, float *grad_pts);
+
 /* Per-kernel timing, opt-in.  pms_profile_enable(ctx, 1) zeroes the totals
  * and from then on records a HIP event pair on ctx's stream around every
  * kernel launch of the library, with the launch's algorithmic bytes (the

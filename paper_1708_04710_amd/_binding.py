@@ -32,7 +32,7 @@ EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
     "pms_reduce", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
-    "pms_filtration_free",
+    "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
 ]
 
 
@@ -113,6 +113,12 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, nm)
         fn.argtypes = [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_int32, ctypes.POINTER(P), P]
         fn.restype = ctypes.c_int
+    lib.pms_gather.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    lib.pms_gather.restype = ctypes.c_int
+    lib.pms_backward_lowerstar.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int64]
+    lib.pms_backward_lowerstar.restype = ctypes.c_int
+    lib.pms_backward_vr_f32.argtypes = [P, P, ctypes.c_int64, P, P, P, ctypes.c_int32, ctypes.c_int64, P]
+    lib.pms_backward_vr_f32.restype = ctypes.c_int
     lib.pms_filtration_view_get.argtypes = [P, ctypes.POINTER(PmsFiltrationView)]
     lib.pms_filtration_view_get.restype = ctypes.c_int
     lib.pms_filtration_copy_out.argtypes = [P, P, P, P, P, P, P, P]

@@ -1,0 +1,192 @@
+"""Backward pass through the fixed pairing.
+
+Lower-star: the gradient of the total H1 persistence is an integer count per
+grid vertex (+1 at a death's critical vertex, -1 at a birth's), so the FP32
+result must equal the count exactly, and central differences of the loss
+must agree where the perturbation keeps the filtration order.
+
+Vietoris-Rips (FP32 clouds): the FP32 gradient of sum over H1 pairs of
+(death - birth)^2 is compared norm-wise with the FP64 gradient on the same
+pairing (rel. error <= 1e-5), and with central differences of the FP64
+pipeline (h = 1e-4) on coordinates whose perturbation keeps the order."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1708_04710_amd import autograd, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+# ---------------------------------------------------------------- lower-star
+def _crit_vertex(f, grid_flat):
+    vv = np.where(f.verts >= 0, grid_flat[np.maximum(f.verts, 0)], -np.inf)
+    best = vv.max(axis=1, keepdims=True)
+    return np.where(vv == best, f.verts, -1).max(axis=1)
+
+
+def _h1_persistence_grad_ref(g):
+    f = oracle.build_lowerstar(g)
+    low = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    b, d = oracle.pairs(low)
+    h1 = f.dim[b] == 1
+    crit = _crit_vertex(f, g.reshape(-1))
+    ref = np.zeros(g.size, np.float64)
+    np.add.at(ref, crit[d[h1]], 1.0)
+    np.add.at(ref, crit[b[h1]], -1.0)
+    loss = float((f.value[d[h1]].astype(np.float64) - f.value[b[h1]].astype(np.float64)).sum())
+    return ref.reshape(g.shape), loss, f
+
+
+def _gpu_h1_grad(g, dev):
+    x = torch.as_tensor(g, device=dev).requires_grad_(True)
+    bv, dv, dims = autograd.persistence_lowerstar(x)
+    h1 = dims == 1
+    loss = (dv[h1] - bv[h1]).sum()
+    loss.backward()
+    return x.grad.detach().cpu().numpy(), float(loss.detach())
+
+
+@pytest.mark.parametrize("shape", [(6, 7, 8), (11, 9, 13)])
+def test_lowerstar_h1_grad_counts_and_fd(gpu, shape):
+    g = synth.random_grid(51, shape)
+    ref, loss_ref, f = _h1_persistence_grad_ref(g)
+    got, loss = _gpu_h1_grad(g, gpu)
+    assert np.array_equal(got, ref.astype(np.float32))
+    assert abs(loss - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+    # central differences on vertices with a nonzero gradient and a few zeros
+    flat = g.reshape(-1)
+    vals = np.unique(flat)
+    gap = np.diff(vals).min()
+    rng = np.random.default_rng(1)
+    picks = list(np.nonzero(ref.reshape(-1))[0][:4]) + list(rng.choice(g.size, 3, replace=False))
+    checked = 0
+    for v in picks:
+        h = np.float32(gap / 4)
+        gp, gm = flat.copy(), flat.copy()
+        gp[v] = np.float32(gp[v] + h)
+        gm[v] = np.float32(gm[v] - h)
+        hp, hm = float(gp[v]) - float(flat[v]), float(flat[v]) - float(gm[v])
+        if hp <= 0 or hm <= 0:
+            continue
+        _, lp, fp = _h1_persistence_grad_ref(gp.reshape(g.shape))
+        _, lm, fm = _h1_persistence_grad_ref(gm.reshape(g.shape))
+        if not (np.array_equal(fp.verts, f.verts) and np.array_equal(fm.verts, f.verts)):
+            continue  # the perturbation changed the order: not a point of differentiability
+        fd = (lp - lm) / (hp + hm)
+        assert abs(fd - ref.reshape(-1)[v]) < 1e-3, (v, fd, ref.reshape(-1)[v])
+        checked += 1
+    assert checked >= 3
+
+
+def test_lowerstar_h1_grad_gaussian_64(gpu):
+    g = synth.gaussian_field()
+    ref, loss_ref, _ = _h1_persistence_grad_ref(g)
+    got, loss = _gpu_h1_grad(g, gpu)
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------- Vietoris-Rips
+def _sqd64(x, a, b):
+    d = x[a] - x[b]
+    return float(d @ d)
+
+
+def _vr_loss_grad64(x32, with_grad=True):
+    """FP64 loss and gradient on the pairing of the FP32 filtration."""
+    f = oracle.build_vr_f32(x32, -1.0, 2)
+    low = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    b, d = oracle.pairs(low)
+    h1 = f.dim[b] == 1
+    x = x32.astype(np.float64)
+    loss, grad = 0.0, np.zeros_like(x)
+    for bi, di in zip(b[h1], d[h1]):
+        ba, bb = f.verts[bi][:2]
+        last = f.rows[f.col_ptr[di + 1] - 1]
+        da, db = f.verts[last][:2]
+        pers = _sqd64(x, da, db) - _sqd64(x, ba, bb)
+        loss += pers * pers
+        if with_grad:
+            w = 2.0 * pers
+            grad[da] += w * 2.0 * (x[da] - x[db])
+            grad[db] -= w * 2.0 * (x[da] - x[db])
+            grad[ba] -= w * 2.0 * (x[ba] - x[bb])
+            grad[bb] += w * 2.0 * (x[ba] - x[bb])
+    return loss, grad, f
+
+
+def _h1_signature(f, low):
+    """The H1 pairs as (birth edge, death triangle's critical edge) vertex
+    tuples: the loss is a smooth function of the points wherever this set
+    does not change."""
+    b, d = oracle.pairs(low)
+    h1 = f.dim[b] == 1
+    last = f.rows[f.col_ptr[d[h1] + 1] - 1]
+    return sorted(zip(map(tuple, f.verts[b[h1]][:, :2]), map(tuple, f.verts[last][:, :2])))
+
+
+def _vr_loss64_f64_pipeline(x64):
+    """Loss and H1 signature from the FP64 filtration (for finite differences)."""
+    f = oracle.build_vr_f64(x64, -1.0, 2)
+    low = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    b, d = oracle.pairs(low)
+    h1 = f.dim[b] == 1
+    pers = f.value[d[h1]] - f.value[b[h1]]
+    return float((pers * pers).sum()), _h1_signature(f, low)
+
+
+def _gpu_vr_grad(x, dev):
+    pts = torch.as_tensor(x, device=dev).requires_grad_(True)
+    bv, dv, dims, cloud = autograd.persistence_vr(pts)
+    h1 = dims == 1
+    loss = ((dv[h1] - bv[h1]) ** 2).sum()
+    loss.backward()
+    return pts.grad.detach().cpu().numpy()
+
+
+def test_vr_grad_vs_fp64_and_fd(gpu):
+    x = synth.circle_batch(seed=61, clouds=3, n=40)
+    got = _gpu_vr_grad(x, gpu)
+    for c in range(x.shape[0]):
+        loss, ref, f32f = _vr_loss_grad64(x[c])
+        err = np.linalg.norm(got[c] - ref) / np.linalg.norm(ref)
+        assert err <= TOL, (c, err)
+    # central differences of the FP64 pipeline at h = 1e-4
+    h = 1e-4
+    x0 = x[0].astype(np.float64)
+    _, ref0, f32f = _vr_loss_grad64(x[0])
+    _, sig0 = _vr_loss64_f64_pipeline(x0)
+    sig32 = _h1_signature(f32f, oracle.reduce_twist(f32f.col_ptr, f32f.rows, f32f.dim))
+    same_as_fp32 = sig0 == sig32
+    checked = skipped = 0
+    rng = np.random.default_rng(2)
+    top = np.argsort(-np.abs(ref0.reshape(-1)))[:6]
+    for k in list(top) + list(rng.choice(x0.size, 6, replace=False)):
+        xp, xm = x0.copy().reshape(-1), x0.copy().reshape(-1)
+        xp[k] += h
+        xm[k] -= h
+        lp, sp = _vr_loss64_f64_pipeline(xp.reshape(x0.shape))
+        lm, sm = _vr_loss64_f64_pipeline(xm.reshape(x0.shape))
+        if not (same_as_fp32 and sp == sig0 and sm == sig0):
+            skipped += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        scale = max(1.0, np.abs(ref0).max())
+        assert abs(fd - ref0.reshape(-1)[k]) <= 1e-4 * scale, (k, fd, ref0.reshape(-1)[k])
+        assert abs(fd - got[0].reshape(-1)[k]) <= 1e-4 * scale, (k, fd, got[0].reshape(-1)[k])
+        checked += 1
+    assert checked >= 6, (checked, skipped)
+
+
+def test_vr_grad_batch64_sampled(gpu):
+    """The 64-cloud x 128-point batch: FP32 gradients of all clouds in one
+    pass; two clouds checked against the FP64 gradient."""
+    x = synth.circle_batch()
+    got = _gpu_vr_grad(x, gpu)
+    for c in (0, 37):
+        _, ref, _ = _vr_loss_grad64(x[c])
+        err = np.linalg.norm(got[c] - ref) / np.linalg.norm(ref)
+        assert err <= TOL, (c, err)
