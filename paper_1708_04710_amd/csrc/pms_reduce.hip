@@ -58,6 +58,7 @@ enum StatId {
     // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
     // length, and shader cycles per phase of a short-pivot step
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CWAIT, S_T_CPASS1, S_T_CNEXT, S_T_CPASS2, S_T_QUEUED,
+    S_T_LANE, S_T_BAIL,
     S_NUM
 };
 
@@ -117,8 +118,9 @@ struct Dev {
     unsigned long long part_base, part_size;
     PivRec *prec;      // [m] pivot records by row
     int32_t *cq;       // chain queue, kPart slices of cq_slice entries
-    int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]
+    int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]; cq_n[kPart*32] = wq entries
     int64_t cq_slice;
+    int32_t *wq;       // columns handed from the lane chain kernel to the wavefront one
 };
 
 constexpr int kStripe = 64;
@@ -265,7 +267,7 @@ __global__ void k_low(Dev d, const int32_t *act, int32_t nA, uint32_t round)
 __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, int32_t nA, uint32_t round, I4 *agg)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < kPart) d.cq_n[q * 32] = 0;  // the chain queue of this round starts empty
+    if (q <= kPart) d.cq_n[q * 32] = 0;  // the chain queues of this round start empty
     I4 e = i4_fill(-1);
     if (q < nA) {
         const int32_t j = act[q];
@@ -570,6 +572,161 @@ __device__ inline uint32_t wave_or32(uint32_t x)
     return x;
 }
 
+// Lane chaining: one lane per queued column, the column in a per-lane LDS
+// buffer (entry e of lane t at sL[e * kLaneThreads + t], so a wave's lanes
+// hit consecutive banks).  Each step adds the pivot of the column's low; its
+// entries below the low (at most kRecInline, from the pivot record) are
+// merged in place from the top down, the larger column entries moving up by
+// the number of pivot entries still to place; cancelled pairs close the gap
+// by moving the merged top part down.  Columns that outgrow the buffer or
+// meet a longer pivot go to the wavefront kernel.
+constexpr int kLaneThreads = 128;
+constexpr int kLaneCap = 64;
+constexpr unsigned kLaneBlocks = 1024;
+constexpr int kLaneSteps = 48;  // a lane hands a longer chain to a wavefront
+
+__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace)
+{
+    __shared__ int32_t sL[kLaneCap * kLaneThreads];
+    __shared__ int32_t s_pre[kPart];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+#define LW(e) sL[(e) * kLaneThreads + tid]
+    if (tid < kPart) s_pre[tid] = d.cq_n[tid * 32];
+    __syncthreads();
+    if (tid == 0)
+        for (int p = 1; p < kPart; p++) s_pre[p] += s_pre[p - 1];  // inclusive prefix of the slice sizes
+    __syncthreads();
+    const int64_t total = s_pre[kPart - 1];
+    const int64_t gwave = (int64_t)blockIdx.x * (kLaneThreads / kWave) + tid / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kLaneThreads / kWave);
+    int64_t adds = 0, xe = 0, by = 0, bails = 0;
+    for (int64_t t0 = gwave * kWave; t0 < total; t0 += nwaves * kWave) {
+        const int64_t t = t0 + lane;
+        int32_t j = -1, L = 0;
+        bool bail = false, dirty = false;
+        if (t < total) {
+            int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] > t) hi = mid;
+                else lo = mid + 1;
+            }
+            const int64_t before = lo > 0 ? s_pre[lo - 1] : 0;
+            j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
+            L = d.len[j];
+            by += 16 + 4 * (int64_t)L;
+            if (L > kLaneCap) {
+                bail = true;
+            } else {
+                const int32_t *g = col_base(d, d.off[j]);
+                for (int32_t e = 0; e < L; e++) LW(e) = g[e];
+                int32_t i = LW(L - 1);
+                Look lk = look_up(d, i);
+                int steps = 0;
+                while (L > 0) {
+                    if (lk.s < 0) {
+                        if (compression && lk.neg) {  // a known-negative row: delete it
+                            L--;
+                            dirty = true;
+                            if (L == 0) break;
+                            i = LW(L - 1);
+                            lk = look_up(d, i);
+                            continue;
+                        }
+                        break;
+                    }
+                    const int32_t kk = lk.k - 1;
+                    if (kk > kRecInline || L - 1 + kk > kLaneCap || ++steps > kLaneSteps) {
+                        bail = true;
+                        break;
+                    }
+                    adds++;
+                    xe += (int64_t)L + kk + 1;
+                    by += 40;
+                    int32_t r = L - 2, w = L - 2 + kk, ncan = 0;
+#pragma unroll
+                    for (int q = kRecInline - 1; q >= 0; q--) {
+                        if (q < kk) {
+                            const int32_t x = lk.e[q];
+                            int32_t y = r >= 0 ? LW(r) : -1;
+                            while (y > x) {  // larger column entries move up past x
+                                LW(w) = y;
+                                w--;
+                                r--;
+                                y = r >= 0 ? LW(r) : -1;
+                            }
+                            if (y == x) {  // 1 + 1 = 0
+                                r--;
+                                ncan++;
+                            } else {
+                                LW(w) = x;
+                                w--;
+                            }
+                        }
+                    }
+                    const int32_t top = L - 2 + kk;
+                    if (ncan)
+                        for (int32_t e = w + 1; e <= top; e++) LW(e - 2 * ncan) = LW(e);
+                    L = L - 1 + kk - 2 * ncan;
+                    dirty = true;
+                    if (L == 0) break;
+                    const int32_t ni = LW(L - 1);
+                    if (ni >= i) {  // the low must drop; stop rather than spin
+                        atomicExch(&d.cnt->bad_source, 2);
+                        dirty = false;
+                        break;
+                    }
+                    i = ni;
+                    lk = look_up(d, i);
+                }
+            }
+        }
+        // write the changed columns back: one arena allocation per wave
+        const bool write = dirty && L > 0;
+        const int64_t need = write ? L : 0;
+        const int64_t incl = wave_incl_sum64(need);
+        const int64_t wtot = __shfl(incl, kWave - 1, kWave);
+        long long base = 0;
+        if (lane == 0 && wtot > 0) base = arena_alloc(d, (unsigned)gwave, wtot);
+        base = __shfl(base, 0, kWave);
+        if (write && base < 0) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
+        if (write && base >= 0) {
+            const int64_t o = base + incl - need;
+            for (int32_t e = 0; e < L; e++) d.arena[o + e] = LW(e);
+            d.off[j] = o | (int64_t)kArenaBit;
+            d.len[j] = L;
+            d.low[j] = LW(L - 1);
+            by += 4 * (int64_t)L + 16;
+        } else if (dirty && L == 0) {
+            d.len[j] = 0;
+            d.low[j] = -1;
+            d.state[j] = ST_ZERO;  // column j is positive
+        }
+        // hand the others over to the wavefront kernel
+        const unsigned long long bal = __ballot(bail);
+        int32_t qb = 0;
+        if (lane == 0 && bal) qb = atomicAdd(&d.cq_n[kPart * 32], (int32_t)__popcll(bal));
+        qb = __shfl(qb, 0, kWave);
+        if (bail) d.wq[qb + __popcll(bal & ((1ull << lane) - 1ull))] = j;
+        bails += bail ? 1 : 0;
+    }
+#undef LW
+    // counters: lane sums -> one atomic per wave
+    const int32_t a32 = (int32_t)adds;
+    const int64_t wadds = wave_incl_sum64(adds), wxe = wave_incl_sum64(xe), wby = wave_incl_sum64(by),
+                  wb = wave_incl_sum64(bails);
+    (void)a32;
+    if (lane == kWave - 1) {
+        stat_add(d, S_ADDS, (unsigned long long)wadds, (unsigned)gwave);
+        stat_add(d, S_XE, (unsigned long long)wxe, (unsigned)gwave);
+        stat_add(d, S_CBYTES, (unsigned long long)wby, (unsigned)gwave);
+        if (trace) {
+            stat_add(d, S_T_LANE, (unsigned long long)wadds, (unsigned)gwave);
+            stat_add(d, S_T_BAIL, (unsigned long long)wb, (unsigned)gwave);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression, int trace)
 {
     __shared__ int32_t sW[kChainWaves][2][kCapW];
@@ -577,19 +734,12 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     __shared__ int32_t sE[kChainWaves][kCapS + 1];
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
-    // queue slice sizes -> inclusive prefix (lane p holds slices 0..p)
-    const int32_t my_n = lane < kPart ? d.cq_n[lane * 32] : 0;
-    const int32_t pre = wave_incl_sum32(my_n);
-    const int32_t total = __shfl(pre, kWave - 1, kWave);
+    const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
     int64_t adds = 0, xe = 0, by = 0;
     unsigned long long tr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // trace: short, long, global, sumL, 4 phases, queued
     if (trace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
-        // static assignment: ticket t lives in the first slice whose prefix exceeds it
-        const unsigned long long over = __ballot(pre > t);
-        const int p = __ffsll((long long)over) - 1;
-        const int32_t before = p > 0 ? __shfl(pre, p - 1, kWave) : 0;
-        const int32_t j = d.cq[(int64_t)p * d.cq_slice + (t - before)];
+        const int32_t j = d.wq[t];
         int32_t L = d.len[j];
         by += 4 + 12 + 4 * (int64_t)L;  // queue entry, header, column in
         const int32_t *g = col_base(d, d.off[j]);
@@ -1126,12 +1276,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t *keep2 = (int32_t *)scratch(c, B_FLAGS, (nblk + 1) * 4);
     d.cq_slice = (nblk + kPart - 1) / kPart * kBlock;  // a slice takes every kPart-th tile
     d.cq = (int32_t *)scratch(c, B_TMP0, (size_t)kPart * d.cq_slice * 4);
-    d.cq_n = (int32_t *)scratch(c, B_CQN, kPart * 32 * 4);
+    d.cq_n = (int32_t *)scratch(c, B_CQN, (kPart + 1) * 32 * 4);
+    d.wq = (int32_t *)scratch(c, B_WQ, (size_t)m * 4);
     d.stats = (unsigned long long *)scratch(c, B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
     d.part = (unsigned long long *)scratch(c, B_PART, kPart * 16 * 8);
     d.prec = (PivRec *)scratch(c, B_PREC, (size_t)m * sizeof(PivRec));
     if (!d.off || !d.len || !d.low || !d.state || !d.beta || !d.left || !d.piv || !d.T || !d.neg || !d.coll ||
-        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec)
+        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec || !d.wq)
         return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
 
     // arena: sized for the first rounds' fill-in, grown on demand
@@ -1202,8 +1353,9 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, (unsigned)tiles, kBlock, d, act, nA, round, opt->variant,
                    opt->compression, opt->chain, opt->tail_active);
         const size_t xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
+        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
         const size_t chain_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_CHAIN, 0.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
         // act, state, act_next
@@ -1225,10 +1377,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             for (int q = 0; q < S_NUM; q++) { dl[q] = h->trace[q] - tprev[q]; tprev[q] = h->trace[q]; }
             const double st = (double)(dl[S_T_SHORT] ? dl[S_T_SHORT] : 1);
             fprintf(stderr,
-                    "pms round %u: active %d -> %d, new pivots %llu, additions %llu, chain queue %llu, chain steps "
-                    "short %llu long %llu global %llu, mean L %.1f, cycles/short step: wait %.0f pass1 %.0f next %.0f "
-                    "pass2 %.0f\n",
-                    round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_QUEUED], dl[S_T_SHORT], dl[S_T_LONG],
+                    "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
+                    "%llu, chain steps short %llu long %llu global %llu, mean L %.1f, cycles/short step: wait %.0f "
+                    "pass1 %.0f next %.0f pass2 %.0f\n",
+                    round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
+                    dl[S_T_LONG],
                     dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
                     dl[S_T_CWAIT] / st, dl[S_T_CPASS1] / st, dl[S_T_CNEXT] / st, dl[S_T_CPASS2] / st);
