@@ -7,7 +7,14 @@ whole device path on the grid already resident in HBM:
 
   filtration build (keys, sort, boundary matrix)  ->  pms reduction
   (Phase 0, rounds of Phase I / Phase II with clearing and compression)
-  ->  low*, the persistence pairs and the essential simplices.
+  ->  low*, the persistence pairs and the essential simplices
+  ->  values of the pairs and the backward pass of the total H1 persistence
+      to the grid values (through the critical vertices).
+
+The same run also times the batched Vietoris-Rips workloads against one call
+per cloud on the same GPU ("batched" field): 512 clouds of 32..256 points
+(reduction only) and 64 FP32 clouds of 128 points (reduction + backward of
+the sum of squared H1 persistences), each checked on the host for its size.
 
 Prints one JSON line.  ``value`` is simplices reduced per second over the
 whole step.  ``roofline`` prices the step's dominant kernel (largest summed
@@ -57,13 +64,204 @@ def cpu_baseline(grid_np, m_gpu):
             "n_pairs": int((low >= 0).sum())}
 
 
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1708_04710_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprof PMC runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None when
+    the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != _source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def _timed(fn, torch, reps=3):
+    fn()  # warm-up (allocations, first launches)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return min(ts)
+
+
+def batched_vs_plain(api, autograd, synth, torch, dev):
+    """Batched pms (+ backward) vs one plain pms call per cloud, same GPU."""
+    out = {}
+    # 512 integer clouds, own 30th-percentile thresholds (reduction only)
+    inst = synth.vr_batch()
+    clouds = [torch.as_tensor(p, device=dev) for p, _ in inst]
+    thrs = [t for _, t in inst]
+    meta = {}
+    wb, wp = api.Filtration(dev), api.Filtration(dev)  # reused device workspaces
+
+    def batch3():
+        f, off = api.build_vr(clouds, thrs, 2, out=wb)
+        r = api.reduce_filtration(f)
+        meta["m"], meta["rounds"], meta["adds"] = f.m, r.rounds, r.additions
+
+    def plain3():
+        for c, t in zip(clouds, thrs):
+            f, _ = api.build_vr([c], [t], 2, out=wp)
+            api.reduce_filtration(f)
+
+    tb, tp = _timed(batch3, torch), _timed(plain3, torch, reps=1)
+    out["vr512"] = {"clouds": len(clouds), "m": meta["m"], "rounds": meta["rounds"], "additions": meta["adds"],
+                    "batched_s": round(tb, 5), "plain_s": round(tp, 5), "speedup": round(tp / tb, 3),
+                    "batched_simplices_per_s": meta["m"] / tb}
+    # 64 FP32 circles x 128 points, full 2-skeleton: batched reduce + backward vs plain reduce
+    x = torch.as_tensor(synth.circle_batch(), device=dev)
+
+    def batch4():
+        pts = x.clone().requires_grad_(True)
+        bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=wb)
+        h1 = dims == 1
+        ((dv[h1] - bv[h1]) ** 2).sum().backward()
+        meta["m4"] = int(bv.grad_fn.f.m)
+
+    def plain4():
+        for c in range(x.shape[0]):
+            f, _ = api.build_vr([x[c]], None, 2, out=wp)
+            api.reduce_filtration(f)
+
+    tb, tp = _timed(batch4, torch), _timed(plain4, torch, reps=1)
+    out["circles64"] = {"clouds": int(x.shape[0]), "m": meta["m4"], "batched_with_backward_s": round(tb, 5),
+                        "plain_reduce_only_s": round(tp, 5), "speedup": round(tp / tb, 3),
+                        "batched_simplices_per_s": meta["m4"] / tb}
+    return out
+
+
+PROFILE_CMDS = [
+    "rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o ls64 -- python3 bench.py --steps 3 "
+    "--warmup 1 --no-cpu-baseline --no-batched --calibrate-copy",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o f -- python3 bench.py --steps 1 --warmup 0 "
+    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o w -- python3 bench.py --steps 1 --warmup 0 "
+    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy",
+]
+COPY_BYTES = 256 << 20
+
+
+def _slot(kernel_name):
+    """Profiler slot of a rocprof kernel name (pms::k_xor(...) -> k_xor)."""
+    if "rocprim" in kernel_name:
+        return "k_sort"
+    if "pms::" not in kernel_name:
+        return None
+    name = kernel_name.split("pms::", 1)[1].split("(", 1)[0].split("<", 1)[0]
+    return {"k_vr_dist": "k_vr_edges", "k_vr_count": "k_vr_tri", "k_vr_emit": "k_vr_tri",
+            "k_keep_count": "k_compact", "k_scan_max4": "k_scan", "k_scan_sum": "k_scan",
+            "k_fin_count": "k_finalize", "k_fin_scatter": "k_finalize", "k_gather": "k_finalize",
+            "k_backward_lowerstar": "k_backward", "k_backward_vr": "k_backward",
+            "k_fill_i32": "k_fill", "k_fill_u64": "k_fill", "k_iota": "k_fill", "k_part_init": "k_fill",
+            "k_stats_fold": "k_fill", "k_scan_i64": "k_build_scan", "k_tile_sums": "k_build_scan",
+            "k_tile_apply": "k_build_scan"}.get(name, name)
+
+
+def rocprof_summary(tdir, fdir, wdir, out_md):
+    """Summarise the three rocprofv3 runs (PROFILE_CMDS) into a text summary
+    and profiles/traffic.json (HBM bytes per launch, scaled by the copy)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(pattern):
+        hits = glob.glob(os.path.join(pattern))
+        if not hits:
+            raise SystemExit(f"no file matches {pattern}")
+        return hits[0]
+
+    stats = list(csv.DictReader(open(one(os.path.join(tdir, "*kernel_stats.csv")))))
+    trace = list(csv.DictReader(open(one(os.path.join(tdir, "*kernel_trace.csv")))))
+    fetch = list(csv.DictReader(open(one(os.path.join(fdir, "*counter_collection.csv")))))
+    write = list(csv.DictReader(open(one(os.path.join(wdir, "*counter_collection.csv")))))
+    def copies(rows):  # the calibration copies: the copy dispatches with the largest grid
+        cp = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        g = max(int(r["Grid_Size"]) for r in cp)
+        return [r for r in cp if int(r["Grid_Size"]) == g]
+
+    copy_rows, copy_w = copies(fetch), copies(write)
+    f_kib = sum(float(r["Counter_Value"]) for r in copy_rows) / len(copy_rows)
+    w_kib = sum(float(r["Counter_Value"]) for r in copy_w) / len(copy_w)
+    f_scale, w_scale = (COPY_BYTES / 1024) / f_kib, (COPY_BYTES / 1024) / w_kib
+    acc = defaultdict(lambda: [0.0, 0, 0.0, 0])
+    for rows, col, scale in ((fetch, 0, f_scale), (write, 2, w_scale)):
+        for r in rows:
+            sl = _slot(r["Kernel_Name"])
+            if sl is None:
+                continue
+            acc[sl][col] += float(r["Counter_Value"]) * 1024 * scale
+            acc[sl][col + 1] += 1
+    durs = defaultdict(list)
+    for r in trace:
+        sl = _slot(r["Kernel_Name"])
+        if sl:
+            durs[sl].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0)
+    kernels = {}
+    for sl, (fb, fn, wb, wn) in acc.items():
+        if fn and wn:
+            kernels[sl] = {"fetch_bytes_per_launch": fb / fn, "write_bytes_per_launch": wb / wn,
+                           "bytes_per_launch": fb / fn + wb / wn}
+    tj = {"source_hash": _source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+          "copy_bytes": COPY_BYTES, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(tj, fh, indent=1, sort_keys=True)
+    lines = ["# rocprofv3 summary: 64^3 lower-star step (build + pms reduce + pairs + backward)", "",
+             "Commands (run from the repository root; <T>, <F>, <W> are output folders):", ""]
+    lines += [f"    {c}" for c in PROFILE_CMDS]
+    lines += ["", "Summarised with: python3 bench.py --rocprof-summary <T> <F> <W> <this file>",
+              "", "## Kernel time (kernel trace, 3 timed + 1 warm-up steps)", "",
+              "| kernel (rocprof name, shortened) | calls | total ms | avg us |", "|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
+        lines.append(f"| {r['Name'][:70]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} |")
+    lines += ["", "## HBM traffic (PMC FETCH_SIZE / WRITE_SIZE per dispatch, one step)", "",
+              f"Copy calibration: a {COPY_BYTES >> 20} MiB device copy reads FETCH_SIZE = {f_kib:.0f} KiB and "
+              f"WRITE_SIZE = {w_kib:.0f} KiB (expected {COPY_BYTES >> 10} KiB each): scales "
+              f"fetch x{f_scale:.3f}, write x{w_scale:.3f}.", "",
+              "| slot | launches | avg us (trace) | fetch MB/launch | write MB/launch |", "|---|---|---|---|---|"]
+    for sl, k in sorted(kernels.items(), key=lambda kv: -sum(durs.get(kv[0], [0]))):
+        d = durs.get(sl, [])
+        avg = sum(d) / len(d) if d else float("nan")
+        lines.append(f"| {sl} | {len(d)} | {avg:.1f} | {k['fetch_bytes_per_launch'] / 1e6:.3f} | "
+                     f"{k['write_bytes_per_launch'] / 1e6:.3f} |")
+    lines += ["", f"Source hash of the kernels measured: {tj['source_hash']}", ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print(out_md)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
+        t, f, w, out = sys.argv[2:6]
+        rocprof_summary(t, f, w, out)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-kernel events")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (known bytes) to scale rocprof's FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path has no multi-GPU mode",
@@ -73,9 +271,16 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1708_04710_amd import api, synth
+    from paper_1708_04710_amd import api, autograd, synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     grid_np = synth.gaussian_field(seed=5, n=64, sigma=4.0)
     grid = torch.as_tensor(grid_np, device=dev)
     f = api.build_lowerstar(grid)
@@ -83,10 +288,14 @@ def main():
     state = {}
 
     def step():
-        api.build_lowerstar(grid, out=f)
-        res = api.reduce_filtration(f)
-        state["res"] = res
-        return res
+        x = grid.clone().requires_grad_(True)
+        bv, dv, dims = autograd.persistence_lowerstar(x, workspace=f)
+        h1 = dims == 1
+        loss = (dv[h1] - bv[h1]).sum()
+        loss.backward()
+        state["x"] = x
+        state["fn"] = (bv, dv, dims)
+        return loss
 
     for _ in range(args.warmup):
         step()
@@ -103,11 +312,14 @@ def main():
     if not args.no_profile:
         api.profile_enable(False, dev)
     ms = (t1 - t0) * 1000.0 / args.steps
-    res = state["res"]
+    bv, dv, dims = state["fn"]
+    res = bv.grad_fn.result if hasattr(bv.grad_fn, "result") else None
     m = f.m
-
-    # light self-check (no oracle on the GPU leg): a 3-ball has one essential class
-    assert res.essential.numel() == 1
+    g = state["x"].grad
+    # light self-checks (no oracle on the GPU leg): the gradient of a total
+    # persistence is a signed count of deaths minus births per vertex
+    assert g is not None and torch.equal(g, g.round())
+    n_pairs = int(bv.numel())
 
     roof = None
     kernels = {}
@@ -121,7 +333,7 @@ def main():
         avg_s = tot_ms / n / 1000.0
         ach = (by / n) / avg_s / 1e9 if avg_s > 0 else 0.0
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
                 "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": by / n}
 
     out = {
@@ -139,13 +351,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lowerstar_freudenthal_64^3_gaussian_field", "grid": [64, 64, 64],
                    "field": "white noise * Gaussian(sigma=4 cells, periodic), standardised, fp32, seed 5",
-                   "m": m, "nnz": f.nnz, "homology": "H0-H2", "step": "build + reduce + pairs",
-                   "rounds": res.rounds, "additions": res.additions, "n_pairs": int(res.pair_birth.numel()),
-                   "n_essential": int(res.essential.numel())},
+                   "m": m, "nnz": f.nnz, "homology": "H0-H2",
+                   "step": "build + reduce + pairs + gather + backward of total H1 persistence",
+                   "rounds": res.rounds if res else None, "additions": res.additions if res else None,
+                   "n_pairs": n_pairs, "n_essential": int(res.essential.numel()) if res else None},
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": None,
     }
+    if not args.no_batched:
+        out["batched"] = batched_vs_plain(api, autograd, synth, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid_np, m)
     print(json.dumps(out), flush=True)

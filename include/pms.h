@@ -129,7 +129,7 @@ typedef struct {
     /* host-visible outputs */
     int64_t n_pairs;
     int64_t n_essential;
-    int32_t rounds;         /* outer iterations run (Sec. 5: one Phase I + Phase II) */
+    int32_t rounds;         /* outer iterations run (Sec. 4: one Phase I + Phase II) */
     int32_t phase0_pivots;  /* pivots known from beta before any addition (Phase 0) */
     int64_t additions;      /* column additions performed (the paper's cost unit) */
     int64_t xor_entries;    /* entries read by those additions */

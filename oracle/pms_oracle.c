@@ -91,7 +91,7 @@ static int check_boundary(int64_t m, const int64_t *col_ptr, const int32_t *rows
 /*
  * Standard reduction.  stats (optional, 2 entries): [0] number of column
  * additions, [1] number of non-trivial scalar XORs (entries of the union of
- * the two supports, i.e. the operations 1+1, 1+0, 0+1 of Sec. 5.1).
+ * the two supports, i.e. the operations 1+1, 1+0, 0+1 of Sec. 4.1).
  */
 int oracle_reduce_standard(int64_t m, const int64_t *col_ptr, const int32_t *rows,
                            int32_t *low_star, int64_t *stats)

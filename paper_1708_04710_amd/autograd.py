@@ -32,8 +32,8 @@ class PersistenceLowerStar(torch.autograd.Function):
     """grid (nz, ny, nx) float32 -> (birth values, death values, pair dims)."""
 
     @staticmethod
-    def forward(ctx, grid, reduce_kw=None):
-        f = api.build_lowerstar(grid.detach())
+    def forward(ctx, grid, reduce_kw=None, workspace=None):
+        f = api.build_lowerstar(grid.detach(), out=workspace)
         res = api.reduce_filtration(f, **(reduce_kw or {}))
         idx = torch.cat([res.pair_birth, res.pair_death])
         vals, dims = gather(f, idx)
@@ -54,7 +54,7 @@ class PersistenceLowerStar(torch.autograd.Function):
         c = api._ctx(ctx.f.device)
         B.check(c, B.load().pms_backward_lowerstar(c, ctx.f.handle, ctx.idx.numel(), ctx.idx.data_ptr(),
                                                    g.data_ptr(), out.data_ptr(), out.numel()))
-        return out, None
+        return out, None, None
 
 
 class PersistenceVR(torch.autograd.Function):
@@ -63,12 +63,12 @@ class PersistenceVR(torch.autograd.Function):
     threshold unless ``thresholds`` is given, one squared distance per cloud)."""
 
     @staticmethod
-    def forward(ctx, points, maxdim=2, thresholds=None, reduce_kw=None):
+    def forward(ctx, points, maxdim=2, thresholds=None, reduce_kw=None, workspace=None):
         if points.dim() != 3 or points.dtype != torch.float32:
             raise ValueError("points must be a float32 tensor (B, n, D)")
         pts = points.detach().contiguous()
         nb, n, D = pts.shape
-        f, off = api.build_vr(list(pts.unbind(0)), thresholds, maxdim)
+        f, off = api.build_vr(list(pts.unbind(0)), thresholds, maxdim, out=workspace)
         res = api.reduce_filtration(f, **(reduce_kw or {}))
         idx = torch.cat([res.pair_birth, res.pair_death])
         vals, dims = gather(f, idx)
@@ -92,12 +92,19 @@ class PersistenceVR(torch.autograd.Function):
         c = api._ctx(ctx.f.device)
         B.check(c, B.load().pms_backward_vr_f32(c, ctx.f.handle, ctx.idx.numel(), ctx.idx.data_ptr(),
                                                 g.data_ptr(), ctx.pts.data_ptr(), ctx.D, npts, out.data_ptr()))
-        return out, None, None, None
+        return out, None, None, None, None
 
 
-def persistence_lowerstar(grid: torch.Tensor, **reduce_kw):
-    return PersistenceLowerStar.apply(grid, reduce_kw or None)
+def persistence_lowerstar(grid: torch.Tensor, workspace: api.Filtration | None = None, **reduce_kw):
+    """Pairs of the lower-star filtration of ``grid`` with differentiable
+    values.  ``workspace``: a Filtration whose device buffers are reused
+    (it holds this call's filtration until the next call that reuses it, so
+    run the backward of one call before the next forward)."""
+    return PersistenceLowerStar.apply(grid, reduce_kw or None, workspace)
 
 
-def persistence_vr(points: torch.Tensor, maxdim: int = 2, thresholds=None, **reduce_kw):
-    return PersistenceVR.apply(points, maxdim, thresholds, reduce_kw or None)
+def persistence_vr(points: torch.Tensor, maxdim: int = 2, thresholds=None,
+                   workspace: api.Filtration | None = None, **reduce_kw):
+    """Pairs of the Vietoris-Rips filtrations of a batch of FP32 clouds with
+    differentiable values (``workspace`` as in ``persistence_lowerstar``)."""
+    return PersistenceVR.apply(points, maxdim, thresholds, reduce_kw or None, workspace)

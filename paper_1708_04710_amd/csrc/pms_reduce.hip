@@ -58,7 +58,7 @@ enum StatId {
     // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
     // length, and shader cycles per phase of a short-pivot step
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CWAIT, S_T_CPASS1, S_T_CNEXT, S_T_CPASS2, S_T_QUEUED,
-    S_T_LANE, S_T_BAIL,
+    S_T_LANE, S_T_BAIL, S_LBYTES,
     S_NUM
 };
 
@@ -68,6 +68,7 @@ struct Counters {
     unsigned long long xor_entries;  // entries read by them
     unsigned long long xor_bytes;    // algorithmic bytes moved by k_xor
     unsigned long long chain_bytes;  // algorithmic bytes moved by k_chain
+    unsigned long long lane_bytes;   // algorithmic bytes moved by k_chain_lane
     int32_t error;       // 1 = not compatible
     int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
@@ -719,7 +720,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, (unsigned)gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, (unsigned)gwave);
-        stat_add(d, S_CBYTES, (unsigned long long)wby, (unsigned)gwave);
+        stat_add(d, S_LBYTES, (unsigned long long)wby, (unsigned)gwave);
         if (trace) {
             stat_add(d, S_T_LANE, (unsigned long long)wadds, (unsigned)gwave);
             stat_add(d, S_T_BAIL, (unsigned long long)wb, (unsigned)gwave);
@@ -1115,6 +1116,7 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->xor_entries = s_sum[S_XE];
         d.cnt->xor_bytes = s_sum[S_XBYTES];
         d.cnt->chain_bytes = s_sum[S_CBYTES];
+        d.cnt->lane_bytes = s_sum[S_LBYTES];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
         for (int q = 0; q < S_NUM; q++) d.cnt->trace[q] = s_sum[q];
@@ -1327,7 +1329,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
-    unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0;
+    unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0;
     const char *tr_env = getenv("PMS_TRACE");
     const int trace = tr_env && tr_env[0] == '1';
     unsigned long long tprev[S_NUM] = {};
@@ -1353,9 +1355,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, (unsigned)tiles, kBlock, d, act, nA, round, opt->variant,
                    opt->compression, opt->chain, opt->tail_active);
         const size_t xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
+        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
+        const size_t lane_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
         const size_t chain_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN, 0.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
         // act, state, act_next
@@ -1370,6 +1373,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             xor_bytes_prev = h->xor_bytes;
             c->pend[chain_slot].bytes = (double)(h->chain_bytes - chain_bytes_prev);
             chain_bytes_prev = h->chain_bytes;
+            c->pend[lane_slot].bytes = (double)(h->lane_bytes - lane_bytes_prev);
+            lane_bytes_prev = h->lane_bytes;
             prof_flush(c);
         }
         if (trace) {
@@ -1488,7 +1493,7 @@ void pms_destroy(pms_ctx *c)
 static const char *const kKernelNames[pms::K_NUM] = {
     "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
     "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
-    "k_vr_index", "k_vr_rows", "k_backward", "k_chain"};
+    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane"};
 
 pms_status pms_profile_enable(pms_ctx *c, int enable)
 {
