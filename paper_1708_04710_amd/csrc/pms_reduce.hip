@@ -56,9 +56,9 @@ constexpr int kScanThreads = 1024;
 enum StatId {
     S_ADDS = 0, S_XE, S_XBYTES, S_CBYTES, S_NEWPIV, S_BETAPIV,
     // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
-    // length, and shader cycles per phase of a short-pivot step
-    S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CWAIT, S_T_CPASS1, S_T_CNEXT, S_T_CPASS2, S_T_QUEUED,
-    S_T_LANE, S_T_BAIL, S_LBYTES,
+    // length, shader cycles per phase of a short-pivot step, flushes, lows from P
+    S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
+    S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP,
     S_NUM
 };
 
@@ -508,13 +508,6 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
 }
 
 // ---------------------------------------------------------------- chaining
-// One wavefront per queued column.  The working column W stays in LDS while
-// it fits; each step adds the known pivot of W's low (a column that never
-// changes again), so the steps of the standard reduction's inner loop run
-// back to back without leaving the kernel.  A step merges the pivot column
-// S into W cooperatively: an entry's output position is its own index plus
-// its rank in the other list minus twice the number of cancelled pairs
-// below it.
 constexpr int kChainWaves = 4;
 constexpr unsigned kChainBlocks = 512;  // 2 per CU; waves take queue entries dynamically
 constexpr int kCapW = 1536;  // LDS entries per working buffer (two per wave)
@@ -543,7 +536,7 @@ __device__ inline int32_t lower_bound_i32(const int32_t *a, int32_t n, int32_t x
 struct Look {
     int32_t s, k;
     int32_t e[kRecInline];
-    bool neg;
+    int32_t neg;
 };
 
 __device__ inline Look look_up(const Dev &d, int32_t i)
@@ -728,6 +721,29 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     }
 }
 
+// Wavefront chaining, for the columns the lane kernel hands over (long
+// chains, long columns, long pivots).  The working column is W = B xor P:
+// B, a sorted base array (in LDS while it fits, else in the arena), only
+// ever loses entries at its top; P, a set of at most 64 pending row
+// toggles, lives one entry per lane.  A step with a short pivot removes the
+// low and toggles the pivot's entries below it into P with one ballot per
+// entry, so its cost does not grow with the length of W.  The pivot records
+// of the 64 topmost B entries and of every P entry are loaded ahead by the
+// lanes that hold them: the record of the next low is a register read, or a
+// load issued one step earlier.  B and P are merged into a new B when P is
+// full, before a long pivot (whose column is merged as a whole) and at the
+// end.
+__device__ inline Look read_look(const Look &v, int32_t l)
+{
+    Look r;
+    r.s = __builtin_amdgcn_readlane(v.s, l);
+    r.k = __builtin_amdgcn_readlane(v.k, l);
+#pragma unroll
+    for (int t = 0; t < kRecInline; t++) r.e[t] = __builtin_amdgcn_readlane(v.e[t], l);
+    r.neg = __builtin_amdgcn_readlane(v.neg, l);
+    return r;
+}
+
 __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression, int trace)
 {
     __shared__ int32_t sW[kChainWaves][2][kCapW];
@@ -735,256 +751,343 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     __shared__ int32_t sE[kChainWaves][kCapS + 1];
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
+    const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // the lanes under this one
     const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
     int64_t adds = 0, xe = 0, by = 0;
-    unsigned long long tr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // trace: short, long, global, sumL, 4 phases, queued
+    // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P
+    unsigned long long tr[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (trace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
         const int32_t j = d.wq[t];
-        int32_t L = d.len[j];
-        by += 4 + 12 + 4 * (int64_t)L;  // queue entry, header, column in
+        const int32_t L0 = d.len[j];
+        by += 4 + 12 + 4 * (int64_t)L0;  // queue entry, header, column in
         const int32_t *g = col_base(d, d.off[j]);
-        // W in LDS when it fits, else the current global column (read only)
         int cur = 0;
-        bool in_lds = L <= kCapW;
-        const int32_t *Wg = g;
+        bool in_lds = L0 <= kCapW;
+        const int32_t *Bg = g;  // B when it is not in LDS
         if (in_lds)
-            for (int32_t a = lane; a < L; a += kWave) sW[w][0][a] = g[a];
+            for (int32_t a = lane; a < L0; a += kWave) sW[w][0][a] = g[a];
         wave_sync();
-        bool dirty = false;  // W differs from the stored column
-        bool failed = false;
-        int32_t i = L > 0 ? (in_lds ? sW[w][0][L - 1] : Wg[L - 1]) : -1;
-        Look lk = look_up(d, i >= 0 ? i : 0);
-        while (L > 0) {
+        int32_t LB = L0;
+        uint64_t valid = 0;             // lanes holding an entry of P
+        int32_t pv = -1;                // this lane's entry of P
+        Look pr{};                      // and its record
+        int32_t wb = 0, wv = -1;        // window: this lane holds B[wb + lane]
+        Look wr{};                      // and its record
+        int32_t i = -1, pl = 0;         // the low, and its lane in P when from_p
+        bool from_p = false;
+        Look lk{};
+        bool dirty = false, failed = false;
+
+        auto Bp = [&]() -> const int32_t * { return in_lds ? (const int32_t *)sW[w][cur] : Bg; };
+        auto refill = [&]() {
+            wb = LB > kWave ? LB - kWave : 0;
+            const int32_t a = wb + lane;
+            wv = a < LB ? Bp()[a] : -1;
+            if (wv >= 0) wr = look_up(d, wv);
+        };
+        // the low of W = max(B) xor-combined with max(P): equal tops cancel
+        auto next = [&]() {
             const int64_t c0 = trace ? clock64() : 0;
-            const int32_t *W = in_lds ? sW[w][cur] : Wg;
-            if (lk.s < 0) {
-                // no pivot owns this low: a known-negative row is deleted
-                // (compression), anything else ends the chain
-                if (compression && lk.neg) {
-                    L--;
-                    dirty = true;
-                    if (L == 0) break;
-                    i = W[L - 1];
-                    lk = look_up(d, i);
-                    continue;
+            for (;;) {
+                if (LB > 0 && LB - 1 < wb) refill();
+                const bool pvld = (valid >> lane) & 1ull;
+                const int32_t pmax = valid ? wave_max_dpp(pvld ? pv + 1 : 0) - 1 : -1;
+                const int32_t bt = LB > 0 ? __builtin_amdgcn_readlane(wv, LB - 1 - wb) : -1;
+                if (pmax < 0 && bt < 0) {
+                    i = -1;
+                    break;
                 }
+                if (pmax >= bt) {
+                    const uint64_t hit = __ballot(pvld && pv == pmax);
+                    const int32_t l = (int32_t)__builtin_ctzll(hit);
+                    if (pmax == bt) {  // 1 + 1 = 0
+                        valid &= ~(1ull << l);
+                        LB--;
+                        continue;
+                    }
+                    i = pmax;
+                    pl = l;
+                    from_p = true;
+                    lk = read_look(pr, l);
+                    if (trace) tr[9]++;
+                    break;
+                }
+                i = bt;
+                from_p = false;
+                lk = read_look(wr, LB - 1 - wb);
                 break;
             }
-            const int32_t k = lk.k;
-            adds++;
-            xe += (int64_t)L + k;
-            if (in_lds && k - 1 <= kRecInline && L + k <= kCapW) {
-                // short pivot: its entries below the low are in registers;
-                // merge W[0, L-1) with them (the two lows cancel)
-                by += 40;  // piv, record, neg word
-                const int32_t kk = k - 1, Lp = L - 1;
-                int32_t sv[kRecInline];
+            if (trace) tr[5] += clock64() - c0;
+        };
+        auto pop = [&]() {
+            if (from_p) valid &= ~(1ull << pl);
+            else LB--;
+        };
+        // toggle the entries s.e[0, kk) into P (needs kk free lanes)
+        auto toggle = [&](int32_t kk, const Look &s) {
+            const int64_t c0 = trace ? clock64() : 0;
+            const bool pvld = (valid >> lane) & 1ull;
+            bool hit = false;
+            uint32_t present = 0;
 #pragma unroll
-                for (int q = 0; q < kRecInline; q++) sv[q] = q < kk ? lk.e[q] : 0x7FFFFFFF;
-                int64_t c1 = 0;
-                if (trace) {
-                    c1 = clock64() + (sv[0] & 0);  // after the record arrived
-                    tr[0]++;
-                    tr[3] += L;
-                    tr[4] += c1 - c0;
+            for (int q = 0; q < kRecInline; q++) {
+                if (q < kk) {
+                    const bool h = pvld && pv == s.e[q];
+                    hit = hit || h;
+                    if (__ballot(h)) present |= 1u << q;
                 }
-                // pass 1: ranks of the pivot's entries in W' (packed two per
-                // word: they are below 2^11), the cancellation mask (each bit
-                // is set by at most one lane, so a sum is an or), and the
-                // largest entry of W' that survives
-                int32_t pk0 = 0, pk1 = 0, pk2 = 0, eqm_l = 0, topw = -1;
-                for (int32_t a = lane; a < Lp; a += kWave) {
-                    const int32_t x = W[a];
-                    bool e = false;
-#pragma unroll
-                    for (int q = 0; q < kRecInline; q++) {
-                        const int32_t lt = x < sv[q] ? 1 : 0;
-                        if (q == 0) pk0 += lt;
-                        if (q == 1) pk0 += lt << 16;
-                        if (q == 2) pk1 += lt;
-                        if (q == 3) pk1 += lt << 16;
-                        if (q == 4) pk2 += lt;
-                        if (q == 5) pk2 += lt << 16;
-                        const bool eq = x == sv[q];
-                        eqm_l |= (eq ? 1 : 0) << q;
-                        e |= eq;
-                    }
-                    if (!e) topw = x;  // ascending stripe: the last survivor is the largest
-                }
-                pk0 = wave_sum_dpp(pk0);
-                pk1 = wave_sum_dpp(pk1);
-                pk2 = wave_sum_dpp(pk2);
-                const uint32_t eqm = (uint32_t)wave_sum_dpp(eqm_l);
-                const int32_t cand_w = wave_max_dpp(topw + 1) - 1;
-                int32_t cnt[kRecInline] = {pk0 & 0xFFFF, pk0 >> 16, pk1 & 0xFFFF, pk1 >> 16, pk2 & 0xFFFF, pk2 >> 16};
-                int64_t c2 = 0;
-                if (trace) {
-                    c2 = clock64() + (eqm & 0);
-                    tr[5] += c2 - c1;
-                }
-                // next low: the larger of the two surviving tops
-                int32_t ts = kk - 1;
-                while (ts >= 0 && ((eqm >> ts) & 1u)) ts--;
-                const int32_t cand_s = ts >= 0 ? sv[ts] : -1;
-                const int32_t nxt = cand_s > cand_w ? cand_s : cand_w;
-                const Look nlk = look_up(d, nxt >= 0 ? nxt : 0);  // in flight during the writes
-                int64_t c3 = 0;
-                if (trace) {
-                    c3 = clock64() + (nxt & 0);
-                    tr[6] += c3 - c2;
-                }
-                int32_t *Wn = sW[w][cur ^ 1];
-                for (int32_t a = lane; a < Lp; a += kWave) {
-                    const int32_t x = W[a];
-                    int32_t r = 0;
-                    bool e = false;
-#pragma unroll
-                    for (int q = 0; q < kRecInline; q++) {
-                        r += sv[q] < x ? 1 : 0;
-                        e |= (x == sv[q]);
-                    }
-                    if (!e) Wn[a + r - 2 * __popc(eqm & ((1u << r) - 1u))] = x;
-                }
-                if (lane < kk && !((eqm >> lane) & 1u)) {
-                    int32_t c = 0;
-#pragma unroll
-                    for (int q = 0; q < kRecInline; q++)
-                        if (q == lane) c = cnt[q];
-                    const int32_t o = lane + c - 2 * __popc(eqm & ((1u << lane) - 1u));
-                    if (o >= 0 && o < kCapW) Wn[o] = sv[lane];  // always true; checked by the nxt test below
-                }
-                const int32_t nL = Lp + kk - 2 * __popc(eqm);
-                wave_sync();
-                if (trace) tr[7] += clock64() - c3;
-                if (nxt >= i || (nL > 0 && Wn[nL - 1] != nxt) || (nL == 0) != (nxt < 0)) {
-                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);  // never expected
-                    failed = true;
-                    break;
-                }
-                L = nL;
-                cur ^= 1;
-                dirty = true;
-                i = nxt;
-                lk = nlk;
-                continue;
             }
-            // long pivot: its column comes from the arena / the input
-            by += 40 + 12 + 4 * (int64_t)k;
-            if (trace) {
-                tr[3] += L;
-                if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
-                else tr[2]++;
-            }
-            const int32_t *Sg = col_base(d, d.off[lk.s]);
-            if (in_lds && L + k <= kCapW && k <= kCapS) {
-                for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
-                wave_sync();
-                const int32_t *S = sS[w];
-                int32_t *Wn = sW[w][cur ^ 1];
-                // cancelled pairs: exclusive prefix count over S
-                int32_t carry = 0;
-                for (int32_t base = 0; base < k; base += kWave) {
-                    const int32_t b = base + lane;
-                    int32_t e = 0;
-                    if (b < k) {
-                        const int32_t q = lower_bound_i32(W, L, S[b]);
-                        e = (q < L && W[q] == S[b]) ? 1 : 0;
+            valid &= ~__ballot(hit);
+            const uint64_t freem = ~valid;
+            const int32_t nins = kk - __popc(present);
+            const int32_t frk = __popcll(freem & below);
+            const bool mine = ((freem >> lane) & 1ull) && frk < nins;
+            if (mine) {
+                int32_t x = -1, c = 0;
+#pragma unroll
+                for (int q = 0; q < kRecInline; q++) {
+                    if (q < kk && !((present >> q) & 1u)) {
+                        if (c == frk) x = s.e[q];
+                        c++;
                     }
-                    const int32_t incl = wave_incl_sum32(e);
-                    if (b < k) sE[w][b] = carry + incl - e;
-                    carry += __shfl(incl, kWave - 1, kWave);
                 }
-                if (lane == 0) sE[w][k] = carry;
-                wave_sync();
-                for (int32_t a = lane; a < L; a += kWave) {
-                    const int32_t x = W[a];
-                    const int32_t r = lower_bound_i32(S, k, x);
-                    if (!(r < k && S[r] == x)) Wn[a + r - 2 * sE[w][r]] = x;
-                }
-                for (int32_t b = lane; b < k; b += kWave) {
-                    const int32_t x = S[b];
-                    const int32_t q = lower_bound_i32(W, L, x);
-                    if (!(q < L && W[q] == x)) Wn[b + q - 2 * sE[w][b]] = x;
-                }
-                const int32_t nL = L + k - 2 * carry;
-                wave_sync();
-                if (nL > 0 && Wn[nL - 1] >= i) {  // the low must drop; stop rather than spin
-                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);
-                    failed = true;
-                    break;
-                }
-                L = nL;
-                cur ^= 1;
-                dirty = true;
+                pv = x;
+                pr = look_up(d, x);
+            }
+            valid |= __ballot(mine);
+            if (trace) tr[4] += clock64() - c0;
+        };
+        // B := B xor P (P emptied), into the free LDS buffer or the arena
+        auto flush = [&]() -> bool {
+            const int64_t c0 = trace ? clock64() : 0;
+            const int32_t np = __popcll(valid);
+            const int32_t cap = LB + np;
+            const int nb = in_lds ? cur ^ 1 : 0;
+            int32_t *dst;
+            bool dst_lds = cap <= kCapW;
+            if (dst_lds) {
+                dst = sW[w][nb];
             } else {
-                // too long for LDS: lane 0 merges in global memory
                 long long o = 0;
-                const int64_t need = (int64_t)L + k;
-                if (lane == 0) o = arena_alloc(d, gw, need);
+                if (lane == 0) o = arena_alloc(d, gw, cap);
                 o = __shfl(o, 0, kWave);
                 if (o < 0) {
                     if (lane == 0) atomicExch(&d.cnt->overflow, 1);
-                    failed = true;  // keep the stored column; redo next round
-                    break;
+                    return false;  // keep the stored column; redo next round
                 }
-                int32_t *out = d.arena + o;
-                int32_t nL = 0;
-                if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
-                nL = __shfl(nL, 0, kWave);
-                __threadfence();  // lane 0's global writes, then every lane reads them
-                wave_sync();
-                if (nL > 0 && out[nL - 1] >= i) {  // the low must drop; stop rather than spin
-                    if (lane == 0) atomicExch(&d.cnt->bad_source, 2);
-                    failed = true;
-                    break;
-                }
-                Wg = out;
-                L = nL;
-                in_lds = false;
-                dirty = true;
+                dst = d.arena + o;
             }
-            if (L == 0) break;
-            i = (in_lds ? sW[w][cur] : Wg)[L - 1];
-            lk = look_up(d, i);
+            const int32_t *B = Bp();
+            int32_t *sc = sE[w];  // [0,64) P by lane, [64,128) P sorted, [128,192) cancel flags, [192,256) their prefix
+            const bool pvld = (valid >> lane) & 1ull;
+            const int32_t my = pvld ? pv : 0x7FFFFFFF;
+            wave_sync();
+            sc[lane] = my;
+            wave_sync();
+            int32_t rk = 0;
+            for (int u = 0; u < kWave; u++) rk += sc[u] < my ? 1 : 0;
+            int32_t q = 0;
+            bool cq = false;
+            if (pvld) {
+                q = lower_bound_i32(B, LB, my);
+                cq = q < LB && B[q] == my;
+                sc[64 + rk] = my;
+                sc[128 + rk] = cq ? 1 : 0;
+            }
+            wave_sync();
+            const int32_t ct = lane < np ? sc[128 + lane] : 0;
+            const int32_t incl = wave_incl_sum32(ct);
+            const int32_t totc = __builtin_amdgcn_readlane(incl, kWave - 1);
+            sc[192 + lane] = incl - ct;
+            wave_sync();
+            const int32_t nL = cap - 2 * totc;
+            if (pvld && !cq) {
+                const int32_t o = q + rk - 2 * sc[192 + rk];
+                if (o >= 0 && o < nL) dst[o] = my;
+            }
+            const int32_t cs = ((LB + kWave - 1) / kWave) | 1;  // odd chunks: lanes start in different banks
+            const int32_t a0 = lane * cs, a1 = min(a0 + cs, LB);
+            if (a0 < a1) {
+                int32_t r = lower_bound_i32(sc + 64, np, B[a0]);
+                for (int32_t a = a0; a < a1; a++) {
+                    const int32_t x = B[a];
+                    while (r < np && sc[64 + r] < x) r++;
+                    if (r < np && sc[64 + r] == x) continue;
+                    const int32_t o = a + r - 2 * (r < np ? sc[192 + r] : totc);
+                    if (o >= 0 && o < nL) dst[o] = x;
+                }
+            }
+            if (!dst_lds) __threadfence();
+            wave_sync();
+            valid = 0;
+            LB = nL;
+            if (dst_lds) {
+                in_lds = true;
+                cur = nb;
+            } else {
+                in_lds = false;
+                Bg = dst;
+            }
+            refill();
+            if (trace) {
+                tr[6] += clock64() - c0;
+                tr[7]++;
+            }
+            return true;
+        };
+
+        refill();
+        next();
+        while (i >= 0) {
+            const int32_t pi = i;
+            if (lk.s < 0) {
+                // no pivot owns this low: a known-negative row is deleted
+                // (compression), anything else ends the chain
+                if (!(compression && lk.neg)) break;
+                pop();
+                dirty = true;
+            } else {
+                const int32_t k = lk.k, kk = k - 1;
+                adds++;
+                xe += (int64_t)LB + __popcll(valid) + k;
+                if (kk <= kRecInline) {
+                    if (__popcll(valid) + kk > kWave) {
+                        if (!flush()) {
+                            failed = true;
+                            break;
+                        }
+                        from_p = false;  // W is unchanged: its low is now the top of B
+                    }
+                    by += 40;  // piv, record, neg word of the low
+                    if (trace) {
+                        tr[0]++;
+                        tr[3] += LB + __popcll(valid);
+                    }
+                    pop();
+                    toggle(kk, lk);
+                    dirty = true;
+                } else {
+                    // long pivot: merge its whole column into W = B
+                    if (valid && !flush()) {
+                        failed = true;
+                        break;
+                    }
+                    const int32_t L = LB;
+                    const int32_t *W = Bp();
+                    by += 40 + 12 + 4 * (int64_t)k;
+                    if (trace) {
+                        tr[3] += L;
+                        if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
+                        else tr[2]++;
+                    }
+                    const int32_t *Sg = col_base(d, d.off[lk.s]);
+                    if (in_lds && L + k <= kCapW && k <= kCapS) {
+                        for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
+                        wave_sync();
+                        const int32_t *S = sS[w];
+                        int32_t *Wn = sW[w][cur ^ 1];
+                        // cancelled pairs: exclusive prefix count over S
+                        int32_t carry = 0;
+                        for (int32_t base = 0; base < k; base += kWave) {
+                            const int32_t b = base + lane;
+                            int32_t e = 0;
+                            if (b < k) {
+                                const int32_t qq = lower_bound_i32(W, L, S[b]);
+                                e = (qq < L && W[qq] == S[b]) ? 1 : 0;
+                            }
+                            const int32_t inc = wave_incl_sum32(e);
+                            if (b < k) sE[w][b] = carry + inc - e;
+                            carry += __shfl(inc, kWave - 1, kWave);
+                        }
+                        if (lane == 0) sE[w][k] = carry;
+                        wave_sync();
+                        // an entry's output position: its own index plus its
+                        // rank in the other list minus twice the number of
+                        // cancelled pairs below it
+                        for (int32_t a = lane; a < L; a += kWave) {
+                            const int32_t x = W[a];
+                            const int32_t r = lower_bound_i32(S, k, x);
+                            if (!(r < k && S[r] == x)) Wn[a + r - 2 * sE[w][r]] = x;
+                        }
+                        for (int32_t b = lane; b < k; b += kWave) {
+                            const int32_t x = S[b];
+                            const int32_t qq = lower_bound_i32(W, L, x);
+                            if (!(qq < L && W[qq] == x)) Wn[b + qq - 2 * sE[w][b]] = x;
+                        }
+                        LB = L + k - 2 * carry;
+                        wave_sync();
+                        cur ^= 1;
+                    } else {
+                        // too long for LDS: lane 0 merges in global memory
+                        long long o = 0;
+                        const int64_t need = (int64_t)L + k;
+                        if (lane == 0) o = arena_alloc(d, gw, need);
+                        o = __shfl(o, 0, kWave);
+                        if (o < 0) {
+                            if (lane == 0) atomicExch(&d.cnt->overflow, 1);
+                            failed = true;  // keep the stored column; redo next round
+                            break;
+                        }
+                        int32_t *out = d.arena + o;
+                        int32_t nL = 0;
+                        if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
+                        nL = __shfl(nL, 0, kWave);
+                        __threadfence();  // lane 0's global writes, then every lane reads them
+                        wave_sync();
+                        Bg = out;
+                        in_lds = false;
+                        LB = nL;
+                    }
+                    dirty = true;
+                    refill();
+                }
+            }
+            next();
+            if (i >= pi) {  // the low must drop; stop rather than spin
+                if (lane == 0) atomicExch(&d.cnt->bad_source, 2);  // never expected
+                failed = true;
+                break;
+            }
         }
+        if (!failed && valid && !flush()) failed = true;
         if (failed || !dirty) continue;
         // write the result back
-        if (L == 0) {
+        if (LB == 0) {
             if (lane == 0) {
                 d.len[j] = 0;
                 d.low[j] = -1;
-                d.state[j] = ST_ZERO;
+                d.state[j] = ST_ZERO;  // column j is positive
             }
             continue;
         }
         int64_t dst;
         if (in_lds) {
             long long o = 0;
-            if (lane == 0) o = arena_alloc(d, gw, L);
+            if (lane == 0) o = arena_alloc(d, gw, LB);
             o = __shfl(o, 0, kWave);
             if (o < 0) {
                 if (lane == 0) atomicExch(&d.cnt->overflow, 1);
                 continue;  // progress of this chain is dropped; the stored column is still valid
             }
             const int32_t *W = sW[w][cur];
-            for (int32_t a = lane; a < L; a += kWave) d.arena[o + a] = W[a];
+            for (int32_t a = lane; a < LB; a += kWave) d.arena[o + a] = W[a];
             dst = (int64_t)o;
         } else {
-            dst = (int64_t)(Wg - d.arena);
-            if (Wg == g) {  // only trailing deletions: the stored column, shortened
+            if (Bg == g) {  // only deletions at the top: the stored column, shortened
                 if (lane == 0) {
-                    d.len[j] = L;
-                    d.low[j] = Wg[L - 1];
+                    d.len[j] = LB;
+                    d.low[j] = Bg[LB - 1];
                 }
                 continue;
             }
+            dst = (int64_t)(Bg - d.arena);
         }
-        by += 4 * (int64_t)L + 16;  // column and header out
+        by += 4 * (int64_t)LB + 16;  // column and header out
         if (lane == 0) {
             d.off[j] = dst | (int64_t)kArenaBit;
-            d.len[j] = L;
-            d.low[j] = in_lds ? sW[w][cur][L - 1] : Wg[L - 1];
+            d.len[j] = LB;
+            d.low[j] = in_lds ? sW[w][cur][LB - 1] : Bg[LB - 1];
         }
         wave_sync();
     }
@@ -993,8 +1096,10 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         stat_add(d, S_ADDS, (unsigned long long)adds, gw);
         stat_add(d, S_XE, (unsigned long long)xe, gw);
         stat_add(d, S_CBYTES, (unsigned long long)by, gw);
-        if (trace)
+        if (trace) {
             for (int q = 0; q < 9; q++) stat_add(d, S_T_SHORT + q, tr[q], gw);
+            stat_add(d, S_T_FROMP, tr[9], gw);
+        }
     }
 }
 
@@ -1383,13 +1488,12 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             const double st = (double)(dl[S_T_SHORT] ? dl[S_T_SHORT] : 1);
             fprintf(stderr,
                     "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
-                    "%llu, chain steps short %llu long %llu global %llu, mean L %.1f, cycles/short step: wait %.0f "
-                    "pass1 %.0f next %.0f pass2 %.0f\n",
+                    "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
+                    "%llu, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
-                    dl[S_T_LONG],
-                    dl[S_T_GLOBAL],
+                    dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
-                    dl[S_T_CWAIT] / st, dl[S_T_CPASS1] / st, dl[S_T_CNEXT] / st, dl[S_T_CPASS2] / st);
+                    dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
         }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
