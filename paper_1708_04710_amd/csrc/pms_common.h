@@ -161,6 +161,25 @@ __device__ inline int32_t wave_max_dpp(int32_t v)
     return __builtin_amdgcn_readlane(v, kWave - 1);
 }
 
+// Broadcasts whose result the compiler knows to be wave-uniform (scalar
+// registers), unlike __shfl: control flow that depends on them stays scalar.
+__device__ inline int32_t bcast_first(int32_t x)
+{
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ inline long long bcast_first64(long long x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((unsigned long long)x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ inline int32_t bcast_lane(int32_t x, int32_t l)
+{
+    return __builtin_amdgcn_readlane(x, l);
+}
+
 // Inclusive wave scans (wave64, __shfl_up).
 __device__ inline int64_t wave_incl_sum64(int64_t x)
 {

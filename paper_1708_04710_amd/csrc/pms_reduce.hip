@@ -78,13 +78,16 @@ struct Counters {
     int32_t n_pairs;
     int32_t n_ess;
     int32_t bad_source;  // internal invariant broken (never expected)
-    int32_t pad[3];
+    int32_t max_chain;   // trace: most additions one column made in k_chain this round
+    int32_t pad[2];
     unsigned long long trace[S_NUM];  // folded stripes (trace output)
 };
 
-// Written once, when column s becomes the pivot of row i (its low is i and
-// stays i): the pivot and, when short, the entries below its low, so a
-// chained addition needs one load instead of three dependent ones.
+// Everything a chained addition needs about row i, in one 32-byte record
+// (one load, one cache line): s >= 0 is the pivot of row i (written once,
+// when column s becomes the pivot: its low is i and stays i) with its length
+// k and, when short, the entries below its low; s = -1 with k = -1 marks a
+// row known to be negative (compression), s = -1 with k = 0 any other row.
 constexpr int kRecInline = 6;
 struct __align__(32) PivRec {
     int32_t s;                // the pivot column
@@ -216,6 +219,7 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
         d.len[j] = n;
         d.low[j] = n ? d.rows[s + n - 1] : -1;
         d.state[j] = n ? ST_ACTIVE : ST_ZERO;
+        *reinterpret_cast<int2 *>(&d.prec[j]) = make_int2(-1, 0);  // row j: no pivot, not known negative
         if (d.dim && d.dim[j] > top) top = d.dim[j];
     }
     if (d.dim) {
@@ -238,7 +242,10 @@ __global__ void k_beta(Dev d, int compression)
             if (d.left[r] == (int32_t)j) { b = r; break; }  // rows ascending: first hit from the end is the max
         }
         d.beta[j] = b;
-        if (compression && b >= 0) atomicOr(&d.neg[j >> 5], 1u << (j & 31));
+        if (compression && b >= 0) {
+            atomicOr(&d.neg[j >> 5], 1u << (j & 31));
+            d.prec[j].k = -1;  // a negative row never gets a pivot record
+        }
     }
 }
 
@@ -269,6 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, i
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q <= kPart) d.cq_n[q * 32] = 0;  // the chain queues of this round start empty
+    if (q == 0) d.cnt->max_chain = 0;
     I4 e = i4_fill(-1);
     if (q < nA) {
         const int32_t j = act[q];
@@ -379,7 +387,10 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, in
             d.prec[i] = r;
             d.state[j] = ST_PIVOT;
             d.low_star[j] = i;
-            if (compression) atomicOr(&d.neg[j >> 5], 1u << (j & 31));
+            if (compression) {
+                atomicOr(&d.neg[j >> 5], 1u << (j & 31));
+                d.prec[j].k = -1;
+            }
             if (d.state[i] == ST_ACTIVE) d.state[i] = ST_CLEARED;  // clearing: sigma_i is positive
             np = 1;
             nb = by_beta ? 1 : 0;
@@ -531,8 +542,7 @@ __device__ inline int32_t lower_bound_i32(const int32_t *a, int32_t n, int32_t x
     return lo;
 }
 
-// Everything a chain step needs about row i, fetched in one go (the three
-// loads are independent, so they share one memory latency).
+// Everything a chain step needs about row i: its record, one load.
 struct Look {
     int32_t s, k;
     int32_t e[kRecInline];
@@ -541,14 +551,13 @@ struct Look {
 
 __device__ inline Look look_up(const Dev &d, int32_t i)
 {
+    const PivRec rec = d.prec[i];
     Look r;
-    r.s = d.piv[i];
-    const PivRec rec = d.prec[i];  // meaningful only when piv[i] >= 0
-    const uint32_t nw = d.neg[i >> 5];
+    r.s = rec.s;
     r.k = rec.k;
 #pragma unroll
     for (int t = 0; t < kRecInline; t++) r.e[t] = rec.e[t];
-    r.neg = (nw >> (i & 31)) & 1u;
+    r.neg = rec.k < 0 ? 1 : 0;
     return r;
 }
 
@@ -636,7 +645,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                     }
                     adds++;
                     xe += (int64_t)L + kk + 1;
-                    by += 40;
+                    by += 32;
                     int32_t r = L - 2, w = L - 2 + kk, ncan = 0;
 #pragma unroll
                     for (int q = kRecInline - 1; q >= 0; q--) {
@@ -725,38 +734,56 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
 // chains, long columns, long pivots).  The working column is W = B xor P:
 // B, a sorted base array (in LDS while it fits, else in the arena), only
 // ever loses entries at its top; P, a set of at most 64 pending row
-// toggles, lives one entry per lane.  A step with a short pivot removes the
-// low and toggles the pivot's entries below it into P with one ballot per
-// entry, so its cost does not grow with the length of W.  The pivot records
-// of the 64 topmost B entries and of every P entry are loaded ahead by the
-// lanes that hold them: the record of the next low is a register read, or a
-// load issued one step earlier.  B and P are merged into a new B when P is
-// full, before a long pivot (whose column is merged as a whole) and at the
-// end.
-__device__ inline Look read_look(const Look &v, int32_t l)
+// toggles, lives one entry per lane (stored as row + 1, 0 = empty).  A step
+// with a short pivot removes the low and toggles the pivot's entries below
+// it into P, one ballot and one lane write per entry, so its cost does not
+// grow with the length of W; one wave-wide max finds the next low.  The
+// pivot records of the 64 topmost B entries and of every P entry are loaded
+// ahead by the lanes that hold them, so the next low's record is a register
+// read, at most one load latency away.  B and P are merged into a new B when
+// P is full, before a long pivot (whose column is merged as a whole) and at
+// the end.  A step issues few instructions on purpose: one wavefront runs
+// one chain, so its instruction issue rate bounds the chain's speed.
+struct Rec {
+    int4 a;  // s, k, e[0], e[1]
+    int4 b;  // e[2] .. e[5]
+};
+
+__device__ inline Rec rec_load(const Dev &d, int32_t i)
 {
-    Look r;
-    r.s = __builtin_amdgcn_readlane(v.s, l);
-    r.k = __builtin_amdgcn_readlane(v.k, l);
-#pragma unroll
-    for (int t = 0; t < kRecInline; t++) r.e[t] = __builtin_amdgcn_readlane(v.e[t], l);
-    r.neg = __builtin_amdgcn_readlane(v.neg, l);
+    const int4 *p = reinterpret_cast<const int4 *>(d.prec + i);
+    Rec r;
+    r.a = p[0];
+    r.b = p[1];
     return r;
 }
 
-__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression, int trace)
+// the record held by lane l, into wave-uniform registers
+__device__ inline void rec_read(const Rec &v, int32_t l, int32_t &s, int32_t &k, int32_t *e)
+{
+    s = __builtin_amdgcn_readlane(v.a.x, l);
+    k = __builtin_amdgcn_readlane(v.a.y, l);
+    e[0] = __builtin_amdgcn_readlane(v.a.z, l);
+    e[1] = __builtin_amdgcn_readlane(v.a.w, l);
+    e[2] = __builtin_amdgcn_readlane(v.b.x, l);
+    e[3] = __builtin_amdgcn_readlane(v.b.y, l);
+    e[4] = __builtin_amdgcn_readlane(v.b.z, l);
+    e[5] = __builtin_amdgcn_readlane(v.b.w, l);
+}
+
+template <bool kTrace>
+__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression)
 {
     __shared__ int32_t sW[kChainWaves][2][kCapW];
     __shared__ int32_t sS[kChainWaves][kCapS];
     __shared__ int32_t sE[kChainWaves][kCapS + 1];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int w = bcast_first(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);  // w: uniform by construction
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
-    const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // the lanes under this one
     const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
     int64_t adds = 0, xe = 0, by = 0;
     // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P
     unsigned long long tr[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (trace && gw == 0) tr[8] = (unsigned long long)total;
+    if (kTrace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
         const int32_t j = d.wq[t];
         const int32_t L0 = d.len[j];
@@ -769,109 +796,106 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             for (int32_t a = lane; a < L0; a += kWave) sW[w][0][a] = g[a];
         wave_sync();
         int32_t LB = L0;
-        uint64_t valid = 0;             // lanes holding an entry of P
-        int32_t pv = -1;                // this lane's entry of P
-        Look pr{};                      // and its record
-        int32_t wb = 0, wv = -1;        // window: this lane holds B[wb + lane]
-        Look wr{};                      // and its record
-        int32_t i = -1, pl = 0;         // the low, and its lane in P when from_p
+        uint64_t valid = 0;      // lanes holding an entry of P
+        int32_t pq = 0;          // this lane's entry of P, plus one (0: none)
+        Rec pr = {};             // and its record
+        int32_t wb = 0, wv = -1; // window: this lane holds B[wb + lane] (-1: none)
+        Rec wr = {};             // and its record
+        int32_t i = -1, pl = 0;  // the low, and its lane when it is in P
         bool from_p = false;
-        Look lk{};
+        int32_t ls = -1, lk = 0; // the low's record
+        int32_t le[kRecInline];
         bool dirty = false, failed = false;
+        const int64_t adds0 = adds;
 
         auto Bp = [&]() -> const int32_t * { return in_lds ? (const int32_t *)sW[w][cur] : Bg; };
         auto refill = [&]() {
             wb = LB > kWave ? LB - kWave : 0;
             const int32_t a = wb + lane;
             wv = a < LB ? Bp()[a] : -1;
-            if (wv >= 0) wr = look_up(d, wv);
+            wr = rec_load(d, wv >= 0 ? wv : 0);  // unconditional: the load writes wr in place
         };
-        // the low of W = max(B) xor-combined with max(P): equal tops cancel
+        // the low of W: the larger of max(B) and max(P); equal tops cancel
         auto next = [&]() {
-            const int64_t c0 = trace ? clock64() : 0;
+            const int64_t c0 = kTrace ? clock64() : 0;
             for (;;) {
                 if (LB > 0 && LB - 1 < wb) refill();
-                const bool pvld = (valid >> lane) & 1ull;
-                const int32_t pmax = valid ? wave_max_dpp(pvld ? pv + 1 : 0) - 1 : -1;
+                const int32_t pm1 = valid ? wave_max_dpp(pq) : 0;
                 const int32_t bt = LB > 0 ? __builtin_amdgcn_readlane(wv, LB - 1 - wb) : -1;
-                if (pmax < 0 && bt < 0) {
+                if (pm1 > bt + 1) {
+                    const int32_t l = (int32_t)__builtin_ctzll(__ballot(pq == pm1));
+                    i = pm1 - 1;
+                    pl = l;
+                    from_p = true;
+                    rec_read(pr, l, ls, lk, le);
+                    if (kTrace) tr[9]++;
+                    break;
+                }
+                if (bt < 0) {
                     i = -1;
                     break;
                 }
-                if (pmax >= bt) {
-                    const uint64_t hit = __ballot(pvld && pv == pmax);
-                    const int32_t l = (int32_t)__builtin_ctzll(hit);
-                    if (pmax == bt) {  // 1 + 1 = 0
-                        valid &= ~(1ull << l);
-                        LB--;
-                        continue;
-                    }
-                    i = pmax;
-                    pl = l;
-                    from_p = true;
-                    lk = read_look(pr, l);
-                    if (trace) tr[9]++;
-                    break;
+                if (pm1 == bt + 1) {  // 1 + 1 = 0
+                    const int32_t l = (int32_t)__builtin_ctzll(__ballot(pq == pm1));
+                    valid &= ~(1ull << l);
+                    pq = (lane == l ? 0 : pq);
+                    LB--;
+                    continue;
                 }
                 i = bt;
                 from_p = false;
-                lk = read_look(wr, LB - 1 - wb);
+                rec_read(wr, LB - 1 - wb, ls, lk, le);
                 break;
             }
-            if (trace) tr[5] += clock64() - c0;
+            if (kTrace) tr[5] += clock64() - c0;
         };
         auto pop = [&]() {
-            if (from_p) valid &= ~(1ull << pl);
-            else LB--;
+            if (from_p) {
+                valid &= ~(1ull << pl);
+                pq = (lane == pl ? 0 : pq);
+            } else {
+                LB--;
+            }
         };
-        // toggle the entries s.e[0, kk) into P (needs kk free lanes)
-        auto toggle = [&](int32_t kk, const Look &s) {
-            const int64_t c0 = trace ? clock64() : 0;
-            const bool pvld = (valid >> lane) & 1ull;
-            bool hit = false;
-            uint32_t present = 0;
+        // toggle le[0, kk) into P (needs kk free lanes); reload the records
+        auto toggle = [&](int32_t kk) {
+            const int64_t c0 = kTrace ? clock64() : 0;
 #pragma unroll
             for (int q = 0; q < kRecInline; q++) {
                 if (q < kk) {
-                    const bool h = pvld && pv == s.e[q];
-                    hit = hit || h;
-                    if (__ballot(h)) present |= 1u << q;
-                }
-            }
-            valid &= ~__ballot(hit);
-            const uint64_t freem = ~valid;
-            const int32_t nins = kk - __popc(present);
-            const int32_t frk = __popcll(freem & below);
-            const bool mine = ((freem >> lane) & 1ull) && frk < nins;
-            if (mine) {
-                int32_t x = -1, c = 0;
-#pragma unroll
-                for (int q = 0; q < kRecInline; q++) {
-                    if (q < kk && !((present >> q) & 1u)) {
-                        if (c == frk) x = s.e[q];
-                        c++;
+                    const int32_t x1 = le[q] + 1;
+                    const uint64_t m = __ballot(pq == x1);
+                    if (m) {
+                        const int32_t l = (int32_t)__builtin_ctzll(m);
+                        valid &= ~(1ull << l);
+                        pq = (lane == l ? 0 : pq);
+                    } else {
+                        const int32_t f = (int32_t)__builtin_ctzll(~valid);
+                        valid |= 1ull << f;
+                        pq = (lane == f ? x1 : pq);
                     }
                 }
-                pv = x;
-                pr = look_up(d, x);
             }
-            valid |= __ballot(mine);
-            if (trace) tr[4] += clock64() - c0;
+            // every lane reloads the record of its entry: a load under a
+            // branch would be copied where the branch joins, which waits
+            // for it; unconditional, it is only waited for when read
+            pr = rec_load(d, pq > 0 ? pq - 1 : 0);
+            if (kTrace) tr[4] += clock64() - c0;
         };
         // B := B xor P (P emptied), into the free LDS buffer or the arena
         auto flush = [&]() -> bool {
-            const int64_t c0 = trace ? clock64() : 0;
+            const int64_t c0 = kTrace ? clock64() : 0;
             const int32_t np = __popcll(valid);
             const int32_t cap = LB + np;
             const int nb = in_lds ? cur ^ 1 : 0;
             int32_t *dst;
-            bool dst_lds = cap <= kCapW;
+            const bool dst_lds = cap <= kCapW;
             if (dst_lds) {
                 dst = sW[w][nb];
             } else {
                 long long o = 0;
                 if (lane == 0) o = arena_alloc(d, gw, cap);
-                o = __shfl(o, 0, kWave);
+                o = bcast_first64(o);
                 if (o < 0) {
                     if (lane == 0) atomicExch(&d.cnt->overflow, 1);
                     return false;  // keep the stored column; redo next round
@@ -880,8 +904,8 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             }
             const int32_t *B = Bp();
             int32_t *sc = sE[w];  // [0,64) P by lane, [64,128) P sorted, [128,192) cancel flags, [192,256) their prefix
-            const bool pvld = (valid >> lane) & 1ull;
-            const int32_t my = pvld ? pv : 0x7FFFFFFF;
+            const bool pvld = pq > 0;
+            const int32_t my = pvld ? pq - 1 : 0x7FFFFFFF;
             wave_sync();
             sc[lane] = my;
             wave_sync();
@@ -921,6 +945,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             if (!dst_lds) __threadfence();
             wave_sync();
             valid = 0;
+            pq = 0;
             LB = nL;
             if (dst_lds) {
                 in_lds = true;
@@ -930,7 +955,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                 Bg = dst;
             }
             refill();
-            if (trace) {
+            if (kTrace) {
                 tr[6] += clock64() - c0;
                 tr[7]++;
             }
@@ -941,16 +966,16 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         next();
         while (i >= 0) {
             const int32_t pi = i;
-            if (lk.s < 0) {
+            if (ls < 0) {
                 // no pivot owns this low: a known-negative row is deleted
                 // (compression), anything else ends the chain
-                if (!(compression && lk.neg)) break;
+                if (!(compression && lk < 0)) break;
                 pop();
                 dirty = true;
             } else {
-                const int32_t k = lk.k, kk = k - 1;
+                const int32_t kk = lk - 1;
                 adds++;
-                xe += (int64_t)LB + __popcll(valid) + k;
+                xe += (int64_t)LB + lk;
                 if (kk <= kRecInline) {
                     if (__popcll(valid) + kk > kWave) {
                         if (!flush()) {
@@ -959,13 +984,13 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                         }
                         from_p = false;  // W is unchanged: its low is now the top of B
                     }
-                    by += 40;  // piv, record, neg word of the low
-                    if (trace) {
+                    by += 32;  // the record of the low
+                    if (kTrace) {
                         tr[0]++;
                         tr[3] += LB + __popcll(valid);
                     }
                     pop();
-                    toggle(kk, lk);
+                    toggle(kk);
                     dirty = true;
                 } else {
                     // long pivot: merge its whole column into W = B
@@ -973,15 +998,15 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                         failed = true;
                         break;
                     }
-                    const int32_t L = LB;
+                    const int32_t k = lk, L = LB;
                     const int32_t *W = Bp();
-                    by += 40 + 12 + 4 * (int64_t)k;
-                    if (trace) {
+                    by += 32 + 12 + 4 * (int64_t)k;
+                    if (kTrace) {
                         tr[3] += L;
                         if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
                         else tr[2]++;
                     }
-                    const int32_t *Sg = col_base(d, d.off[lk.s]);
+                    const int32_t *Sg = col_base(d, d.off[ls]);
                     if (in_lds && L + k <= kCapW && k <= kCapS) {
                         for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
                         wave_sync();
@@ -998,7 +1023,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                             }
                             const int32_t inc = wave_incl_sum32(e);
                             if (b < k) sE[w][b] = carry + inc - e;
-                            carry += __shfl(inc, kWave - 1, kWave);
+                            carry += bcast_lane(inc, kWave - 1);
                         }
                         if (lane == 0) sE[w][k] = carry;
                         wave_sync();
@@ -1023,7 +1048,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                         long long o = 0;
                         const int64_t need = (int64_t)L + k;
                         if (lane == 0) o = arena_alloc(d, gw, need);
-                        o = __shfl(o, 0, kWave);
+                        o = bcast_first64(o);
                         if (o < 0) {
                             if (lane == 0) atomicExch(&d.cnt->overflow, 1);
                             failed = true;  // keep the stored column; redo next round
@@ -1032,7 +1057,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                         int32_t *out = d.arena + o;
                         int32_t nL = 0;
                         if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
-                        nL = __shfl(nL, 0, kWave);
+                        nL = bcast_first(nL);
                         __threadfence();  // lane 0's global writes, then every lane reads them
                         wave_sync();
                         Bg = out;
@@ -1051,6 +1076,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             }
         }
         if (!failed && valid && !flush()) failed = true;
+        if (kTrace && lane == 0) atomicMax(&d.cnt->max_chain, (int32_t)(adds - adds0));
         if (failed || !dirty) continue;
         // write the result back
         if (LB == 0) {
@@ -1065,7 +1091,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         if (in_lds) {
             long long o = 0;
             if (lane == 0) o = arena_alloc(d, gw, LB);
-            o = __shfl(o, 0, kWave);
+            o = bcast_first64(o);
             if (o < 0) {
                 if (lane == 0) atomicExch(&d.cnt->overflow, 1);
                 continue;  // progress of this chain is dropped; the stored column is still valid
@@ -1096,7 +1122,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         stat_add(d, S_ADDS, (unsigned long long)adds, gw);
         stat_add(d, S_XE, (unsigned long long)xe, gw);
         stat_add(d, S_CBYTES, (unsigned long long)by, gw);
-        if (trace) {
+        if (kTrace) {
             for (int q = 0; q < 9; q++) stat_add(d, S_T_SHORT + q, tr[q], gw);
             stat_add(d, S_T_FROMP, tr[9], gw);
         }
@@ -1419,7 +1445,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_fill_i32, grid_for(nwords, kBlock, 65536), kBlock, (int32_t *)d.neg, nwords, 0);
     PMS_LAUNCH(c, K_FILL, 8 * dm, k_fill_u64, gm, kBlock, d.T, m, ~0ull);
     // col_ptr, rows, left updates, dims (facets and columns), headers out
-    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 17 * dm, k_init, gm, kBlock, d, nnz,
+    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm, k_init, gm, kBlock, d, nnz,
                opt->validate);
     // col_ptr, len, rows, left, beta out, neg bits
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
@@ -1462,7 +1488,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         const size_t xor_slot = c->pend.size() - 1;
         PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
         const size_t lane_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain, kChainBlocks, kChainWaves * kWave, d, opt->compression, trace);
+        if (trace)
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+        else
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
         const size_t chain_slot = c->pend.size() - 1;
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
@@ -1489,11 +1518,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             fprintf(stderr,
                     "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
-                    "%llu, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
+                    "%llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
-                    dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
+                    dl[S_T_FROMP], dl[S_T_FLUSHES], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
         }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
