@@ -139,11 +139,17 @@ __global__ void k_vr_bounds(VrInst *inst, int32_t B, const int64_t *escan, const
 
 template <bool F32>
 __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, const unsigned long long *adj,
-                          const int64_t *escan, const int64_t *tscan, unsigned long long *keys, int maxdim)
+                          const int64_t *escan, const int64_t *tscan, unsigned long long *keys, uint16_t *cl,
+                          int maxdim)
 {
+    // cl (batches): the cloud of every key, for the sort by (cloud, key)
     const VrInst I = inst[blockIdx.y];
+    const uint16_t cb = (uint16_t)blockIdx.y;
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (sl < I.n) keys[I.col_base + sl] = vr_key<F32>(0, 0, (unsigned long long)sl);  // vertex sl
+    if (sl < I.n) {
+        keys[I.col_base + sl] = vr_key<F32>(0, 0, (unsigned long long)sl);  // vertex sl
+        if (cl) cl[I.col_base + sl] = cb;
+    }
     if (sl >= (int64_t)I.n * I.n) return;
     const int32_t a = (int32_t)(sl / I.n), b = (int32_t)(sl % I.n);
     if (a >= b) return;
@@ -152,8 +158,9 @@ __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, con
     if (maxdim < 1 || !((ra[b >> 6] >> (b & 63)) & 1ull)) return;
     const unsigned long long n = (unsigned long long)I.n;
     const unsigned long long vab = val[I.slot_base + sl];
-    keys[I.col_base + I.n + (escan[I.slot_base + sl] - I.e_first)] =
-        vr_key<F32>(vab, 1, (unsigned long long)a * n + (unsigned long long)b);
+    const int64_t pe = I.col_base + I.n + (escan[I.slot_base + sl] - I.e_first);
+    keys[pe] = vr_key<F32>(vab, 1, (unsigned long long)a * n + (unsigned long long)b);
+    if (cl) cl[pe] = cb;
     if (maxdim < 2) return;
     int64_t pos = I.col_base + I.n + I.E + (tscan[I.slot_base + sl] - I.t_first);
     for (int w = (b + 1) >> 6; w < I.words; w++) {
@@ -168,6 +175,7 @@ __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, con
             // FP32 values are >= 0, so their bit patterns order like the values
             v = v > vac ? v : vac;
             v = v > vbc ? v : vbc;
+            if (cl) cl[pos] = cb;
             keys[pos++] = vr_key<F32>(v, 2, ((unsigned long long)a * n + (unsigned long long)b) * n + (unsigned long long)c);
         }
     }
@@ -389,9 +397,22 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         return PMS_OK;
     }
     const dim3 g3((unsigned)((maxnn + kBlock - 1) / kBlock > 0 ? (maxnn + kBlock - 1) / kBlock : 1), (unsigned)B);
-    if (f32) PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<true>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, maxdim);
-    else PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<false>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, maxdim);
+    // batches: one stable sort of all keys (carrying their cloud) by key,
+    // then a stable sort by cloud, so each cloud's columns come out in key
+    // order; the whole device sorts, not one workgroup per cloud
+    const bool by_cloud = B > 1 && B <= 65536;
+    uint16_t *cl = nullptr, *cl2 = nullptr;
+    if (by_cloud) {
+        cl = (uint16_t *)scratch(c, B_BUILD12, M * 2);
+        cl2 = (uint16_t *)scratch(c, B_BUILD13, M * 2);
+        if (!cl || !cl2) return set_err(c, PMS_ERR_OOM, "builder scratch");
+    }
+    if (f32)
+        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<true>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim);
+    else
+        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<false>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim);
     PMS_LAUNCH(c, K_FILL, 0, k_vr_colbase, (unsigned)((B + 255) / 256), 256, dinst, B, colb, seg, seg + B);
+    const unsigned long long *sorted = keys2;
     {
         hipEvent_t e0 = nullptr;
         if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
@@ -401,6 +422,17 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
             void *tmps = scratch(c, B_AGG, tb);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
             PMS_HIP(rocprim::radix_sort_keys(tmps, tb, keys, keys2, (size_t)m, 0, 64, s));
+        } else if (by_cloud) {
+            int cbits = 1;
+            while ((1 << cbits) < B) cbits++;
+            size_t tb2 = 0;
+            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, cl, cl2, (size_t)m, 0, 64, s));
+            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
+            void *tmps = scratch(c, B_AGG, tb > tb2 ? tb : tb2);
+            if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
+            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, cl, cl2, (size_t)m, 0, 64, s));
+            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
+            sorted = keys;
         } else {
             PMS_HIP(rocprim::segmented_radix_sort_keys(nullptr, tb, keys, keys2, (unsigned)m, (unsigned)B, seg,
                                                        seg + B, 0, 64, s));
@@ -412,21 +444,21 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         if (c->prof_on) {
             hipEvent_t e1 = prof_event(c);
             (void)hipEventRecord(e1, s);
-            c->pend.push_back({K_SORT, e0, e1, 16.0 * m});
+            c->pend.push_back({K_SORT, e0, e1, by_cloud ? 40.0 * m : 16.0 * m});
         }
     }
     if (f32)
-        PMS_LAUNCH(c, K_VR_INDEX, 41.0 * m, k_vr_index<true>, (unsigned)tiles, kBlock, dinst, colb, B, keys2, m, vidx,
+        PMS_LAUNCH(c, K_VR_INDEX, 41.0 * m, k_vr_index<true>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, vidx,
                    eidx, f->dim, f->value, f->verts, tsum);
     else
-        PMS_LAUNCH(c, K_VR_INDEX, 45.0 * m, k_vr_index<false>, (unsigned)tiles, kBlock, dinst, colb, B, keys2, m, vidx,
+        PMS_LAUNCH(c, K_VR_INDEX, 45.0 * m, k_vr_index<false>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, vidx,
                    eidx, f->dim, f->value, f->verts, tsum);
     PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * tiles, k_scan_i64, 1, 1024, tsum, tiles);
     if (f32)
-        PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<true>, (unsigned)tiles, kBlock, dinst, colb, B, keys2,
+        PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<true>, (unsigned)tiles, kBlock, dinst, colb, B, sorted,
                    m, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
     else
-        PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<false>, (unsigned)tiles, kBlock, dinst, colb, B, keys2,
+        PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<false>, (unsigned)tiles, kBlock, dinst, colb, B, sorted,
                    m, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
     PMS_HIP(hipGetLastError());
     PMS_HIP(hipStreamSynchronize(s));

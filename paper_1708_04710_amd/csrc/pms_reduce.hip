@@ -58,7 +58,7 @@ enum StatId {
     // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
-    S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP,
+    S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL,
     S_NUM
 };
 
@@ -211,7 +211,7 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
             if (r <= prev || (int64_t)r >= j) { bad = true; break; }
             if (validate && d.dim && d.dim[r] != d.dim[j] - 1) { bad = true; break; }
             prev = r;
-            atomicMin(&d.left[r], (int32_t)j);
+            if ((int32_t)j < d.left[r]) atomicMin(&d.left[r], (int32_t)j);  // left only decreases
         }
         if (validate && d.dim && d.dim[j] < 0) bad = true;
         if (bad) { atomicExch(&d.cnt->error, 1); n = 0; }
@@ -267,7 +267,10 @@ __global__ void k_low(Dev d, const int32_t *act, int32_t nA, uint32_t round)
         }
         const int32_t i = c[n - 1];
         d.low[j] = i;
-        atomicMin(&d.T[i], t_key(round, j));
+        // T only ever decreases: a plain read that already shows a smaller
+        // key saves the atomic (many columns share a low)
+        const unsigned long long key = t_key(round, j);
+        if (key < d.T[i]) atomicMin(&d.T[i], key);
     }
 }
 
@@ -521,7 +524,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
 // ---------------------------------------------------------------- chaining
 constexpr int kChainWaves = 4;
 constexpr unsigned kChainBlocks = 512;  // 2 per CU; waves take queue entries dynamically
-constexpr int kCapW = 1536;  // LDS entries per working buffer (two per wave)
+constexpr int kCapW = 1520;  // LDS entries per working buffer (two per wave); two blocks fit a CU
 constexpr int kCapS = 512;   // LDS entries for the pivot column
 
 __device__ inline void wave_sync()
@@ -736,39 +739,29 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
 // ever loses entries at its top; P, a set of at most 64 pending row
 // toggles, lives one entry per lane (stored as row + 1, 0 = empty).  A step
 // with a short pivot removes the low and toggles the pivot's entries below
-// it into P, one ballot and one lane write per entry, so its cost does not
+// it into P, one ballot and one lane select per entry, so its cost does not
 // grow with the length of W; one wave-wide max finds the next low.  The
-// pivot records of the 64 topmost B entries and of every P entry are loaded
-// ahead by the lanes that hold them, so the next low's record is a register
-// read, at most one load latency away.  B and P are merged into a new B when
-// P is full, before a long pivot (whose column is merged as a whole) and at
-// the end.  A step issues few instructions on purpose: one wavefront runs
-// one chain, so its instruction issue rate bounds the chain's speed.
-struct Rec {
-    int4 a;  // s, k, e[0], e[1]
-    int4 b;  // e[2] .. e[5]
-};
+// pivot records of every P entry and of the 64 topmost B entries are copied
+// ahead, memory to LDS without passing through registers, into one LDS slot
+// per lane: the next low's record is an LDS read, at most one load latency
+// after the step that inserted it.  Known-negative lows are deleted while
+// the next low is searched.  B and P are merged into a new B when P is full,
+// before a long pivot (whose column is merged as a whole) and at the end.
+// A step issues few instructions on purpose: one wavefront runs one chain,
+// so its instruction issue rate bounds the chain's speed.
+typedef __attribute__((address_space(3))) void lds_void_t;
 
-__device__ inline Rec rec_load(const Dev &d, int32_t i)
+// copy this lane's record of row i to LDS slot (lane) of ra / rb (16 bytes each)
+__device__ inline void rec_to_lds(const Dev &d, int32_t i, int4 *ra, int4 *rb)
 {
-    const int4 *p = reinterpret_cast<const int4 *>(d.prec + i);
-    Rec r;
-    r.a = p[0];
-    r.b = p[1];
-    return r;
+    const int4 *src = reinterpret_cast<const int4 *>(d.prec + i);
+    __builtin_amdgcn_global_load_lds(src, (lds_void_t *)ra, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(src + 1, (lds_void_t *)rb, 16, 0, 0);
 }
 
-// the record held by lane l, into wave-uniform registers
-__device__ inline void rec_read(const Rec &v, int32_t l, int32_t &s, int32_t &k, int32_t *e)
+__device__ inline void wait_vmem()
 {
-    s = __builtin_amdgcn_readlane(v.a.x, l);
-    k = __builtin_amdgcn_readlane(v.a.y, l);
-    e[0] = __builtin_amdgcn_readlane(v.a.z, l);
-    e[1] = __builtin_amdgcn_readlane(v.a.w, l);
-    e[2] = __builtin_amdgcn_readlane(v.b.x, l);
-    e[3] = __builtin_amdgcn_readlane(v.b.y, l);
-    e[4] = __builtin_amdgcn_readlane(v.b.z, l);
-    e[5] = __builtin_amdgcn_readlane(v.b.w, l);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies to LDS have landed
 }
 
 template <bool kTrace>
@@ -777,12 +770,15 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     __shared__ int32_t sW[kChainWaves][2][kCapW];
     __shared__ int32_t sS[kChainWaves][kCapS];
     __shared__ int32_t sE[kChainWaves][kCapS + 1];
+    __shared__ int4 sRP[kChainWaves][2][kWave];  // records of the P entries (two halves), slot = lane
+    __shared__ int4 sRW[kChainWaves][2][kWave];  // records of the window entries
     const int w = bcast_first(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);  // w: uniform by construction
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
+    int4 *RPa = sRP[w][0], *RPb = sRP[w][1], *RWa = sRW[w][0], *RWb = sRW[w][1];
     const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
     int64_t adds = 0, xe = 0, by = 0;
-    // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P
-    unsigned long long tr[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P, deletions
+    unsigned long long tr[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (kTrace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
         const int32_t j = d.wq[t];
@@ -796,38 +792,57 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             for (int32_t a = lane; a < L0; a += kWave) sW[w][0][a] = g[a];
         wave_sync();
         int32_t LB = L0;
-        uint64_t valid = 0;      // lanes holding an entry of P
-        int32_t pq = 0;          // this lane's entry of P, plus one (0: none)
-        Rec pr = {};             // and its record
-        int32_t wb = 0, wv = -1; // window: this lane holds B[wb + lane] (-1: none)
-        Rec wr = {};             // and its record
-        int32_t i = -1, pl = 0;  // the low, and its lane when it is in P
+        uint64_t valid = 0;       // lanes holding an entry of P
+        int32_t pq = 0;           // this lane's entry of P, plus one (0: none)
+        int32_t pm1 = 0;          // max(P) + 1 (0: P empty), when !pdirty
+        bool pdirty = false;
+        int32_t wb = 0, wv = -1;  // window: this lane holds B[wb + lane] (-1: none)
+        int32_t i = -1, pl = 0;   // the low, and its lane when it is in P
         bool from_p = false;
-        int32_t ls = -1, lk = 0; // the low's record
-        int32_t le[kRecInline];
+        int32_t ls = -1, lk = 0;  // the low's record: pivot, length
+        int4 lea, leb;            // and entries (e[0], e[1] in lea.z, lea.w; e[2..5] in leb)
         bool dirty = false, failed = false;
-        const int64_t adds0 = adds;
+        int32_t cadds = 0, cxe = 0, cby = 0;  // this column's counters (32-bit: cheap in the loop)
 
         auto Bp = [&]() -> const int32_t * { return in_lds ? (const int32_t *)sW[w][cur] : Bg; };
         auto refill = [&]() {
             wb = LB > kWave ? LB - kWave : 0;
             const int32_t a = wb + lane;
             wv = a < LB ? Bp()[a] : -1;
-            wr = rec_load(d, wv >= 0 ? wv : 0);  // unconditional: the load writes wr in place
+            if (wv >= 0) rec_to_lds(d, wv, RWa, RWb);
+            wait_vmem();  // window records are read without a wait
         };
-        // the low of W: the larger of max(B) and max(P); equal tops cancel
+        auto read_rec = [&](const int4 *ra, const int4 *rb, int32_t l, bool wait) {
+            if (wait) wait_vmem();  // the copies of the P records issued since
+            lea = ra[l];
+            leb = rb[l];
+            ls = bcast_first(lea.x);
+            lk = bcast_first(lea.y);
+        };
+        // the low of W: the larger of max(B) and max(P), equal tops cancel;
+        // known-negative lows are deleted on the way
         auto next = [&]() {
             const int64_t c0 = kTrace ? clock64() : 0;
             for (;;) {
                 if (LB > 0 && LB - 1 < wb) refill();
-                const int32_t pm1 = valid ? wave_max_dpp(pq) : 0;
+                if (pdirty) {
+                    pm1 = valid ? wave_max_dpp(pq) : 0;
+                    pdirty = false;
+                }
                 const int32_t bt = LB > 0 ? __builtin_amdgcn_readlane(wv, LB - 1 - wb) : -1;
                 if (pm1 > bt + 1) {
                     const int32_t l = (int32_t)__builtin_ctzll(__ballot(pq == pm1));
                     i = pm1 - 1;
                     pl = l;
                     from_p = true;
-                    rec_read(pr, l, ls, lk, le);
+                    read_rec(RPa, RPb, l, true);
+                    if (compression && ls < 0 && lk < 0) {  // a negative row: delete it
+                        valid &= ~(1ull << l);
+                        pq = lane == l ? 0 : pq;
+                        pdirty = true;
+                        if (kTrace) tr[10]++;
+                        continue;
+                    }
                     if (kTrace) tr[9]++;
                     break;
                 }
@@ -838,48 +853,57 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                 if (pm1 == bt + 1) {  // 1 + 1 = 0
                     const int32_t l = (int32_t)__builtin_ctzll(__ballot(pq == pm1));
                     valid &= ~(1ull << l);
-                    pq = (lane == l ? 0 : pq);
+                    pq = lane == l ? 0 : pq;
+                    pdirty = true;
                     LB--;
                     continue;
                 }
                 i = bt;
                 from_p = false;
-                rec_read(wr, LB - 1 - wb, ls, lk, le);
+                read_rec(RWa, RWb, LB - 1 - wb, false);
+                if (compression && ls < 0 && lk < 0) {  // max(P) is unchanged
+                    LB--;
+                    if (kTrace) tr[10]++;
+                    continue;
+                }
                 break;
             }
             if (kTrace) tr[5] += clock64() - c0;
         };
-        auto pop = [&]() {
+        // remove the low, toggle its pivot's entries e[0, kk) into P (needs
+        // kk free lanes) and start the copies of the new entries' records
+        auto step = [&](int32_t kk) {
+            const int64_t c0 = kTrace ? clock64() : 0;
             if (from_p) {
                 valid &= ~(1ull << pl);
-                pq = (lane == pl ? 0 : pq);
+                pq = lane == pl ? 0 : pq;
+                pdirty = true;  // the low was max(P)
             } else {
                 LB--;
             }
-        };
-        // toggle le[0, kk) into P (needs kk free lanes); reload the records
-        auto toggle = [&](int32_t kk) {
-            const int64_t c0 = kTrace ? clock64() : 0;
+            const int32_t ev[kRecInline] = {lea.z, lea.w, leb.x, leb.y, leb.z, leb.w};
+            uint64_t fresh = 0;
 #pragma unroll
             for (int q = 0; q < kRecInline; q++) {
                 if (q < kk) {
-                    const int32_t x1 = le[q] + 1;
+                    const int32_t x1 = ev[q] + 1;
                     const uint64_t m = __ballot(pq == x1);
                     if (m) {
                         const int32_t l = (int32_t)__builtin_ctzll(m);
                         valid &= ~(1ull << l);
-                        pq = (lane == l ? 0 : pq);
+                        fresh &= ~(1ull << l);
+                        if (x1 == pm1) pdirty = true;
+                        pq = lane == l ? 0 : pq;
                     } else {
                         const int32_t f = (int32_t)__builtin_ctzll(~valid);
                         valid |= 1ull << f;
-                        pq = (lane == f ? x1 : pq);
+                        fresh |= 1ull << f;
+                        pm1 = max(pm1, x1);
+                        pq = lane == f ? x1 : pq;
                     }
                 }
             }
-            // every lane reloads the record of its entry: a load under a
-            // branch would be copied where the branch joins, which waits
-            // for it; unconditional, it is only waited for when read
-            pr = rec_load(d, pq > 0 ? pq - 1 : 0);
+            if ((fresh >> lane) & 1ull) rec_to_lds(d, pq - 1, RPa, RPb);
             if (kTrace) tr[4] += clock64() - c0;
         };
         // B := B xor P (P emptied), into the free LDS buffer or the arena
@@ -946,6 +970,8 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             wave_sync();
             valid = 0;
             pq = 0;
+            pm1 = 0;
+            pdirty = false;
             LB = nL;
             if (dst_lds) {
                 in_lds = true;
@@ -964,109 +990,100 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
 
         refill();
         next();
-        while (i >= 0) {
+        while (i >= 0 && ls >= 0) {  // a low without a pivot ends the chain
             const int32_t pi = i;
-            if (ls < 0) {
-                // no pivot owns this low: a known-negative row is deleted
-                // (compression), anything else ends the chain
-                if (!(compression && lk < 0)) break;
-                pop();
-                dirty = true;
-            } else {
-                const int32_t kk = lk - 1;
-                adds++;
-                xe += (int64_t)LB + lk;
-                if (kk <= kRecInline) {
-                    if (__popcll(valid) + kk > kWave) {
-                        if (!flush()) {
-                            failed = true;
-                            break;
-                        }
-                        from_p = false;  // W is unchanged: its low is now the top of B
-                    }
-                    by += 32;  // the record of the low
-                    if (kTrace) {
-                        tr[0]++;
-                        tr[3] += LB + __popcll(valid);
-                    }
-                    pop();
-                    toggle(kk);
-                    dirty = true;
-                } else {
-                    // long pivot: merge its whole column into W = B
-                    if (valid && !flush()) {
+            const int32_t kk = lk - 1;
+            cadds++;
+            cxe += LB + lk;
+            if (kk <= kRecInline) {
+                if (__popcll(valid) + kk > kWave) {
+                    if (!flush()) {
                         failed = true;
                         break;
                     }
-                    const int32_t k = lk, L = LB;
-                    const int32_t *W = Bp();
-                    by += 32 + 12 + 4 * (int64_t)k;
-                    if (kTrace) {
-                        tr[3] += L;
-                        if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
-                        else tr[2]++;
-                    }
-                    const int32_t *Sg = col_base(d, d.off[ls]);
-                    if (in_lds && L + k <= kCapW && k <= kCapS) {
-                        for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
-                        wave_sync();
-                        const int32_t *S = sS[w];
-                        int32_t *Wn = sW[w][cur ^ 1];
-                        // cancelled pairs: exclusive prefix count over S
-                        int32_t carry = 0;
-                        for (int32_t base = 0; base < k; base += kWave) {
-                            const int32_t b = base + lane;
-                            int32_t e = 0;
-                            if (b < k) {
-                                const int32_t qq = lower_bound_i32(W, L, S[b]);
-                                e = (qq < L && W[qq] == S[b]) ? 1 : 0;
-                            }
-                            const int32_t inc = wave_incl_sum32(e);
-                            if (b < k) sE[w][b] = carry + inc - e;
-                            carry += bcast_lane(inc, kWave - 1);
-                        }
-                        if (lane == 0) sE[w][k] = carry;
-                        wave_sync();
-                        // an entry's output position: its own index plus its
-                        // rank in the other list minus twice the number of
-                        // cancelled pairs below it
-                        for (int32_t a = lane; a < L; a += kWave) {
-                            const int32_t x = W[a];
-                            const int32_t r = lower_bound_i32(S, k, x);
-                            if (!(r < k && S[r] == x)) Wn[a + r - 2 * sE[w][r]] = x;
-                        }
-                        for (int32_t b = lane; b < k; b += kWave) {
-                            const int32_t x = S[b];
-                            const int32_t qq = lower_bound_i32(W, L, x);
-                            if (!(qq < L && W[qq] == x)) Wn[b + qq - 2 * sE[w][b]] = x;
-                        }
-                        LB = L + k - 2 * carry;
-                        wave_sync();
-                        cur ^= 1;
-                    } else {
-                        // too long for LDS: lane 0 merges in global memory
-                        long long o = 0;
-                        const int64_t need = (int64_t)L + k;
-                        if (lane == 0) o = arena_alloc(d, gw, need);
-                        o = bcast_first64(o);
-                        if (o < 0) {
-                            if (lane == 0) atomicExch(&d.cnt->overflow, 1);
-                            failed = true;  // keep the stored column; redo next round
-                            break;
-                        }
-                        int32_t *out = d.arena + o;
-                        int32_t nL = 0;
-                        if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
-                        nL = bcast_first(nL);
-                        __threadfence();  // lane 0's global writes, then every lane reads them
-                        wave_sync();
-                        Bg = out;
-                        in_lds = false;
-                        LB = nL;
-                    }
-                    dirty = true;
-                    refill();
+                    from_p = false;  // W is unchanged: its low is now the top of B
                 }
+                cby += 32;  // the record of the low
+                if (kTrace) {
+                    tr[0]++;
+                    tr[3] += LB + __popcll(valid);
+                }
+                step(kk);
+                dirty = true;
+            } else {
+                // long pivot: merge its whole column into W = B
+                if (valid && !flush()) {
+                    failed = true;
+                    break;
+                }
+                const int32_t k = lk, L = LB;
+                const int32_t *W = Bp();
+                cby += 32 + 12 + 4 * k;
+                if (kTrace) {
+                    tr[3] += L;
+                    if (in_lds && L + k <= kCapW && k <= kCapS) tr[1]++;
+                    else tr[2]++;
+                }
+                const int32_t *Sg = col_base(d, d.off[ls]);
+                if (in_lds && L + k <= kCapW && k <= kCapS) {
+                    for (int32_t b = lane; b < k; b += kWave) sS[w][b] = Sg[b];
+                    wave_sync();
+                    const int32_t *S = sS[w];
+                    int32_t *Wn = sW[w][cur ^ 1];
+                    // cancelled pairs: exclusive prefix count over S
+                    int32_t carry = 0;
+                    for (int32_t base = 0; base < k; base += kWave) {
+                        const int32_t b = base + lane;
+                        int32_t e = 0;
+                        if (b < k) {
+                            const int32_t qq = lower_bound_i32(W, L, S[b]);
+                            e = (qq < L && W[qq] == S[b]) ? 1 : 0;
+                        }
+                        const int32_t inc = wave_incl_sum32(e);
+                        if (b < k) sE[w][b] = carry + inc - e;
+                        carry += bcast_lane(inc, kWave - 1);
+                    }
+                    if (lane == 0) sE[w][k] = carry;
+                    wave_sync();
+                    // an entry's output position: its own index plus its
+                    // rank in the other list minus twice the number of
+                    // cancelled pairs below it
+                    for (int32_t a = lane; a < L; a += kWave) {
+                        const int32_t x = W[a];
+                        const int32_t r = lower_bound_i32(S, k, x);
+                        if (!(r < k && S[r] == x)) Wn[a + r - 2 * sE[w][r]] = x;
+                    }
+                    for (int32_t b = lane; b < k; b += kWave) {
+                        const int32_t x = S[b];
+                        const int32_t qq = lower_bound_i32(W, L, x);
+                        if (!(qq < L && W[qq] == x)) Wn[b + qq - 2 * sE[w][b]] = x;
+                    }
+                    LB = L + k - 2 * carry;
+                    wave_sync();
+                    cur ^= 1;
+                } else {
+                    // too long for LDS: lane 0 merges in global memory
+                    long long o = 0;
+                    const int64_t need = (int64_t)L + k;
+                    if (lane == 0) o = arena_alloc(d, gw, need);
+                    o = bcast_first64(o);
+                    if (o < 0) {
+                        if (lane == 0) atomicExch(&d.cnt->overflow, 1);
+                        failed = true;  // keep the stored column; redo next round
+                        break;
+                    }
+                    int32_t *out = d.arena + o;
+                    int32_t nL = 0;
+                    if (lane == 0) nL = merge_add(W, L, Sg, k, out, d.neg, compression);
+                    nL = bcast_first(nL);
+                    __threadfence();  // lane 0's global writes, then every lane reads them
+                    wave_sync();
+                    Bg = out;
+                    in_lds = false;
+                    LB = nL;
+                }
+                dirty = true;
+                refill();
             }
             next();
             if (i >= pi) {  // the low must drop; stop rather than spin
@@ -1076,7 +1093,11 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             }
         }
         if (!failed && valid && !flush()) failed = true;
-        if (kTrace && lane == 0) atomicMax(&d.cnt->max_chain, (int32_t)(adds - adds0));
+        wait_vmem();  // no record copy may land after this column is done
+        adds += cadds;
+        xe += cxe;
+        by += cby;
+        if (kTrace && lane == 0) atomicMax(&d.cnt->max_chain, cadds);
         if (failed || !dirty) continue;
         // write the result back
         if (LB == 0) {
@@ -1125,6 +1146,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         if (kTrace) {
             for (int q = 0; q < 9; q++) stat_add(d, S_T_SHORT + q, tr[q], gw);
             stat_add(d, S_T_FROMP, tr[9], gw);
+            stat_add(d, S_T_DEL, tr[10], gw);
         }
     }
 }
@@ -1518,11 +1540,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             fprintf(stderr,
                     "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
-                    "%llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
+                    "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
-                    dl[S_T_FROMP], dl[S_T_FLUSHES], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
+                    dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
         }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
