@@ -58,7 +58,7 @@ enum StatId {
     // opt-in trace of k_chain (PMS_TRACE=1): steps by path, working-column
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
-    S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL,
+    S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
     S_NUM
 };
 
@@ -578,17 +578,21 @@ __device__ inline uint32_t wave_or32(uint32_t x)
     return x;
 }
 
-// Lane chaining: one lane per queued column, the column in a per-lane LDS
-// buffer (entry e of lane t at sL[e * kLaneThreads + t], so a wave's lanes
-// hit consecutive banks).  Each step adds the pivot of the column's low; its
-// entries below the low (at most kRecInline, from the pivot record) are
-// merged in place from the top down, the larger column entries moving up by
-// the number of pivot entries still to place; cancelled pairs close the gap
-// by moving the merged top part down.  Columns that outgrow the buffer or
-// meet a longer pivot go to the wavefront kernel.
+// Lane chaining: one lane per queued column.  The column is W = B xor P:
+// B, its sorted base, sits in a per-lane LDS buffer (entry e of lane t at
+// sL[e * kLaneThreads + t], so a wave's lanes hit consecutive banks) and
+// only loses entries at its top; P, at most kLaneP pending toggles, lives in
+// registers in descending order (P[0] is its largest entry, -1 = empty) and
+// is updated by fixed compare-select networks.  A step removes the low and
+// toggles the pivot's entries below it (at most kRecInline, from its record)
+// into P, so its cost does not depend on the column's length; B and P are
+// merged in place when P is full.  Every changed column is written back
+// merged into the arena; columns that outgrow the buffer, meet a longer
+// pivot or chain too long go on to the wavefront kernel.
 constexpr int kLaneThreads = 128;
-constexpr int kLaneCap = 64;
-constexpr unsigned kLaneBlocks = 1024;
+constexpr int kLaneCap = 48;
+constexpr int kLaneP = 8;
+constexpr unsigned kLaneBlocks = 1536;
 constexpr int kLaneSteps = 48;  // a lane hands a longer chain to a wavefront
 
 __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace)
@@ -605,11 +609,79 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     const int64_t total = s_pre[kPart - 1];
     const int64_t gwave = (int64_t)blockIdx.x * (kLaneThreads / kWave) + tid / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * (kLaneThreads / kWave);
-    int64_t adds = 0, xe = 0, by = 0, bails = 0;
+    int64_t adds = 0, xe = 0, by = 0, bails = 0, tsl = 0, tg16 = 0, tg32 = 0;
     for (int64_t t0 = gwave * kWave; t0 < total; t0 += nwaves * kWave) {
         const int64_t t = t0 + lane;
-        int32_t j = -1, L = 0;
+        int32_t j = -1, LB = 0, np = 0;
+        int32_t p[kLaneP];
+#pragma unroll
+        for (int u = 0; u < kLaneP; u++) p[u] = -1;
         bool bail = false, dirty = false;
+        // P's top leaves it
+        auto shift_p = [&]() {
+#pragma unroll
+            for (int u = 0; u < kLaneP - 1; u++) p[u] = p[u + 1];
+            p[kLaneP - 1] = -1;
+            np--;
+        };
+        // the low of W: equal tops of B and P cancel
+        auto top = [&]() -> int32_t {
+            for (;;) {
+                const int32_t bt = LB > 0 ? LW(LB - 1) : -1;
+                if (p[0] != bt) return p[0] > bt ? p[0] : bt;
+                if (bt < 0) return -1;
+                shift_p();
+                LB--;
+            }
+        };
+        // P := P xor {x}
+        auto toggle = [&](int32_t x) {
+            bool pres = false;
+#pragma unroll
+            for (int u = 0; u < kLaneP; u++) pres = pres || p[u] == x;
+            int32_t q[kLaneP];
+#pragma unroll
+            for (int u = 0; u < kLaneP; u++) {
+                const int32_t nxt = u + 1 < kLaneP ? p[u + 1] : -1;
+                const int32_t prv = u > 0 ? p[u - 1] : 0x7FFFFFFF;
+                q[u] = p[u] > x ? p[u] : (pres ? nxt : (prv < x ? prv : x));
+            }
+#pragma unroll
+            for (int u = 0; u < kLaneP; u++) p[u] = q[u];
+            np += pres ? -1 : 1;
+        };
+        // B := B xor P in place, from the top down (needs LB + np <= kLaneCap);
+        // cancelled pairs close the gap by moving the merged top part down
+        auto flush = [&]() {
+            int32_t r = LB - 1, w = LB + np - 1, c = 0;
+#pragma unroll
+            for (int u = 0; u < kLaneP; u++) {
+                if (u < np) {
+                    const int32_t x = p[u];
+                    int32_t y = r >= 0 ? LW(r) : -1;
+                    while (y > x) {
+                        LW(w) = y;
+                        w--;
+                        r--;
+                        y = r >= 0 ? LW(r) : -1;
+                    }
+                    if (y == x) {  // 1 + 1 = 0
+                        r--;
+                        c++;
+                    } else {
+                        LW(w) = x;
+                        w--;
+                    }
+                }
+            }
+            const int32_t topi = LB + np - 1;
+            if (c)
+                for (int32_t e = w + 1; e <= topi; e++) LW(e - 2 * c) = LW(e);
+            LB = LB + np - 2 * c;
+#pragma unroll
+            for (int u = 0; u < kLaneP; u++) p[u] = -1;
+            np = 0;
+        };
         if (t < total) {
             int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
             while (lo < hi) {
@@ -619,94 +691,94 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
             }
             const int64_t before = lo > 0 ? s_pre[lo - 1] : 0;
             j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
-            L = d.len[j];
+            const int32_t L = d.len[j];
             by += 16 + 4 * (int64_t)L;
             if (L > kLaneCap) {
                 bail = true;
             } else {
                 const int32_t *g = col_base(d, d.off[j]);
                 for (int32_t e = 0; e < L; e++) LW(e) = g[e];
-                int32_t i = LW(L - 1);
-                Look lk = look_up(d, i);
+                LB = L;
+                int32_t i = top();
+                Look lk = look_up(d, i >= 0 ? i : 0);
                 int steps = 0;
-                while (L > 0) {
+                while (i >= 0) {
                     if (lk.s < 0) {
-                        if (compression && lk.neg) {  // a known-negative row: delete it
-                            L--;
-                            dirty = true;
-                            if (L == 0) break;
-                            i = LW(L - 1);
-                            lk = look_up(d, i);
-                            continue;
+                        if (!(compression && lk.neg)) break;  // no pivot: the chain ends
+                        if (p[0] == i) shift_p();  // a known-negative row: delete it
+                        else LB--;
+                        dirty = true;
+                    } else {
+                        const int32_t kk = lk.k - 1;
+                        if (kk > kRecInline || ++steps > kLaneSteps) {
+                            bail = true;
+                            break;
                         }
-                        break;
-                    }
-                    const int32_t kk = lk.k - 1;
-                    if (kk > kRecInline || L - 1 + kk > kLaneCap || ++steps > kLaneSteps) {
-                        bail = true;
-                        break;
-                    }
-                    adds++;
-                    xe += (int64_t)L + kk + 1;
-                    by += 32;
-                    int32_t r = L - 2, w = L - 2 + kk, ncan = 0;
+                        if (np + kk > kLaneP) {
+                            if (LB + np > kLaneCap) {
+                                bail = true;
+                                break;
+                            }
+                            flush();
+                        }
+                        adds++;
+                        xe += (int64_t)LB + np + kk + 1;
+                        by += 32;
+                        if (trace) {
+                            tsl += LB + np;
+                            tg16 += LB + np > 16 ? 1 : 0;
+                            tg32 += LB + np > 32 ? 1 : 0;
+                        }
+                        if (p[0] == i) shift_p();
+                        else LB--;
 #pragma unroll
-                    for (int q = kRecInline - 1; q >= 0; q--) {
-                        if (q < kk) {
-                            const int32_t x = lk.e[q];
-                            int32_t y = r >= 0 ? LW(r) : -1;
-                            while (y > x) {  // larger column entries move up past x
-                                LW(w) = y;
-                                w--;
-                                r--;
-                                y = r >= 0 ? LW(r) : -1;
-                            }
-                            if (y == x) {  // 1 + 1 = 0
-                                r--;
-                                ncan++;
-                            } else {
-                                LW(w) = x;
-                                w--;
-                            }
-                        }
+                        for (int q = 0; q < kRecInline; q++)
+                            if (q < kk) toggle(lk.e[q]);
+                        dirty = true;
                     }
-                    const int32_t top = L - 2 + kk;
-                    if (ncan)
-                        for (int32_t e = w + 1; e <= top; e++) LW(e - 2 * ncan) = LW(e);
-                    L = L - 1 + kk - 2 * ncan;
-                    dirty = true;
-                    if (L == 0) break;
-                    const int32_t ni = LW(L - 1);
+                    const int32_t ni = top();
                     if (ni >= i) {  // the low must drop; stop rather than spin
                         atomicExch(&d.cnt->bad_source, 2);
                         dirty = false;
                         break;
                     }
                     i = ni;
-                    lk = look_up(d, i);
+                    if (i >= 0) lk = look_up(d, i);
                 }
             }
         }
-        // write the changed columns back: one arena allocation per wave
-        const bool write = dirty && L > 0;
-        const int64_t need = write ? L : 0;
+        // write the changed columns back, B and P merged from the bottom up:
+        // one arena allocation per wave
+        const int64_t need = dirty ? (int64_t)LB + np : 0;
         const int64_t incl = wave_incl_sum64(need);
         const int64_t wtot = __shfl(incl, kWave - 1, kWave);
         long long base = 0;
         if (lane == 0 && wtot > 0) base = arena_alloc(d, (unsigned)gwave, wtot);
         base = __shfl(base, 0, kWave);
-        if (write && base < 0) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
-        if (write && base >= 0) {
-            const int64_t o = base + incl - need;
-            for (int32_t e = 0; e < L; e++) d.arena[o + e] = LW(e);
-            d.off[j] = o | (int64_t)kArenaBit;
-            d.len[j] = L;
-            d.low[j] = LW(L - 1);
-            by += 4 * (int64_t)L + 16;
-        } else if (dirty && L == 0) {
-            d.len[j] = 0;
-            d.low[j] = -1;
-            d.state[j] = ST_ZERO;  // column j is positive
+        if (dirty && base < 0) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
+        if (dirty && base >= 0) {
+            int32_t *out = d.arena + (base + incl - need);
+            int32_t w = 0, r = 0;
+#pragma unroll
+            for (int u = kLaneP - 1; u >= 0; u--) {
+                if (u < np) {
+                    const int32_t x = p[u];
+                    while (r < LB && LW(r) < x) out[w++] = LW(r++);
+                    if (r < LB && LW(r) == x) r++;  // 1 + 1 = 0
+                    else out[w++] = x;
+                }
+            }
+            while (r < LB) out[w++] = LW(r++);
+            if (w > 0) {
+                d.off[j] = (base + incl - need) | (int64_t)kArenaBit;
+                d.len[j] = w;
+                d.low[j] = out[w - 1];
+            } else {
+                d.len[j] = 0;
+                d.low[j] = -1;
+                d.state[j] = ST_ZERO;  // column j is positive
+            }
+            by += 4 * (int64_t)w + 16;
         }
         // hand the others over to the wavefront kernel
         const unsigned long long bal = __ballot(bail);
@@ -718,10 +790,10 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     }
 #undef LW
     // counters: lane sums -> one atomic per wave
-    const int32_t a32 = (int32_t)adds;
     const int64_t wadds = wave_incl_sum64(adds), wxe = wave_incl_sum64(xe), wby = wave_incl_sum64(by),
                   wb = wave_incl_sum64(bails);
-    (void)a32;
+    const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
+                  wg32 = trace ? wave_incl_sum64(tg32) : 0;
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, (unsigned)gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, (unsigned)gwave);
@@ -729,6 +801,9 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         if (trace) {
             stat_add(d, S_T_LANE, (unsigned long long)wadds, (unsigned)gwave);
             stat_add(d, S_T_BAIL, (unsigned long long)wb, (unsigned)gwave);
+            stat_add(d, S_T_LSUML, (unsigned long long)wsl, (unsigned)gwave);
+            stat_add(d, S_T_LGT16, (unsigned long long)wg16, (unsigned)gwave);
+            stat_add(d, S_T_LGT32, (unsigned long long)wg32, (unsigned)gwave);
         }
     }
 }
@@ -1540,11 +1615,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             fprintf(stderr,
                     "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
-                    "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f\n",
+                    "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
+                    "mean L %.1f, L>16 %llu, L>32 %llu\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
-                    dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st);
+                    dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st,
+                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32]);
         }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
