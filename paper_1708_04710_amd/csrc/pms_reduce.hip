@@ -586,207 +586,303 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // is updated by fixed compare-select networks.  A step removes the low and
 // toggles the pivot's entries below it (at most kRecInline, from its record)
 // into P, so its cost does not depend on the column's length; B and P are
-// merged in place when P is full.  Every changed column is written back
-// merged into the arena; columns that outgrow the buffer, meet a longer
-// pivot or chain too long go on to the wavefront kernel.
+// merged in place when P is full.  Lanes work independently: each loop
+// iteration every busy lane takes one step, and a lane whose chain ends
+// writes its column back merged into the arena (from a chunk its wave
+// claimed) and takes the wave's next queued column, so short and long chains
+// share a wave without idling it.  Columns that outgrow the buffer, meet a longer
+// pivot or chain longer than kLaneSteps go on to the wavefront kernel.
 constexpr int kLaneThreads = 128;
 constexpr int kLaneCap = 48;
 constexpr int kLaneP = 8;
 constexpr unsigned kLaneBlocks = 1536;
-constexpr int kLaneSteps = 48;  // a lane hands a longer chain to a wavefront
+// A lane hands a longer chain to a wavefront, whose steps are faster: with
+// many queued columns lanes keep chains longer (throughput), with few the
+// long chains move on early (they are the critical path).
+constexpr int kLaneSteps = 128;
+constexpr int kLaneStepsFew = 32;
+constexpr int32_t kLaneMany = 65536;  // queued columns from which a round counts as throughput-bound
+constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
+constexpr int kLaneRefill = 16;    // free lanes that trigger a wave's write-back and refill
 
 __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace)
 {
     __shared__ int32_t sL[kLaneCap * kLaneThreads];
     __shared__ int32_t s_pre[kPart];
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // the lanes under this one
 #define LW(e) sL[(e) * kLaneThreads + tid]
     if (tid < kPart) s_pre[tid] = d.cq_n[tid * 32];
     __syncthreads();
     if (tid == 0)
         for (int p = 1; p < kPart; p++) s_pre[p] += s_pre[p - 1];  // inclusive prefix of the slice sizes
     __syncthreads();
-    const int64_t total = s_pre[kPart - 1];
-    const int64_t gwave = (int64_t)blockIdx.x * (kLaneThreads / kWave) + tid / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kLaneThreads / kWave);
+    const int32_t total = s_pre[kPart - 1];
+    const int32_t step_cap = total >= kLaneMany ? kLaneSteps : kLaneStepsFew;
+    const unsigned gwave = blockIdx.x * (kLaneThreads / kWave) + (unsigned)bcast_first(tid / kWave);
     int64_t adds = 0, xe = 0, by = 0, bails = 0, tsl = 0, tg16 = 0, tg32 = 0;
-    for (int64_t t0 = gwave * kWave; t0 < total; t0 += nwaves * kWave) {
-        const int64_t t = t0 + lane;
-        int32_t j = -1, LB = 0, np = 0;
-        int32_t p[kLaneP];
+    // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
+    // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ...
+    const int64_t nwaves = (int64_t)gridDim.x * (kLaneThreads / kWave);
+    int64_t kc = gwave;
+    int32_t tb = 0, te = 0;
+    bool drained = false;
+    long long cb = 0, ce = 0;
+    // lane state
+    int32_t j = -1, LB = 0, np = 0, i = -1, steps = 0;
+    int32_t p[kLaneP];
 #pragma unroll
-        for (int u = 0; u < kLaneP; u++) p[u] = -1;
-        bool bail = false, dirty = false;
-        // P's top leaves it
-        auto shift_p = [&]() {
+    for (int u = 0; u < kLaneP; u++) p[u] = -1;
+    bool dirty = false;
+    Look lk{};
+    // P's top leaves it
+    auto shift_p = [&]() {
 #pragma unroll
-            for (int u = 0; u < kLaneP - 1; u++) p[u] = p[u + 1];
-            p[kLaneP - 1] = -1;
-            np--;
-        };
-        // the low of W: equal tops of B and P cancel
-        auto top = [&]() -> int32_t {
-            for (;;) {
-                const int32_t bt = LB > 0 ? LW(LB - 1) : -1;
-                if (p[0] != bt) return p[0] > bt ? p[0] : bt;
-                if (bt < 0) return -1;
-                shift_p();
-                LB--;
-            }
-        };
-        // P := P xor {x}
-        auto toggle = [&](int32_t x) {
-            bool pres = false;
+        for (int u = 0; u < kLaneP - 1; u++) p[u] = p[u + 1];
+        p[kLaneP - 1] = -1;
+        np--;
+    };
+    // the low of W: equal tops of B and P cancel
+    auto top = [&]() -> int32_t {
+        for (;;) {
+            const int32_t bt = LB > 0 ? LW(LB - 1) : -1;
+            if (p[0] != bt) return p[0] > bt ? p[0] : bt;
+            if (bt < 0) return -1;
+            shift_p();
+            LB--;
+        }
+    };
+    // P := P xor {x}
+    auto toggle = [&](int32_t x) {
+        bool pres = false;
 #pragma unroll
-            for (int u = 0; u < kLaneP; u++) pres = pres || p[u] == x;
-            int32_t q[kLaneP];
+        for (int u = 0; u < kLaneP; u++) pres = pres || p[u] == x;
+        int32_t q[kLaneP];
 #pragma unroll
-            for (int u = 0; u < kLaneP; u++) {
-                const int32_t nxt = u + 1 < kLaneP ? p[u + 1] : -1;
-                const int32_t prv = u > 0 ? p[u - 1] : 0x7FFFFFFF;
-                q[u] = p[u] > x ? p[u] : (pres ? nxt : (prv < x ? prv : x));
-            }
+        for (int u = 0; u < kLaneP; u++) {
+            const int32_t nxt = u + 1 < kLaneP ? p[u + 1] : -1;
+            const int32_t prv = u > 0 ? p[u - 1] : 0x7FFFFFFF;
+            q[u] = p[u] > x ? p[u] : (pres ? nxt : (prv < x ? prv : x));
+        }
 #pragma unroll
-            for (int u = 0; u < kLaneP; u++) p[u] = q[u];
-            np += pres ? -1 : 1;
-        };
-        // B := B xor P in place, from the top down (needs LB + np <= kLaneCap);
-        // cancelled pairs close the gap by moving the merged top part down
-        auto flush = [&]() {
-            int32_t r = LB - 1, w = LB + np - 1, c = 0;
+        for (int u = 0; u < kLaneP; u++) p[u] = q[u];
+        np += pres ? -1 : 1;
+    };
+    // B := B xor P in place, from the top down (needs LB + np <= kLaneCap);
+    // cancelled pairs close the gap by moving the merged top part down
+    auto flush = [&]() {
+        int32_t r = LB - 1, w = LB + np - 1, c = 0;
 #pragma unroll
-            for (int u = 0; u < kLaneP; u++) {
-                if (u < np) {
-                    const int32_t x = p[u];
-                    int32_t y = r >= 0 ? LW(r) : -1;
-                    while (y > x) {
-                        LW(w) = y;
-                        w--;
-                        r--;
-                        y = r >= 0 ? LW(r) : -1;
-                    }
-                    if (y == x) {  // 1 + 1 = 0
-                        r--;
-                        c++;
-                    } else {
-                        LW(w) = x;
-                        w--;
-                    }
+        for (int u = 0; u < kLaneP; u++) {
+            if (u < np) {
+                const int32_t x = p[u];
+                int32_t y = r >= 0 ? LW(r) : -1;
+                while (y > x) {
+                    LW(w) = y;
+                    w--;
+                    r--;
+                    y = r >= 0 ? LW(r) : -1;
+                }
+                if (y == x) {  // 1 + 1 = 0
+                    r--;
+                    c++;
+                } else {
+                    LW(w) = x;
+                    w--;
                 }
             }
-            const int32_t topi = LB + np - 1;
-            if (c)
-                for (int32_t e = w + 1; e <= topi; e++) LW(e - 2 * c) = LW(e);
-            LB = LB + np - 2 * c;
+        }
+        const int32_t topi = LB + np - 1;
+        if (c)
+            for (int32_t e = w + 1; e <= topi; e++) LW(e - 2 * c) = LW(e);
+        LB = LB + np - 2 * c;
 #pragma unroll
-            for (int u = 0; u < kLaneP; u++) p[u] = -1;
-            np = 0;
-        };
-        if (t < total) {
-            int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_pre[mid] > t) hi = mid;
-                else lo = mid + 1;
+        for (int u = 0; u < kLaneP; u++) p[u] = -1;
+        np = 0;
+    };
+    bool fin = true, bail = false;  // fin: no column in progress (finished, or never given one)
+    for (;;) {
+        // finished lanes are written back and refilled together, once at
+        // least kLaneRefill of them (or every lane) are waiting: the wave-wide
+        // work is shared by many columns
+        const uint64_t finm = __ballot(fin);
+        const bool more = !(drained && tb >= te);  // tasks left for this wave
+        const uint64_t want = __ballot(fin && (j >= 0 || more));
+        if (__popcll(want) >= kLaneRefill || finm == ~0ull) {
+            // write back (B and P merged from the bottom up) from the wave's arena chunk
+            const bool wr = fin && j >= 0 && dirty;
+            const int32_t need = wr ? LB + np : 0;
+            const int32_t incl = wave_incl_sum32(need);
+            const int32_t wtot = bcast_lane(incl, kWave - 1);
+            if (wtot > 0 && ce - cb < wtot) {
+                const int32_t claim = wtot > kLaneChunk ? wtot : kLaneChunk;
+                long long o = 0;
+                if (lane == 0) o = arena_alloc(d, gwave, claim);
+                o = bcast_first64(o);
+                if (o < 0) {
+                    cb = ce = 0;
+                } else {
+                    cb = o;
+                    ce = o + claim;
+                }
             }
-            const int64_t before = lo > 0 ? s_pre[lo - 1] : 0;
-            j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
-            const int32_t L = d.len[j];
-            by += 16 + 4 * (int64_t)L;
-            if (L > kLaneCap) {
-                bail = true;
-            } else {
-                const int32_t *g = col_base(d, d.off[j]);
-                for (int32_t e = 0; e < L; e++) LW(e) = g[e];
-                LB = L;
-                int32_t i = top();
-                Look lk = look_up(d, i >= 0 ? i : 0);
-                int steps = 0;
-                while (i >= 0) {
-                    if (lk.s < 0) {
-                        if (!(compression && lk.neg)) break;  // no pivot: the chain ends
-                        if (p[0] == i) shift_p();  // a known-negative row: delete it
-                        else LB--;
-                        dirty = true;
-                    } else {
-                        const int32_t kk = lk.k - 1;
-                        if (kk > kRecInline || ++steps > kLaneSteps) {
-                            bail = true;
-                            break;
-                        }
-                        if (np + kk > kLaneP) {
-                            if (LB + np > kLaneCap) {
-                                bail = true;
-                                break;
-                            }
-                            flush();
-                        }
-                        adds++;
-                        xe += (int64_t)LB + np + kk + 1;
-                        by += 32;
-                        if (trace) {
-                            tsl += LB + np;
-                            tg16 += LB + np > 16 ? 1 : 0;
-                            tg32 += LB + np > 32 ? 1 : 0;
-                        }
-                        if (p[0] == i) shift_p();
-                        else LB--;
+            const bool room = wtot == 0 || ce - cb >= wtot;
+            if (wr && !room) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
+            if (wr && room) {
+                const long long o = cb + incl - need;
+                int32_t *out = d.arena + o;
+                int32_t w = 0, r = 0;
 #pragma unroll
-                        for (int q = 0; q < kRecInline; q++)
-                            if (q < kk) toggle(lk.e[q]);
-                        dirty = true;
+                for (int u = kLaneP - 1; u >= 0; u--) {
+                    if (u < np) {
+                        const int32_t x = p[u];
+                        while (r < LB && LW(r) < x) out[w++] = LW(r++);
+                        if (r < LB && LW(r) == x) r++;  // 1 + 1 = 0
+                        else out[w++] = x;
                     }
+                }
+                while (r < LB) out[w++] = LW(r++);
+                if (w > 0) {
+                    d.off[j] = o | (int64_t)kArenaBit;
+                    d.len[j] = w;
+                    d.low[j] = out[w - 1];
+                } else {
+                    d.len[j] = 0;
+                    d.low[j] = -1;
+                    d.state[j] = ST_ZERO;  // column j is positive
+                }
+                by += 4 * (int64_t)w + 16;
+            }
+            if (room) cb += wtot;
+            // hand the bailing columns over to the wavefront kernel
+            const uint64_t bal = __ballot(fin && bail);
+            if (bal) {
+                int32_t qb = 0;
+                if (lane == 0) qb = atomicAdd(&d.cq_n[kPart * 32], (int32_t)__popcll(bal));
+                qb = bcast_first(qb);
+                if (fin && bail) d.wq[qb + __popcll(bal & below)] = j;
+                bails += (fin && bail) ? 1 : 0;
+            }
+            if (fin) {
+                j = -1;
+                bail = false;
+            }
+            // refill: the wave's next tasks to the free lanes
+            uint64_t idle = finm;
+            for (int pass = 0; pass < 2 && idle && !(drained && tb >= te); pass++) {
+                if (tb >= te && !drained) {  // the wave's next chunk of 64 tasks
+                    const int64_t nb = kc * kWave;
+                    kc += nwaves;
+                    if (nb >= total) {
+                        drained = true;
+                        break;
+                    }
+                    tb = (int32_t)nb;
+                    te = (int32_t)min(nb + kWave, (int64_t)total);
+                }
+                const int32_t rank = __popcll(idle & below);
+                const int32_t avail = te - tb;
+                if (((idle >> lane) & 1ull) && rank < avail) {
+                    const int32_t t = tb + rank;
+                    int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] > t) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int32_t before = lo > 0 ? s_pre[lo - 1] : 0;
+                    j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
+                    fin = false;
+                }
+                tb += min(__popcll(idle), avail);
+                idle = __ballot(fin);
+            }
+            if (__ballot(!fin) == 0) break;  // every lane free and the queue drained
+            // load the new columns (all new lanes at once, 8 loads in flight each)
+            const bool fresh = ((finm >> lane) & 1ull) && !fin;
+            if (fresh) {
+                const int32_t L = d.len[j];
+                by += 16 + 4 * (int64_t)L;
+                np = 0;
+#pragma unroll
+                for (int u = 0; u < kLaneP; u++) p[u] = -1;
+                dirty = false;
+                steps = 0;
+                if (L > kLaneCap) {
+                    bail = true;  // too long for a lane: straight to the wavefront kernel
+                    fin = true;
+                    LB = 0;
+                } else {
+                    const int32_t *g = col_base(d, d.off[j]);
+                    for (int32_t e0 = 0; e0 < L; e0 += 8) {
+                        int32_t v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; u++) v[u] = e0 + u < L ? g[e0 + u] : 0;
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+                            if (e0 + u < L) LW(e0 + u) = v[u];
+                    }
+                    LB = L;
+                    i = top();
+                    lk = look_up(d, i >= 0 ? i : 0);
+                }
+            }
+        }
+        // one step for every lane with a column in progress
+        if (!fin) {
+            if (i < 0) {
+                fin = true;  // W is zero
+            } else if (lk.s < 0) {
+                if (compression && lk.neg) {  // a known-negative row: delete it
+                    if (p[0] == i) shift_p();
+                    else LB--;
+                    dirty = true;
                     const int32_t ni = top();
                     if (ni >= i) {  // the low must drop; stop rather than spin
                         atomicExch(&d.cnt->bad_source, 2);
                         dirty = false;
-                        break;
+                        fin = true;
+                    } else {
+                        i = ni;
+                        if (i >= 0) lk = look_up(d, i);
                     }
-                    i = ni;
-                    if (i >= 0) lk = look_up(d, i);
+                } else {
+                    fin = true;  // no pivot owns the low: the chain ends here
                 }
-            }
-        }
-        // write the changed columns back, B and P merged from the bottom up:
-        // one arena allocation per wave
-        const int64_t need = dirty ? (int64_t)LB + np : 0;
-        const int64_t incl = wave_incl_sum64(need);
-        const int64_t wtot = __shfl(incl, kWave - 1, kWave);
-        long long base = 0;
-        if (lane == 0 && wtot > 0) base = arena_alloc(d, (unsigned)gwave, wtot);
-        base = __shfl(base, 0, kWave);
-        if (dirty && base < 0) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
-        if (dirty && base >= 0) {
-            int32_t *out = d.arena + (base + incl - need);
-            int32_t w = 0, r = 0;
-#pragma unroll
-            for (int u = kLaneP - 1; u >= 0; u--) {
-                if (u < np) {
-                    const int32_t x = p[u];
-                    while (r < LB && LW(r) < x) out[w++] = LW(r++);
-                    if (r < LB && LW(r) == x) r++;  // 1 + 1 = 0
-                    else out[w++] = x;
-                }
-            }
-            while (r < LB) out[w++] = LW(r++);
-            if (w > 0) {
-                d.off[j] = (base + incl - need) | (int64_t)kArenaBit;
-                d.len[j] = w;
-                d.low[j] = out[w - 1];
             } else {
-                d.len[j] = 0;
-                d.low[j] = -1;
-                d.state[j] = ST_ZERO;  // column j is positive
+                const int32_t kk = lk.k - 1;
+                if (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > kLaneCap)) {
+                    bail = true;
+                    fin = true;
+                } else {
+                    if (np + kk > kLaneP) flush();
+                    steps++;
+                    adds++;
+                    xe += (int64_t)LB + np + kk + 1;
+                    by += 32;
+                    if (trace) {
+                        tsl += LB + np;
+                        tg16 += LB + np > 16 ? 1 : 0;
+                        tg32 += LB + np > 32 ? 1 : 0;
+                    }
+                    if (p[0] == i) shift_p();
+                    else LB--;
+#pragma unroll
+                    for (int q = 0; q < kRecInline; q++)
+                        if (q < kk) toggle(lk.e[q]);
+                    dirty = true;
+                    const int32_t ni = top();
+                    if (ni >= i) {
+                        atomicExch(&d.cnt->bad_source, 2);
+                        dirty = false;
+                        fin = true;
+                    } else {
+                        i = ni;
+                        if (i >= 0) lk = look_up(d, i);
+                    }
+                }
             }
-            by += 4 * (int64_t)w + 16;
         }
-        // hand the others over to the wavefront kernel
-        const unsigned long long bal = __ballot(bail);
-        int32_t qb = 0;
-        if (lane == 0 && bal) qb = atomicAdd(&d.cq_n[kPart * 32], (int32_t)__popcll(bal));
-        qb = __shfl(qb, 0, kWave);
-        if (bail) d.wq[qb + __popcll(bal & ((1ull << lane) - 1ull))] = j;
-        bails += bail ? 1 : 0;
     }
 #undef LW
     // counters: lane sums -> one atomic per wave
@@ -795,15 +891,15 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
                   wg32 = trace ? wave_incl_sum64(tg32) : 0;
     if (lane == kWave - 1) {
-        stat_add(d, S_ADDS, (unsigned long long)wadds, (unsigned)gwave);
-        stat_add(d, S_XE, (unsigned long long)wxe, (unsigned)gwave);
-        stat_add(d, S_LBYTES, (unsigned long long)wby, (unsigned)gwave);
+        stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
+        stat_add(d, S_XE, (unsigned long long)wxe, gwave);
+        stat_add(d, S_LBYTES, (unsigned long long)wby, gwave);
         if (trace) {
-            stat_add(d, S_T_LANE, (unsigned long long)wadds, (unsigned)gwave);
-            stat_add(d, S_T_BAIL, (unsigned long long)wb, (unsigned)gwave);
-            stat_add(d, S_T_LSUML, (unsigned long long)wsl, (unsigned)gwave);
-            stat_add(d, S_T_LGT16, (unsigned long long)wg16, (unsigned)gwave);
-            stat_add(d, S_T_LGT32, (unsigned long long)wg32, (unsigned)gwave);
+            stat_add(d, S_T_LANE, (unsigned long long)wadds, gwave);
+            stat_add(d, S_T_BAIL, (unsigned long long)wb, gwave);
+            stat_add(d, S_T_LSUML, (unsigned long long)wsl, gwave);
+            stat_add(d, S_T_LGT16, (unsigned long long)wg16, gwave);
+            stat_add(d, S_T_LGT32, (unsigned long long)wg32, gwave);
         }
     }
 }
