@@ -141,6 +141,24 @@ typedef struct {
  * Phase II simultaneous column additions, with clearing and compression). */
 pms_status pms_reduce(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *opt, pms_result *res);
 
+/* Reduce `count` filtrations concatenated block-diagonally (as built by
+ * pms_build_vr_*: instance b owns the columns [inst_col_off[b],
+ * inst_col_off[b+1]) and its rows stay in that range), in one pms_reduce of
+ * the whole matrix; the instances never interact, so each gets its own
+ * exact pairs (Sec. 2.3).  inst_col_off: device, count + 1 entries
+ * ascending from 0 to m (checked: PMS_ERR_INVALID_ARG otherwise).  Outputs
+ * beyond pms_reduce's, each optional (NULL = not wanted), device:
+ *   inst_pair_off[b], inst_ess_off[b] (count + 1 entries): where instance
+ *     b's pairs / essential simplices start in res's arrays (its pairs are
+ *     those whose death column is in its range; they are contiguous since
+ *     the arrays ascend);
+ *   pair_inst[k] (res->cap_pairs entries): the instance of pair k.
+ * The pair / essential arrays of res must be given for the offsets of
+ * the pairs / essentials to be meaningful (0 otherwise). */
+pms_status pms_reduce_batched(pms_ctx *ctx, int32_t count, const int64_t *inst_col_off, const pms_boundary *bnd,
+                              const pms_options *opt, pms_result *res, int64_t *inst_pair_off, int64_t *inst_ess_off,
+                              int32_t *pair_inst);
+
 /* ------------------------------------------------------------------------
  * Filtrations built on the device.  A pms_filtration is library-owned
  * device memory holding a filtration in compatible order (Sec. 2.2: the

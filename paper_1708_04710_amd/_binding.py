@@ -30,7 +30,7 @@ STATUS_NAMES = {
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
-    "pms_reduce", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
+    "pms_reduce", "pms_reduce_batched", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
 ]
@@ -97,6 +97,9 @@ def load(path: str = LIB_PATH):
     lib.pms_reduce.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                ctypes.POINTER(PmsResult)]
     lib.pms_reduce.restype = ctypes.c_int
+    lib.pms_reduce_batched.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
+                                       ctypes.POINTER(PmsResult), P, P, P]
+    lib.pms_reduce_batched.restype = ctypes.c_int
     lib.pms_profile_enable.argtypes = [P, ctypes.c_int]
     lib.pms_profile_enable.restype = ctypes.c_int
     lib.pms_profile_kernels.argtypes = []

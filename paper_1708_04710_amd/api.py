@@ -87,6 +87,11 @@ class ReduceResult:
     phase0_pivots: int
     additions: int
     xor_entries: int
+    # batched reductions only (reduce_batched): per-instance starts in the
+    # pair / essential lists ([count+1] int64) and the instance of each pair
+    inst_pair_off: torch.Tensor | None = None
+    inst_ess_off: torch.Tensor | None = None
+    pair_inst: torch.Tensor | None = None
 
 
 class Filtration:
@@ -204,7 +209,8 @@ def _dptr(t):
 
 
 def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=True, max_rounds=0,
-                 chain=True, tail_active=1024, validate=True, outputs=True, arena_entries=0) -> ReduceResult:
+                 chain=True, tail_active=1024, validate=True, outputs=True, arena_entries=0,
+                 inst_col_off=None) -> ReduceResult:
     lib = B.load()
     ctx = _ctx(dev)
     low_star = torch.empty(m, dtype=torch.int32, device=dev)
@@ -224,11 +230,22 @@ def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=Tru
         res.cap_pairs = cap_p
         res.essential = ess.data_ptr() if cap_e else None
         res.cap_essential = cap_e
-    st = lib.pms_reduce(ctx, ctypes.byref(bnd), ctypes.byref(opt), ctypes.byref(res))
+    extra = {}
+    if inst_col_off is None:
+        st = lib.pms_reduce(ctx, ctypes.byref(bnd), ctypes.byref(opt), ctypes.byref(res))
+    else:
+        nb = inst_col_off.numel() - 1
+        poff = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+        eoff = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+        pinst = torch.empty(max(cap_p, 1), dtype=torch.int32, device=dev)
+        st = lib.pms_reduce_batched(ctx, nb, inst_col_off.data_ptr(), ctypes.byref(bnd), ctypes.byref(opt),
+                                    ctypes.byref(res), poff.data_ptr(), eoff.data_ptr(),
+                                    pinst.data_ptr() if outputs else None)
+        extra = dict(inst_pair_off=poff, inst_ess_off=eoff, pair_inst=pinst[:res.n_pairs] if outputs else None)
     B.check(ctx, st)
     return ReduceResult(low_star=low_star, pair_birth=birth[:res.n_pairs], pair_death=death[:res.n_pairs],
                         essential=ess[:res.n_essential], rounds=res.rounds, phase0_pivots=res.phase0_pivots,
-                        additions=res.additions, xor_entries=res.xor_entries)
+                        additions=res.additions, xor_entries=res.xor_entries, **extra)
 
 
 def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None = None, **kw) -> ReduceResult:
@@ -260,3 +277,13 @@ def reduce_filtration(f: Filtration, **kw) -> ReduceResult:
     """Reduce a device-built filtration in place of its library-owned arrays."""
     v = f.view
     return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, **kw)
+
+
+def reduce_batched(f: Filtration, col_off, **kw) -> ReduceResult:
+    """Reduce a batch built by ``build_vr`` (``pms_reduce_batched``): same as
+    ``reduce_filtration``, plus the per-instance pair / essential offsets and
+    the instance of every pair.  ``col_off``: the instances' column offsets
+    (count + 1 entries, host list or int64 tensor)."""
+    off = torch.as_tensor(col_off, dtype=torch.int64).to(f.device)
+    v = f.view
+    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, inst_col_off=off, **kw)

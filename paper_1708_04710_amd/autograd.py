@@ -69,12 +69,11 @@ class PersistenceVR(torch.autograd.Function):
         pts = points.detach().contiguous()
         nb, n, D = pts.shape
         f, off = api.build_vr(list(pts.unbind(0)), thresholds, maxdim, out=workspace)
-        res = api.reduce_filtration(f, **(reduce_kw or {}))
+        res = api.reduce_batched(f, off, **(reduce_kw or {}))
         idx = torch.cat([res.pair_birth, res.pair_death])
         vals, dims = gather(f, idx)
         m = res.pair_birth.numel()
-        offs = torch.as_tensor(off[1:], dtype=torch.int64, device=pts.device)
-        cloud = torch.searchsorted(offs, res.pair_death.to(torch.int64), right=True)
+        cloud = res.pair_inst.to(torch.int64)
         ctx.f, ctx.idx, ctx.pts, ctx.D = f, idx, pts, D
         ctx.result = res
         pair_dims = dims[:m].to(torch.int64)

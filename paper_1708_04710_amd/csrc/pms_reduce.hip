@@ -43,6 +43,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "pms_common.h"
 
@@ -1768,6 +1769,50 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 // ==================================================================== ABI
 struct pms_ctx : pms::Ctx {};
 
+namespace pms {
+
+__device__ inline int64_t lower_bound_i64(const int32_t *a, int64_t n, int64_t x)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Where each instance's pairs and essential simplices start: the outputs are
+// ascending in the death (resp. essential) index and instance b owns the
+// columns [col_off[b], col_off[b+1]), so one lower bound per instance.
+__global__ void k_inst_offsets(int32_t count, const int64_t *col_off, const int32_t *pair_death, int64_t n_pairs,
+                               const int32_t *essential, int64_t n_ess, int64_t *pair_off, int64_t *ess_off)
+{
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= count; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = col_off[b];
+        if (pair_off) pair_off[b] = pair_death ? lower_bound_i64(pair_death, n_pairs, c) : 0;
+        if (ess_off) ess_off[b] = essential ? lower_bound_i64(essential, n_ess, c) : 0;
+    }
+}
+
+// The instance of every pair (the one owning its death column).
+__global__ void k_pair_inst(int32_t count, const int64_t *col_off, const int32_t *pair_death, int64_t n_pairs,
+                            int32_t *pair_inst)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_pairs; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = pair_death[k];
+        int32_t lo = 0, hi = count - 1;  // last instance whose first column is <= j
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (col_off[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        pair_inst[k] = lo;
+    }
+}
+
+}  // namespace pms
+
 extern "C" {
 
 const char *pms_version(void) { return "pms-gfx950 0.1"; }
@@ -1892,6 +1937,42 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         res->n_pairs = res->n_essential = 0;
     }
     return s;
+}
+
+pms_status pms_reduce_batched(pms_ctx *c, int32_t count, const int64_t *inst_col_off, const pms_boundary *bnd,
+                              const pms_options *opt, pms_result *res, int64_t *inst_pair_off, int64_t *inst_ess_off,
+                              int32_t *pair_inst)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!bnd || !res || count < 1 || !inst_col_off)
+        return pms::set_err(c, PMS_ERR_INVALID_ARG, "null boundary / result / offsets, or count < 1");
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    {
+        // the offsets: count + 1 entries, ascending from 0 to m
+        std::vector<int64_t> h((size_t)count + 1);
+        PMS_HIP(hipMemcpyAsync(h.data(), inst_col_off, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        PMS_HIP(hipStreamSynchronize(c->stream));
+        bool ok = h[0] == 0 && h[count] == bnd->m;
+        for (int32_t b = 0; ok && b < count; b++) ok = h[b] <= h[b + 1];
+        if (!ok)
+            return pms::set_err(c, PMS_ERR_INVALID_ARG,
+                                "inst_col_off must ascend from 0 to m (count + 1 entries)");
+    }
+    pms_status s = pms_reduce(c, bnd, opt, res);
+    if (s != PMS_OK) return s;
+    const bool pairs = res->pair_birth && res->pair_death;
+    if (inst_pair_off || inst_ess_off)
+        PMS_LAUNCH(c, pms::K_FINAL, 16.0 * (count + 1), pms::k_inst_offsets, pms::grid_for(count + 1), pms::kBlock,
+                   count, inst_col_off, pairs ? res->pair_death : nullptr, res->n_pairs, res->essential,
+                   res->n_essential, inst_pair_off, inst_ess_off);
+    if (pair_inst && pairs && res->n_pairs > 0)
+        PMS_LAUNCH(c, pms::K_FINAL, 8.0 * res->n_pairs, pms::k_pair_inst, pms::grid_for(res->n_pairs, pms::kBlock, 65536),
+                   pms::kBlock, count, inst_col_off, res->pair_death, res->n_pairs, pair_inst);
+    PMS_HIP(hipGetLastError());
+    PMS_HIP(hipStreamSynchronize(c->stream));
+    if (c->prof_on) pms::prof_flush(c);
+    return PMS_OK;
 }
 
 }  // extern "C"

@@ -176,3 +176,37 @@ def test_vr_batch512_sampled(gpu):
 def test_vr_builder_rejects_large_cloud(gpu):
     with pytest.raises(_binding.PmsError):
         api.build_vr([torch.zeros((600, 2), dtype=torch.int32, device=gpu)], [-1], 2)
+
+
+def test_reduce_batched_instance_offsets(gpu):
+    """pms_reduce_batched: each instance's pairs and essential simplices are
+    the contiguous slices its offsets name, equal to the oracle's for that
+    cloud alone; pair_inst names the instance of every pair."""
+    inst = synth.vr_batch(seed=33, count=7, n_range=(3, 36))
+    clouds = [np.zeros((0, 3), np.int32)] + [p for p, _ in inst] + [np.array([[1, 2, 3]], np.int32)]
+    thrs = [-1] + [t for _, t in inst] + [-1]
+    f, off = api.build_vr([torch.as_tensor(c, device=gpu) for c in clouds], thrs, 2)
+    res = api.reduce_batched(f, off)
+    poff = res.inst_pair_off.cpu().numpy()
+    eoff = res.inst_ess_off.cpu().numpy()
+    pb, pd = res.pair_birth.cpu().numpy(), res.pair_death.cpu().numpy()
+    ess = res.essential.cpu().numpy()
+    pinst = res.pair_inst.cpu().numpy()
+    assert poff[0] == 0 and poff[-1] == len(pd) and eoff[0] == 0 and eoff[-1] == len(ess)
+    for b, (c, t) in enumerate(zip(clouds, thrs)):
+        ref = oracle.build_vr_i32(c, t, 2)
+        low = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        rb, rd = oracle.pairs(low)
+        re = oracle.essential(low)
+        sl = slice(poff[b], poff[b + 1])
+        assert np.array_equal(pb[sl] - off[b], rb) and np.array_equal(pd[sl] - off[b], rd), b
+        assert np.array_equal(ess[eoff[b]:eoff[b + 1]] - off[b], re), b
+        assert np.all(pinst[sl] == b)
+
+
+def test_reduce_batched_rejects_bad_offsets(gpu):
+    f, off = api.build_vr([torch.as_tensor(synth.vr_grid_cloud()[:20], device=gpu)], [-1], 2)
+    for bad in ([0, off[1] - 1], [1, off[1]]):
+        with pytest.raises(_binding.PmsError) as e:
+            api.reduce_batched(f, bad)
+        assert e.value.status == _binding.PMS_ERR_INVALID_ARG
