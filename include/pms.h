@@ -103,6 +103,12 @@ typedef struct {
     int32_t tail_active;
     /* 1 = check the CSC input (sorted rows, upper triangular, dims). */
     int32_t validate;
+    /* > 0: run the rounds as a HIP graph of this many rounds (rounded up to
+     * even) captured once and replayed, one host synchronisation per replay
+     * instead of one per round; rounds after convergence do nothing.  Used
+     * only with max_rounds = 0 and the profiler off.  0 = one round at a time. */
+    int32_t graph_rounds;
+    int32_t reserved;       /* 0 */
     /* Initial capacity of the column arena in int32 entries; 0 = automatic.
      * A non-zero value reallocates the arena to exactly this size (the
      * arena still grows when fill-in exceeds it). */

@@ -45,6 +45,7 @@ class PmsOptions(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("compression", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("chain", ctypes.c_int32),
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("graph_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("arena_entries", ctypes.c_int64)]
 
 

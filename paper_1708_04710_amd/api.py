@@ -210,7 +210,7 @@ def _dptr(t):
 
 def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=True, max_rounds=0,
                  chain=True, tail_active=1024, validate=True, outputs=True, arena_entries=0,
-                 inst_col_off=None) -> ReduceResult:
+                 graph_rounds=0, inst_col_off=None) -> ReduceResult:
     lib = B.load()
     ctx = _ctx(dev)
     low_star = torch.empty(m, dtype=torch.int32, device=dev)
@@ -221,7 +221,7 @@ def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=Tru
     ess = torch.empty(cap_e, dtype=torch.int32, device=dev)
     bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
     opt = B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
-                       int(bool(validate)), arena_entries)
+                       int(bool(validate)), graph_rounds, 0, arena_entries)
     res = B.PmsResult()
     res.low_star = low_star.data_ptr() if m else None
     if outputs:
@@ -254,7 +254,7 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     col_ptr: int64 [m+1]; rows: int32 [nnz] ascending per column; dim: int8 [m]
     or None.  All on the same device.  Keyword options as in ``pms_options``:
     variant, compression, max_rounds, chain, tail_active, validate,
-    arena_entries; ``outputs=False`` skips the pair / essential lists."""
+    graph_rounds, arena_entries; ``outputs=False`` skips the pair / essential lists."""
     if not col_ptr.is_cuda or not rows.is_cuda or (dim is not None and not dim.is_cuda):
         raise ValueError("col_ptr, rows and dim must be device tensors")
     if col_ptr.dtype != torch.int64 or rows.dtype != torch.int32 or (dim is not None and dim.dtype != torch.int8):

@@ -53,6 +53,10 @@ struct Ctx {
     int32_t *arena = nullptr;
     uint64_t arena_cap = 0;  // entries
     void *host_pinned = nullptr;
+    // graph-mode rounds: captured and replayed on a stream of the context
+    // (the caller's may be the legacy default stream, which cannot capture)
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_ev = nullptr;
 };
 
 enum BufId {

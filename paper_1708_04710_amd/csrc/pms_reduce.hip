@@ -50,6 +50,7 @@
 namespace pms {
 
 enum : uint8_t { ST_ACTIVE = 0, ST_PIVOT = 1, ST_ZERO = 2, ST_CLEARED = 3 };
+constexpr int8_t kNotLive = 2;  // coll[q]: column act[q] was not active when the round's collisions were taken
 
 constexpr uint64_t kArenaBit = 1ull << 62;
 constexpr int kScanThreads = 1024;
@@ -80,7 +81,8 @@ struct Counters {
     int32_t n_ess;
     int32_t bad_source;  // internal invariant broken (never expected)
     int32_t max_chain;   // trace: most additions one column made in k_chain this round
-    int32_t pad[2];
+    int32_t n_cur;       // active columns of the current round (read by the round kernels)
+    uint32_t round;      // rounds that did work so far
     unsigned long long trace[S_NUM];  // folded stripes (trace output)
 };
 
@@ -251,8 +253,10 @@ __global__ void k_beta(Dev d, int compression)
 }
 
 // ---------------------------------------------------------------- round
-__global__ void k_low(Dev d, const int32_t *act, int32_t nA, uint32_t round)
+__global__ void k_low(Dev d, const int32_t *act)
 {
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nA; q += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = act[q];
         int32_t n = d.len[j];
@@ -276,15 +280,19 @@ __global__ void k_low(Dev d, const int32_t *act, int32_t nA, uint32_t round)
 }
 
 // One tile of kBlock active positions per block.
-__global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, int32_t nA, uint32_t round, I4 *agg)
+__global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I4 *agg)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q <= kPart) d.cq_n[q * 32] = 0;  // the chain queues of this round start empty
-    if (q == 0) d.cnt->max_chain = 0;
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    if (blockIdx.x == 0 && threadIdx.x <= kPart) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = 0;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t q = tile * kBlock + threadIdx.x;
     I4 e = i4_fill(-1);
     if (q < nA) {
         const int32_t j = act[q];
-        int8_t cl = 0;
+        int8_t cl = kNotLive;  // the state as of this kernel, for the rest of the round
         if (d.state[j] == ST_ACTIVE) {
             const int32_t i = d.low[j];
             const int32_t t = t_decode(d.T[i], round);
@@ -295,12 +303,15 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, i
     }
     I4 tot;
     block_excl_max4(e, &tot);
-    if (threadIdx.x == 0) agg[blockIdx.x] = tot;
+    if (threadIdx.x == 0) agg[tile] = tot;
+    __syncthreads();
+    }
 }
 
 // Exclusive max-scan of the per-block aggregates, one block of 1024 threads.
-__global__ void __launch_bounds__(kScanThreads) k_scan_max4(I4 *agg, int64_t nb)
+__global__ void __launch_bounds__(kScanThreads) k_scan_max4(I4 *agg, const int32_t *n_cur)
 {
+    const int64_t nb = ((int64_t)*n_cur + kBlock - 1) / kBlock;  // one aggregate per tile of the round
     __shared__ I4 s_w[kScanThreads / kWave];
     __shared__ I4 s_carry;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -330,8 +341,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_max4(I4 *agg, int64_t nb)
     }
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_sum(int32_t *cnt, int64_t nb, int32_t *total)
+// nb entries, or, when n_cur is given, one entry per tile of *n_cur columns
+__global__ void __launch_bounds__(kScanThreads) k_scan_sum(int32_t *cnt, int64_t nb, const int32_t *n_cur,
+                                                           int32_t *total)
 {
+    if (n_cur) nb = ((int64_t)*n_cur + kBlock - 1) / kBlock;
     __shared__ int32_t s_w[kScanThreads / kWave];
     __shared__ int32_t s_carry;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -357,24 +371,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sum(int32_t *cnt, int64_t
 }
 
 // Phase I + the beta test + clearing.
-__global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, int32_t nA, const I4 *agg,
-                                                   int compression, int count_beta)
+__global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, const I4 *agg, int compression)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t nA = d.cnt->n_cur;
+    const int count_beta = d.cnt->round == 0;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t q = tile * kBlock + threadIdx.x;
     I4 e = i4_fill(-1);
     int32_t j = -1, i = -1;
     bool live = false, cl = false;
     if (q < nA) {
         j = act[q];
-        live = d.state[j] == ST_ACTIVE;
+        // liveness as k_collide saw it: columns cleared by other threads of
+        // this kernel stay in the test, so the pivots found do not depend on
+        // timing (a cleared column is positive and never passes it)
+        const int8_t c0 = d.coll[q];
+        live = c0 != kNotLive;
         if (live) {
             i = d.low[j];
-            cl = d.coll[q] != 0;
+            cl = c0 == 1;
             if (cl) e.v[slot_of(d, j)] = i;
         }
     }
     I4 tot;
-    I4 mc = i4_max(block_excl_max4(e, &tot), agg[blockIdx.x]);
+    I4 mc = i4_max(block_excl_max4(e, &tot), agg[tile]);
     int np = 0, nb = 0;
     if (live && !cl) {
         const bool by_beta = d.beta[j] == i;                  // beta_j = low(j): Thm. P.5
@@ -405,9 +426,11 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, in
     if (count_beta) {
         int32_t tnb;
         block_excl_sum32(nb, &tnb);
-        if (threadIdx.x == 0) stat_add(d, S_BETAPIV, (unsigned long long)tnb, blockIdx.x);
+        if (threadIdx.x == 0) stat_add(d, S_BETAPIV, (unsigned long long)tnb, (unsigned)tile);
     }
-    if (threadIdx.x == 0) stat_add(d, S_NEWPIV, (unsigned long long)tnp, blockIdx.x);
+    if (threadIdx.x == 0) stat_add(d, S_NEWPIV, (unsigned long long)tnp, (unsigned)tile);
+    __syncthreads();
+    }
 }
 
 // Sorted symmetric difference of two ascending row lists (F2 column
@@ -444,16 +467,20 @@ __device__ inline int32_t merge_add(const int32_t *__restrict__ x, int32_t nx, c
 // column: most columns are a few entries long).  A column that may keep
 // adding known pivots (chaining) and whose new low has one is queued for
 // k_chain.
-__global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32_t nA, uint32_t round, int variant,
-                                                int compression, int chain, int tail)
+__global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int variant, int compression, int chain,
+                                                int tail)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t q = tile * kBlock + threadIdx.x;
     int32_t j = -1, s = -1, tlen = 0, slen = 0;
     int64_t toff = 0, soff = 0;
     bool target = false;
     if (q < nA) {
         j = act[q];
-        if (d.state[j] == ST_ACTIVE && d.coll[q]) {
+        if (d.state[j] == ST_ACTIVE && d.coll[q] == 1) {
             const int32_t i = d.low[j];
             s = d.piv[i];
             if (s < 0 && variant == 0) {
@@ -476,7 +503,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
     const int64_t need = target ? (int64_t)tlen + slen : 0;
     const int64_t excl = block_excl_sum64(need);
     const int64_t btot = block_sum64(need);
-    if (threadIdx.x == 0) s_base = btot ? arena_alloc(d, blockIdx.x, btot) : 0;
+    if (threadIdx.x == 0) s_base = btot ? arena_alloc(d, (unsigned)tile, btot) : 0;
     __syncthreads();
     const int64_t bbase = s_base;
     if (target && bbase < 0) {
@@ -508,7 +535,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
     __shared__ int32_t s_q;
     int32_t npush;
     const int32_t qpos = block_excl_sum32(push ? 1 : 0, &npush);
-    const unsigned qp = blockIdx.x & (kPart - 1);
+    const unsigned qp = (unsigned)tile & (kPart - 1);
     if (threadIdx.x == 0) s_q = npush ? atomicAdd(&d.cq_n[qp * 32], npush) : 0;
     __syncthreads();
     if (push) d.cq[(int64_t)qp * d.cq_slice + s_q + qpos] = j;
@@ -516,9 +543,11 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int32
     const int64_t bxe = block_sum64(xe);
     const int64_t bby = block_sum64(by);
     if (threadIdx.x == 0) {
-        stat_add(d, S_XBYTES, (unsigned long long)bby, blockIdx.x);
-        stat_add(d, S_ADDS, (unsigned long long)badds, blockIdx.x);
-        stat_add(d, S_XE, (unsigned long long)bxe, blockIdx.x);
+        stat_add(d, S_XBYTES, (unsigned long long)bby, (unsigned)tile);
+        stat_add(d, S_ADDS, (unsigned long long)badds, (unsigned)tile);
+        stat_add(d, S_XE, (unsigned long long)bxe, (unsigned)tile);
+    }
+    __syncthreads();
     }
 }
 
@@ -1324,20 +1353,28 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
 }
 
 // Per-tile count of the positions that stay active.
-__global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act, int32_t nA, int32_t *keep_cnt)
+__global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act, int32_t *keep_cnt)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int keep = (q < nA && d.state[act[q]] == ST_ACTIVE) ? 1 : 0;
-    int32_t tk;
-    block_excl_sum32(keep, &tk);
-    if (threadIdx.x == 0) keep_cnt[blockIdx.x] = tk;
+    const int32_t nA = d.cnt->n_cur;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t q = tile * kBlock + threadIdx.x;
+        const int keep = (q < nA && d.state[act[q]] == ST_ACTIVE) ? 1 : 0;
+        int32_t tk;
+        block_excl_sum32(keep, &tk);
+        if (threadIdx.x == 0) keep_cnt[tile] = tk;
+        __syncthreads();
+    }
 }
 
 // Stable compaction of the active list; finalises cleared columns.
-__global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, int32_t nA, const int32_t *keep_off,
+__global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, const int32_t *keep_off,
                                                     int32_t *act_next)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t nA = d.cnt->n_cur;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t q = tile * kBlock + threadIdx.x;
     int keep = 0;
     int32_t j = -1;
     if (q < nA) {
@@ -1352,7 +1389,23 @@ __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, i
     }
     int32_t tot;
     const int32_t pos = block_excl_sum32(keep, &tot);
-    if (keep) act_next[keep_off[blockIdx.x] + pos] = j;
+    if (keep) act_next[keep_off[tile] + pos] = j;
+    __syncthreads();
+    }
+}
+
+__global__ void k_round_init(Dev d, int32_t m)
+{
+    d.cnt->n_cur = m;
+    d.cnt->round = 0;
+}
+
+// End of a round: the compacted list is the next round's; a round that did
+// work advances the round number (the T table's stamp).
+__global__ void k_round_end(Dev d)
+{
+    if (d.cnt->n_cur > 0) d.cnt->round = d.cnt->round + 1;
+    d.cnt->n_cur = d.cnt->n_next;
 }
 
 // Arena regrowth: copy every live arena column into a new arena.
@@ -1644,6 +1697,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // col_ptr, len, rows, left, beta out, neg bits
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
     PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act0, m);
+    PMS_LAUNCH(c, K_FILL, 0, k_round_init, 1, 1, d, (int32_t)m);
     PMS_HIP(hipGetLastError());
 
     Counters *h = (Counters *)c->host_pinned;
@@ -1660,6 +1714,106 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     unsigned long long tprev[S_NUM] = {};
     int32_t nA_prev = 0;
     int32_t *act = act0, *act_next = act1;
+    // One round (Phase I, Phase II, compaction) on the list `a` into `an`.
+    // The kernels read the round's active count and number from the device
+    // (they loop over tiles), so `grid_tiles` only bounds their grids: the
+    // exact tile count when the host knows it, a fixed size in a graph.
+    size_t xor_slot = 0, lane_slot = 0, chain_slot = 0;
+    auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
+        const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
+        const unsigned gA = grid_for(grid_tiles * kBlock, kBlock, 65536);
+        const double dt = (double)grid_tiles;
+        // act, len, off, last row, low out, T atomic
+        PMS_LAUNCH(c, K_LOW, 32 * dA, k_low, gA, kBlock, d, a);
+        // act, state, low, T, piv, coll out, dim; block aggregates
+        PMS_LAUNCH(c, K_COLLIDE, 23 * dA + 16 * dt, k_collide, gT, kBlock, d, a, agg);
+        PMS_LAUNCH(c, K_SCAN, 32 * dt, k_scan_max4, 1, kScanThreads, agg, &d.cnt->n_cur);
+        // act, state, low, coll, dim, beta; aggregates
+        PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, gT, kBlock, d, a, agg, opt->compression);
+        PMS_LAUNCH(c, K_XOR, -1.0, k_xor, gT, kBlock, d, a, opt->variant, opt->compression, opt->chain,
+                   opt->tail_active);
+        xor_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
+        lane_slot = c->pend.size() - 1;
+        if (trace)
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+        else
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+        chain_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep);
+        PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
+        // act, state, act_next
+        PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an);
+        if (c->prof_on || trace) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+        PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, 1, d);
+        return PMS_OK;
+    };
+
+    // Graph mode: `graph_rounds` rounds (rounded up to even, so the active
+    // list ends where it started) captured once into a HIP graph and
+    // replayed, one host synchronisation per replay; rounds after
+    // convergence find no active column and return at once.
+    const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && opt->max_rounds == 0)
+                            ? (opt->graph_rounds + 1) & ~1 : 0;
+    if (graph_k > 0) {
+        const int64_t gtiles = std::min<int64_t>((m + kBlock - 1) / kBlock, 16384);
+        if (!c->graph_stream) PMS_HIP(hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
+        if (!c->graph_ev) PMS_HIP(hipEventCreateWithFlags(&c->graph_ev, hipEventDisableTiming));
+        hipStream_t gs = c->graph_stream;
+        // the graph runs after everything issued on the caller's stream so far
+        PMS_HIP(hipEventRecord(c->graph_ev, st));
+        PMS_HIP(hipStreamWaitEvent(gs, c->graph_ev, 0));
+        hipGraphExec_t exec = nullptr;
+        auto capture = [&]() -> pms_status {
+            hipGraph_t graph = nullptr;
+            PMS_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            c->stream = gs;  // PMS_LAUNCH issues on c->stream
+            pms_status sr = PMS_OK;
+            for (int r = 0; r < graph_k && sr == PMS_OK; r++)
+                sr = (r & 1) ? launch_round(act1, act0, gtiles, 0.0) : launch_round(act0, act1, gtiles, 0.0);
+            c->stream = st;
+            const hipError_t ec = hipStreamEndCapture(gs, &graph);
+            if (sr != PMS_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return sr;
+            }
+            PMS_HIP(ec);
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            PMS_HIP(ei);
+            return PMS_OK;
+        };
+        pms_status sg = capture();
+        if (sg != PMS_OK) return sg;
+        for (;;) {
+            hipError_t e = hipGraphLaunch(exec, gs);
+            if (e == hipSuccess) e = hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, gs);
+            if (e == hipSuccess) e = hipStreamSynchronize(gs);
+            if (e != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
+            }
+            round = h->round;
+            if (h->bad_source) {
+                (void)hipGraphExecDestroy(exec);
+                return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
+            }
+            if (h->overflow) {  // the arena moves: grow it (on the caller's stream) and capture again
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+                pms_status s = grow_arena(c, d, h);
+                if (s != PMS_OK) return s;
+                PMS_HIP(hipEventRecord(c->graph_ev, st));
+                PMS_HIP(hipStreamWaitEvent(gs, c->graph_ev, 0));
+                s = capture();
+                if (s != PMS_OK) return s;
+                continue;
+            }
+            if (h->n_cur == 0) break;
+        }
+        (void)hipGraphExecDestroy(exec);
+        nA = 0;
+    }
     while (nA > 0) {
         if (opt->max_rounds > 0 && (int32_t)round >= opt->max_rounds) {
             res->rounds = (int32_t)round;
@@ -1667,31 +1821,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         }
         nA_prev = nA;
         const int64_t tiles = (nA + kBlock - 1) / kBlock;
-        const unsigned gA = grid_for(nA, kBlock, 65536);
-        const double dA = (double)nA, dt = (double)tiles;
-        // act, len, off, last row, low out, T atomic
-        PMS_LAUNCH(c, K_LOW, 32 * dA, k_low, gA, kBlock, d, act, nA, round);
-        // act, state, low, T, piv, coll out, dim; block aggregates
-        PMS_LAUNCH(c, K_COLLIDE, 23 * dA + 16 * dt, k_collide, (unsigned)tiles, kBlock, d, act, nA, round, agg);
-        PMS_LAUNCH(c, K_SCAN, 32 * dt, k_scan_max4, 1, kScanThreads, agg, tiles);
-        // act, state, low, coll, dim, beta; aggregates
-        PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, (unsigned)tiles, kBlock, d, act, nA, agg,
-                   opt->compression, round == 0);
-        PMS_LAUNCH(c, K_XOR, -1.0, k_xor, (unsigned)tiles, kBlock, d, act, nA, round, opt->variant,
-                   opt->compression, opt->chain, opt->tail_active);
-        const size_t xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
-        const size_t lane_slot = c->pend.size() - 1;
-        if (trace)
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
-        else
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
-        const size_t chain_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, (unsigned)tiles, kBlock, d, act, nA, keep);
-        PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, tiles, &d.cnt->n_next);
-        // act, state, act_next
-        PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, (unsigned)tiles, kBlock, d, act, nA, keep, act_next);
-        if (c->prof_on || trace) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+        pms_status sr = launch_round(act, act_next, tiles, (double)nA);
+        if (sr != PMS_OK) return sr;
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
         PMS_HIP(hipStreamSynchronize(st));
@@ -1742,8 +1873,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // pairs and essential simplices, canonical order
     int32_t *cp = keep, *ce = keep2;
     PMS_LAUNCH(c, K_FINAL, 8 * dm, k_fin_count, (unsigned)nblk, kBlock, d, cp, ce);
-    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, cp, nblk, &d.cnt->n_pairs);
-    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, ce, nblk, &d.cnt->n_ess);
+    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, cp, nblk, nullptr, &d.cnt->n_pairs);
+    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, ce, nblk, nullptr, &d.cnt->n_ess);
     PMS_HIP(hipGetLastError());
     PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     PMS_HIP(hipStreamSynchronize(st));
@@ -1826,6 +1957,8 @@ pms_options pms_default_options(void)
     o.chain = 1;
     o.tail_active = 1024;
     o.validate = 1;
+    o.graph_rounds = 0;
+    o.reserved = 0;
     o.arena_entries = 0;
     return o;
 }
@@ -1860,6 +1993,8 @@ void pms_destroy(pms_ctx *c)
         if (b.p) (void)hipFree(b.p);
     if (c->arena) (void)hipFree(c->arena);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->graph_ev) (void)hipEventDestroy(c->graph_ev);
+    if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
     delete c;
 }
 
@@ -1929,7 +2064,8 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
     if (bnd->m > 0 && (!bnd->col_ptr || !bnd->rows || !res->low_star))
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "null col_ptr / rows / low_star");
     pms_options o = opt ? *opt : pms_default_options();
-    if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0)
+    if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0 || o.graph_rounds < 0 ||
+        o.graph_rounds > 1024)
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
     pms_status s = pms::reduce_impl(c, bnd, &o, res);

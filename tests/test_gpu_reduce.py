@@ -157,3 +157,45 @@ def test_arena_regrowth(gpu):
     _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=1024), ref)
     # the next call on the same context starts from a normal arena again
     _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
+
+
+# ---------------------------------------------------------------- graph mode
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_graph_rounds_parity(gpu, k):
+    """Rounds replayed as a captured HIP graph give the oracle's low* and the
+    same number of rounds as one round at a time (graph_rounds rounds per
+    host synchronisation; the rounds after convergence do nothing)."""
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    # same arena for both (an arena overflow redoes a round's dropped additions
+    # one round later, so the round count depends on the arena's size)
+    big = 1 << 24
+    eager = _reduce(f.col_ptr, f.rows, f.dim, gpu, chain=False, arena_entries=big)
+    res = _reduce(f.col_ptr, f.rows, f.dim, gpu, chain=False, graph_rounds=k, arena_entries=big)
+    _check(res, ref)
+    assert res.rounds == eager.rounds
+    assert res.additions == eager.additions
+    # the default path (chaining) and a replay longer than the whole reduction
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, graph_rounds=64), ref)
+
+
+def test_graph_rounds_fuzz_and_lowerstar(gpu):
+    rng = np.random.default_rng(77)
+    for t in range(40):
+        cp, rows, dim, _, _ = brute.random_filtration(rng, n_vertices=int(rng.integers(2, 9)),
+                                                      n_facets=int(rng.integers(1, 9)),
+                                                      max_dim=int(rng.integers(1, 4)))
+        ref = oracle.reduce_standard(cp, rows)
+        _check(_reduce(cp, rows, dim, gpu, graph_rounds=1 + t % 4), ref)
+    g = synth.random_grid(81, (9, 10, 11))
+    f = oracle.build_lowerstar(g)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, graph_rounds=4), oracle.reduce_twist(f.col_ptr, f.rows, f.dim))
+
+
+def test_graph_rounds_arena_regrowth(gpu):
+    """An arena overflow inside a replay: the arena grows, the graph is
+    captured again and the result is unchanged."""
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2)
+    ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=1024, graph_rounds=4), ref)
+    _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
