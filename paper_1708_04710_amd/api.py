@@ -138,8 +138,12 @@ class Filtration:
         return out
 
     def __del__(self):
-        if self.handle and B._lib is not None:
-            B._lib.pms_filtration_free(self.handle)
+        try:
+            lib = B._lib
+        except AttributeError:  # interpreter shutdown: the module is gone
+            return
+        if self.handle and lib is not None:
+            lib.pms_filtration_free(self.handle)
             self.handle = ctypes.c_void_p()
 
 
