@@ -624,7 +624,7 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // pivot or chain longer than kLaneSteps go on to the wavefront kernel.
 constexpr int kLaneThreads = 128;
 constexpr int kLaneCap = 48;
-constexpr int kLaneP = 8;
+constexpr int kLaneP = 16;
 constexpr unsigned kLaneBlocks = 1536;
 // A lane hands a longer chain to a wavefront, whose steps are faster: with
 // many queued columns lanes keep chains longer (throughput), with few the
@@ -634,6 +634,7 @@ constexpr int kLaneStepsFew = 32;
 constexpr int32_t kLaneMany = 65536;  // queued columns from which a round counts as throughput-bound
 constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
 constexpr int kLaneRefill = 16;    // free lanes that trigger a wave's write-back and refill
+constexpr int kLaneFlushBatch = 8; // lanes with a full P that trigger a wave's merge phase
 
 __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace)
 {
@@ -731,6 +732,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         np = 0;
     };
     bool fin = true, bail = false;  // fin: no column in progress (finished, or never given one)
+    bool wantf = false;             // P is full: this lane waits for a merge phase
     for (;;) {
         // finished lanes are written back and refilled together, once at
         // least kLaneRefill of them (or every lane) are waiting: the wave-wide
@@ -837,6 +839,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
 #pragma unroll
                 for (int u = 0; u < kLaneP; u++) p[u] = -1;
                 dirty = false;
+                wantf = false;
                 steps = 0;
                 if (L > kLaneCap) {
                     bail = true;  // too long for a lane: straight to the wavefront kernel
@@ -858,8 +861,20 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 }
             }
         }
+        // lanes whose P is full are merged together, once enough of them
+        // wait (the merge loop's trip count varies from lane to lane)
+        {
+            const uint64_t busy = __ballot(!fin);
+            const uint64_t nf = __ballot(!fin && wantf);
+            if (nf && (__popcll(nf) >= kLaneFlushBatch || nf == busy)) {
+                if (wantf) {
+                    flush();
+                    wantf = false;
+                }
+            }
+        }
         // one step for every lane with a column in progress
-        if (!fin) {
+        if (!fin && !wantf) {
             if (i < 0) {
                 fin = true;  // W is zero
             } else if (lk.s < 0) {
@@ -884,8 +899,9 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 if (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > kLaneCap)) {
                     bail = true;
                     fin = true;
+                } else if (np + kk > kLaneP) {
+                    wantf = true;  // P is full: wait for the wave's next merge phase
                 } else {
-                    if (np + kk > kLaneP) flush();
                     steps++;
                     adds++;
                     xe += (int64_t)LB + np + kk + 1;
@@ -1756,15 +1772,36 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && opt->max_rounds == 0)
                             ? (opt->graph_rounds + 1) & ~1 : 0;
     if (graph_k > 0) {
-        const int64_t gtiles = std::min<int64_t>((m + kBlock - 1) / kBlock, 16384);
+        // fixed grids: enough blocks to fill the device, looping over tiles
+        const int64_t gtiles = std::min<int64_t>((m + kBlock - 1) / kBlock, 2048);
         if (!c->graph_stream) PMS_HIP(hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
         if (!c->graph_ev) PMS_HIP(hipEventCreateWithFlags(&c->graph_ev, hipEventDisableTiming));
         hipStream_t gs = c->graph_stream;
         // the graph runs after everything issued on the caller's stream so far
         PMS_HIP(hipEventRecord(c->graph_ev, st));
         PMS_HIP(hipStreamWaitEvent(gs, c->graph_ev, 0));
-        hipGraphExec_t exec = nullptr;
+        // everything the captured launches depend on
+        auto make_key = [&]() {
+            std::vector<unsigned char> k(sizeof(Dev) + sizeof(pms_options) + 5 * sizeof(void *) + 2 * sizeof(int64_t));
+            unsigned char *p = k.data();
+            memcpy(p, &d, sizeof(Dev));
+            p += sizeof(Dev);
+            pms_options o2 = *opt;
+            memcpy(p, &o2, sizeof(o2));
+            p += sizeof(o2);
+            const void *ptrs[5] = {act0, act1, agg, keep, (const void *)(intptr_t)graph_k};
+            memcpy(p, ptrs, sizeof(ptrs));
+            p += sizeof(ptrs);
+            const int64_t sz[2] = {gtiles, m};
+            memcpy(p, sz, sizeof(sz));
+            return k;
+        };
         auto capture = [&]() -> pms_status {
+            if (c->graph_exec) {
+                (void)hipGraphExecDestroy(c->graph_exec);
+                c->graph_exec = nullptr;
+                c->graph_key.clear();
+            }
             hipGraph_t graph = nullptr;
             PMS_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
             c->stream = gs;  // PMS_LAUNCH issues on c->stream
@@ -1778,29 +1815,26 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                 return sr;
             }
             PMS_HIP(ec);
+            hipGraphExec_t exec = nullptr;
             const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             PMS_HIP(ei);
+            c->graph_exec = exec;
+            c->graph_key = make_key();
             return PMS_OK;
         };
-        pms_status sg = capture();
-        if (sg != PMS_OK) return sg;
+        if (!c->graph_exec || c->graph_key != make_key()) {
+            pms_status sg = capture();
+            if (sg != PMS_OK) return sg;
+        }
         for (;;) {
-            hipError_t e = hipGraphLaunch(exec, gs);
+            hipError_t e = hipGraphLaunch(c->graph_exec, gs);
             if (e == hipSuccess) e = hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, gs);
             if (e == hipSuccess) e = hipStreamSynchronize(gs);
-            if (e != hipSuccess) {
-                (void)hipGraphExecDestroy(exec);
-                return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
-            }
+            if (e != hipSuccess) return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
             round = h->round;
-            if (h->bad_source) {
-                (void)hipGraphExecDestroy(exec);
-                return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
-            }
+            if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
             if (h->overflow) {  // the arena moves: grow it (on the caller's stream) and capture again
-                (void)hipGraphExecDestroy(exec);
-                exec = nullptr;
                 pms_status s = grow_arena(c, d, h);
                 if (s != PMS_OK) return s;
                 PMS_HIP(hipEventRecord(c->graph_ev, st));
@@ -1811,7 +1845,6 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             }
             if (h->n_cur == 0) break;
         }
-        (void)hipGraphExecDestroy(exec);
         nA = 0;
     }
     while (nA > 0) {
@@ -1993,6 +2026,7 @@ void pms_destroy(pms_ctx *c)
         if (b.p) (void)hipFree(b.p);
     if (c->arena) (void)hipFree(c->arena);
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph_ev) (void)hipEventDestroy(c->graph_ev);
     if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
     delete c;
