@@ -19,8 +19,12 @@ the sum of squared H1 persistences), each checked on the host for its size.
 Prints one JSON line.  ``value`` is simplices reduced per second over the
 whole step.  ``roofline`` prices the step's dominant kernel (largest summed
 event time) with its algorithmic bytes per launch against the MI355X HBM
-peak.  ``cpu_baseline`` times the CPU oracle (filtration build + standard
-reduction) on the same grid.
+peak; the per-kernel times come from a second pass of the same K steps
+with a HIP event pair around every launch (the events slow the step, so
+``value`` and ``ms_per_step`` come from the first pass, without them).
+``phases`` splits the step (build, reduction alone, the rest) and prices
+the whole step's bytes against the peak.  ``cpu_baseline`` times the
+CPU oracle (filtration build + standard reduction) on the same grid.
 """
 from __future__ import annotations
 
@@ -132,8 +136,7 @@ def batched_vs_plain(api, autograd, synth, torch, dev):
     def batch4():
         pts = x.clone().requires_grad_(True)
         bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=wb)
-        h1 = dims == 1
-        ((dv[h1] - bv[h1]) ** 2).sum().backward()
+        torch.where(dims == 1, (dv - bv) ** 2, torch.zeros_like(dv)).sum().backward()
         meta["m4"] = int(bv.grad_fn.f.m)
 
     def plain4():
@@ -227,12 +230,12 @@ def rocprof_summary(tdir, fdir, wdir, out_md):
              "Commands (run from the repository root; <T>, <F>, <W> are output folders):", ""]
     lines += [f"    {c}" for c in PROFILE_CMDS]
     lines += ["", "Summarised with: python3 bench.py --rocprof-summary <T> <F> <W> <this file>",
-              "", "## Kernel time (kernel trace, 3 timed + 1 warm-up steps)", "",
+              "", "## Kernel time (kernel trace: 1 warm-up step, then 3 steps timed without and 3 with per-kernel events)", "",
               "| kernel (rocprof name, shortened) | calls | total ms | avg us |", "|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
         lines.append(f"| {r['Name'][:70]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} |")
-    lines += ["", "## HBM traffic (PMC FETCH_SIZE / WRITE_SIZE per dispatch, one step)", "",
+    lines += ["", "## HBM traffic (PMC FETCH_SIZE / WRITE_SIZE per dispatch; one step, run unprofiled)", "",
               f"Copy calibration: a {COPY_BYTES >> 20} MiB device copy reads FETCH_SIZE = {f_kib:.0f} KiB and "
               f"WRITE_SIZE = {w_kib:.0f} KiB (expected {COPY_BYTES >> 10} KiB each): scales "
               f"fetch x{f_scale:.3f}, write x{w_scale:.3f}.", "",
@@ -290,8 +293,9 @@ def main():
     def step():
         x = grid.clone().requires_grad_(True)
         bv, dv, dims = autograd.persistence_lowerstar(x, workspace=f)
-        h1 = dims == 1
-        loss = (dv[h1] - bv[h1]).sum()
+        # total H1 persistence; a masked sum (boolean indexing would make the
+        # host wait for the device to learn the mask's size)
+        loss = torch.where(dims == 1, dv - bv, torch.zeros_like(dv)).sum()
         loss.backward()
         state["x"] = x
         state["fn"] = (bv, dv, dims)
@@ -299,19 +303,27 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    if not args.no_profile:
-        api.profile_enable(True, dev)
+    # the timed region: K steps, no per-kernel events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = api.profile_read(dev) if not args.no_profile else {}
-    if not args.no_profile:
-        api.profile_enable(False, dev)
     ms = (t1 - t0) * 1000.0 / args.steps
+    # the same K steps again with a HIP event pair around every kernel launch
+    # (per-kernel times for the roofline; the events slow the step down)
+    prof, prof_ms = {}, None
+    if not args.no_profile:
+        api.profile_enable(True, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        prof = api.profile_read(dev)
+        api.profile_enable(False, dev)
     bv, dv, dims = state["fn"]
     res = bv.grad_fn.result if hasattr(bv.grad_fn, "result") else None
     m = f.m
@@ -320,6 +332,27 @@ def main():
     # persistence is a signed count of deaths minus births per vertex
     assert g is not None and torch.equal(g, g.round())
     n_pairs = int(bv.numel())
+
+    # phases of the step, timed apart (outside the timed region): build, and
+    # the reduction alone on the built filtration (the survey's t_reduce)
+    def _med(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        ts.sort()
+        return ts[len(ts) // 2] * 1000.0
+
+    build_ms = _med(lambda: api.build_lowerstar(grid, out=f))
+    reduce_ms = _med(lambda: api.reduce_filtration(f))
+    phases = {"profiled_ms_per_step": round(prof_ms, 4) if prof_ms else None,
+              "build_ms": round(build_ms, 3), "reduce_ms": round(reduce_ms, 3),
+              "pairs_gather_backward_ms": round(max(ms - build_ms - reduce_ms, 0.0), 3),
+              "reduce_only_simplices_per_s": m / (reduce_ms / 1000.0)}
 
     roof = None
     kernels = {}
@@ -335,6 +368,23 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
                 "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": by / n}
+        # the whole step's HBM traffic (rocprof FETCH+WRITE per kernel launch,
+        # when the counters match these kernels) and algorithmic bytes
+        alg = sum(v[2] for v in prof.values()) / args.steps
+        meas, missing = 0.0, []
+        for name, (_, nl, _) in prof.items():
+            b = measured_traffic(name)
+            if b is None:
+                missing.append(name)
+            else:
+                meas += b * nl / args.steps
+        phases["step_algorithmic_bytes"] = alg
+        phases["step_algorithmic_frac_of_hbm_peak"] = round(alg / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)
+        if not missing:
+            phases["step_measured_hbm_bytes"] = meas
+            phases["step_measured_frac_of_hbm_peak"] = round(meas / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)
+        else:
+            phases["step_measured_hbm_bytes"] = None  # kernels changed since the counters were taken
 
     out = {
         "metric": METRIC,
@@ -356,6 +406,7 @@ def main():
                    "rounds": res.rounds if res else None, "additions": res.additions if res else None,
                    "n_pairs": n_pairs, "n_essential": int(res.essential.numel()) if res else None},
         "roofline": roof,
+        "phases": phases,
         "kernels": kernels,
         "cpu_baseline": None,
     }
