@@ -210,3 +210,24 @@ def test_reduce_batched_rejects_bad_offsets(gpu):
         with pytest.raises(_binding.PmsError) as e:
             api.reduce_batched(f, bad)
         assert e.value.status == _binding.PMS_ERR_INVALID_ARG
+
+
+def test_vr_circles64_batch_sampled(gpu):
+    """The 64-cloud x 128-point FP32 batch (full 2-skeleton) at full size:
+    built and reduced on the device in one go; three clouds' pairs and
+    essential simplices checked against the oracle run on each alone."""
+    x = synth.circle_batch()
+    f, off = api.build_vr([torch.as_tensor(c, device=gpu) for c in x], [-1.0] * len(x), 2)
+    res = api.reduce_batched(f, off)
+    poff = res.inst_pair_off.cpu().numpy()
+    eoff = res.inst_ess_off.cpu().numpy()
+    pb, pd = res.pair_birth.cpu().numpy(), res.pair_death.cpu().numpy()
+    ess = res.essential.cpu().numpy()
+    for b in (0, 29, len(x) - 1):
+        ref = oracle.build_vr_f32(x[b], -1.0, 2)
+        assert off[b + 1] - off[b] == ref.m
+        low = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        rb, rd = oracle.pairs(low)
+        sl = slice(poff[b], poff[b + 1])
+        assert np.array_equal(pb[sl] - off[b], rb) and np.array_equal(pd[sl] - off[b], rd), b
+        assert np.array_equal(ess[eoff[b]:eoff[b + 1]] - off[b], oracle.essential(low)), b
