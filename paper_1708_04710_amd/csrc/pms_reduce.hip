@@ -463,6 +463,63 @@ __device__ inline int32_t merge_add(const int32_t *__restrict__ x, int32_t nx, c
     return k;
 }
 
+// The same symmetric difference for one lane with long inputs in global
+// memory: both lists are read in blocks of kMB entries held in registers
+// (a block's loads are independent, so one memory latency per block rather
+// than per entry), the negative-row bits of a block fetched with it; the
+// head of each list is element 0 of its block, consumed by shifting.
+constexpr int kMB = 4;
+__device__ inline int32_t merge_add_stream(const int32_t *__restrict__ x, int32_t nx, const int32_t *__restrict__ y,
+                                           int32_t ny, int32_t *__restrict__ out, const uint32_t *neg, int compression)
+{
+    constexpr int32_t kEnd = 0x7FFFFFFF;
+    int32_t xb[kMB], yb[kMB], xn[kMB], yn[kMB];
+    auto load = [&](const int32_t *a, int32_t n, int32_t pos, int32_t *b, int32_t *nb) {
+#pragma unroll
+        for (int u = 0; u < kMB; u++) b[u] = pos + u < n ? a[pos + u] : kEnd;
+#pragma unroll
+        for (int u = 0; u < kMB; u++) nb[u] = (compression && b[u] != kEnd) ? (int32_t)((neg[b[u] >> 5] >> (b[u] & 31)) & 1u) : 0;
+    };
+    load(x, nx, 0, xb, xn);
+    load(y, ny, 0, yb, yn);
+    int32_t xp = kMB, yp = kMB, k = 0;
+    while (xb[0] != kEnd || yb[0] != kEnd) {
+        const int32_t u = xb[0], v = yb[0];
+        if (u < v) {
+            if (!xn[0]) out[k++] = u;
+        } else if (v < u) {
+            if (!yn[0]) out[k++] = v;
+        }  // equal: 1 + 1 = 0
+        if (u <= v) {
+#pragma unroll
+            for (int t = 0; t < kMB - 1; t++) {
+                xb[t] = xb[t + 1];
+                xn[t] = xn[t + 1];
+            }
+            xb[kMB - 1] = kEnd;
+            xn[kMB - 1] = 0;
+            if (xb[0] == kEnd && xp < nx) {
+                load(x, nx, xp, xb, xn);
+                xp += kMB;
+            }
+        }
+        if (v <= u) {
+#pragma unroll
+            for (int t = 0; t < kMB - 1; t++) {
+                yb[t] = yb[t + 1];
+                yn[t] = yn[t + 1];
+            }
+            yb[kMB - 1] = kEnd;
+            yn[kMB - 1] = 0;
+            if (yb[0] == kEnd && yp < ny) {
+                load(y, ny, yp, yb, yn);
+                yp += kMB;
+            }
+        }
+    }
+    return k;
+}
+
 // Phase II, first addition of every colliding column (one lane per
 // column: most columns are a few entries long).  A column that may keep
 // adding known pivots (chaining) and whose new low has one is queued for
@@ -515,7 +572,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     if (target) {
         const int64_t dst = bbase + excl;
         int32_t *out = d.arena + dst;
-        const int32_t k = merge_add(col_base(d, toff), tlen, col_base(d, soff), slen, out, d.neg, compression);
+        const int32_t k = merge_add_stream(col_base(d, toff), tlen, col_base(d, soff), slen, out, d.neg, compression);
         adds = 1;
         xe = (int64_t)tlen + slen;
         by += 42 + 4 * ((int64_t)tlen + slen + k) + 16;  // headers, low, piv/T, beta, dim; data in and out
