@@ -57,6 +57,10 @@ struct Ctx {
     // (the caller's may be the legacy default stream, which cannot capture)
     hipStream_t graph_stream = nullptr;
     hipEvent_t graph_ev = nullptr;
+    // the last captured round graph, reused while its key (the device
+    // arguments and options it was captured with) is unchanged
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
 };
 
 enum BufId {
