@@ -687,7 +687,7 @@ constexpr unsigned kLaneBlocks = 1536;
 // many queued columns lanes keep chains longer (throughput), with few the
 // long chains move on early (they are the critical path).
 constexpr int kLaneSteps = 128;
-constexpr int kLaneStepsFew = 32;
+constexpr int kLaneStepsFew = 8;
 constexpr int32_t kLaneMany = 65536;  // queued columns from which a round counts as throughput-bound
 constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
 constexpr int kLaneRefill = 16;    // free lanes that trigger a wave's write-back and refill
