@@ -16,6 +16,11 @@ per cloud on the same GPU ("batched" field): 512 clouds of 32..256 points
 (reduction only) and 64 FP32 clouds of 128 points (reduction + backward of
 the sum of squared H1 persistences), each checked on the host for its size.
 
+Before the warm-up steps, the chaining kernels' launch shapes and the
+graph-mode round count are autotuned on each workload's own filtration
+(``paper_1708_04710_amd.autotune``; outside every timed region), or read
+from ``--tune-cache`` when it holds the workload's size class.
+
 Prints one JSON line.  ``value`` is simplices reduced per second over the
 whole step.  ``roofline`` prices the step's dominant kernel (largest summed
 event time) with its algorithmic bytes per launch against the MI355X HBM
@@ -106,8 +111,20 @@ def _timed(fn, torch, reps=3):
     return min(ts)
 
 
-def batched_vs_plain(api, autograd, synth, torch, dev):
-    """Batched pms (+ backward) vs one plain pms call per cloud, same GPU."""
+def _tune(tune, f, count=1):
+    """Autotune (or read from the cache) the shapes for filtration f; returns
+    the reduce keywords and the record (None: the built-in shapes)."""
+    if tune is False:
+        return {}, None
+    from paper_1708_04710_amd import autotune
+    rec = autotune.autotune(f, count=count, cache=tune, reps=3)
+    return {"graph_rounds": rec["graph_rounds"]}, {k: rec[k] for k in ("tuning", "graph_rounds", "ms", "cached")}
+
+
+def batched_vs_plain(api, autograd, synth, torch, dev, tune):
+    """Batched pms (+ backward) vs one plain pms call per cloud, same GPU.
+    Each side runs with the shapes tuned for it (the plain side's tuned on its
+    largest cloud)."""
     out = {}
     # 512 integer clouds, own 30th-percentile thresholds (reduction only)
     inst = synth.vr_batch()
@@ -115,49 +132,68 @@ def batched_vs_plain(api, autograd, synth, torch, dev):
     thrs = [t for _, t in inst]
     meta = {}
     wb, wp = api.Filtration(dev), api.Filtration(dev)  # reused device workspaces
+    f, off = api.build_vr(clouds, thrs, 2, out=wb)
+    kw_b, rec_b = _tune(tune, f, len(clouds))
+    big = max(range(len(clouds)), key=lambda b: off[b + 1] - off[b])
+    f1, _ = api.build_vr([clouds[big]], [thrs[big]], 2, out=wp)
+    kw_p, rec_p = _tune(tune, f1)
 
     def batch3():
         f, off = api.build_vr(clouds, thrs, 2, out=wb)
-        r = api.reduce_filtration(f)
+        r = api.reduce_filtration(f, **kw_b)
         meta["m"], meta["rounds"], meta["adds"] = f.m, r.rounds, r.additions
 
     def plain3():
         for c, t in zip(clouds, thrs):
             f, _ = api.build_vr([c], [t], 2, out=wp)
-            api.reduce_filtration(f)
+            api.reduce_filtration(f, **kw_p)
 
-    tb, tp = _timed(batch3, torch), _timed(plain3, torch, reps=1)
+    _tune(tune, f, len(clouds))
+    tb = _timed(batch3, torch)
+    _tune(tune, f1)
+    tp = _timed(plain3, torch, reps=1)
     out["vr512"] = {"clouds": len(clouds), "m": meta["m"], "rounds": meta["rounds"], "additions": meta["adds"],
                     "batched_s": round(tb, 5), "plain_s": round(tp, 5), "speedup": round(tp / tb, 3),
-                    "batched_simplices_per_s": meta["m"] / tb}
+                    "batched_simplices_per_s": meta["m"] / tb, "tuning_batched": rec_b, "tuning_plain": rec_p}
     # 64 FP32 circles x 128 points, full 2-skeleton: batched reduce + backward vs plain reduce
     x = torch.as_tensor(synth.circle_batch(), device=dev)
+    f, _ = api.build_vr(list(x.unbind(0)), None, 2, out=wb)
+    kw_b, rec_b = _tune(tune, f, x.shape[0])
+    f1, _ = api.build_vr([x[0]], None, 2, out=wp)
+    kw_p, rec_p = _tune(tune, f1)
 
     def batch4():
         pts = x.clone().requires_grad_(True)
-        bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=wb)
+        bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=wb, **kw_b)
         torch.where(dims == 1, (dv - bv) ** 2, torch.zeros_like(dv)).sum().backward()
         meta["m4"] = int(bv.grad_fn.f.m)
 
     def plain4():
         for c in range(x.shape[0]):
             f, _ = api.build_vr([x[c]], None, 2, out=wp)
-            api.reduce_filtration(f)
+            api.reduce_filtration(f, **kw_p)
 
-    tb, tp = _timed(batch4, torch), _timed(plain4, torch, reps=1)
+    _tune(tune, f, x.shape[0])
+    tb = _timed(batch4, torch)
+    _tune(tune, f1)
+    tp = _timed(plain4, torch, reps=1)
     out["circles64"] = {"clouds": int(x.shape[0]), "m": meta["m4"], "batched_with_backward_s": round(tb, 5),
                         "plain_reduce_only_s": round(tp, 5), "speedup": round(tp / tb, 3),
-                        "batched_simplices_per_s": meta["m4"] / tb}
+                        "batched_simplices_per_s": meta["m4"] / tb, "tuning_batched": rec_b,
+                        "tuning_plain": rec_p}
     return out
 
 
+# the bench run autotunes and stores the shapes in <C>; the profiled runs
+# read them from there (no candidate timings in the traces)
 PROFILE_CMDS = [
+    "python3 bench.py --steps 10 --warmup 2 --tune-cache <C>",
     "rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o ls64 -- python3 bench.py --steps 3 "
-    "--warmup 1 --no-cpu-baseline --no-batched --calibrate-copy",
+    "--warmup 1 --no-cpu-baseline --no-batched --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o f -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy",
+    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o w -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy",
+    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy --tune-cache <C>",
 ]
 COPY_BYTES = 256 << 20
 
@@ -227,7 +263,7 @@ def rocprof_summary(tdir, fdir, wdir, out_md):
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(tj, fh, indent=1, sort_keys=True)
     lines = ["# rocprofv3 summary: 64^3 lower-star step (build + pms reduce + pairs + backward)", "",
-             "Commands (run from the repository root; <T>, <F>, <W> are output folders):", ""]
+             "Commands (run from the repository root; <T>, <F>, <W> are output folders, <C> the tuning cache the first writes):", ""]
     lines += [f"    {c}" for c in PROFILE_CMDS]
     lines += ["", "Summarised with: python3 bench.py --rocprof-summary <T> <F> <W> <this file>",
               "", "## Kernel time (kernel trace: 1 warm-up step, then 3 steps timed without and 3 with per-kernel events)", "",
@@ -263,6 +299,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-kernel events")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuned shapes by size class (read, and written on a miss)")
+    ap.add_argument("--no-autotune", action="store_true", help="run with the library's built-in shapes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to scale rocprof's FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -287,12 +326,14 @@ def main():
     grid_np = synth.gaussian_field(seed=5, n=64, sigma=4.0)
     grid = torch.as_tensor(grid_np, device=dev)
     f = api.build_lowerstar(grid)
+    tune = False if args.no_autotune else args.tune_cache
+    rkw, tune_rec = _tune(tune, f)
 
     state = {}
 
     def step():
         x = grid.clone().requires_grad_(True)
-        bv, dv, dims = autograd.persistence_lowerstar(x, workspace=f)
+        bv, dv, dims = autograd.persistence_lowerstar(x, workspace=f, **rkw)
         # total H1 persistence; a masked sum (boolean indexing would make the
         # host wait for the device to learn the mask's size)
         loss = torch.where(dims == 1, dv - bv, torch.zeros_like(dv)).sum()
@@ -348,7 +389,7 @@ def main():
         return ts[len(ts) // 2] * 1000.0
 
     build_ms = _med(lambda: api.build_lowerstar(grid, out=f))
-    reduce_ms = _med(lambda: api.reduce_filtration(f))
+    reduce_ms = _med(lambda: api.reduce_filtration(f, **rkw))
     phases = {"profiled_ms_per_step": round(prof_ms, 4) if prof_ms else None,
               "build_ms": round(build_ms, 3), "reduce_ms": round(reduce_ms, 3),
               "pairs_gather_backward_ms": round(max(ms - build_ms - reduce_ms, 0.0), 3),
@@ -404,14 +445,15 @@ def main():
                    "m": m, "nnz": f.nnz, "homology": "H0-H2",
                    "step": "build + reduce + pairs + gather + backward of total H1 persistence",
                    "rounds": res.rounds if res else None, "additions": res.additions if res else None,
-                   "n_pairs": n_pairs, "n_essential": int(res.essential.numel()) if res else None},
+                   "n_pairs": n_pairs, "n_essential": int(res.essential.numel()) if res else None,
+                   "tuning": tune_rec},
         "roofline": roof,
         "phases": phases,
         "kernels": kernels,
         "cpu_baseline": None,
     }
     if not args.no_batched:
-        out["batched"] = batched_vs_plain(api, autograd, synth, torch, dev)
+        out["batched"] = batched_vs_plain(api, autograd, synth, torch, dev, tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid_np, m)
     print(json.dumps(out), flush=True)

@@ -166,6 +166,50 @@ pms_status pms_reduce_batched(pms_ctx *ctx, int32_t count, const int64_t *inst_c
                               int32_t *pair_inst);
 
 /* ------------------------------------------------------------------------
+ * Tuning.  Pivot chaining (an addition to Phase II of Sec. 3.1: a column
+ * keeps adding the known pivot of its low within a round) runs in two
+ * kernels: a lane kernel, one lane per queued column, and a wavefront
+ * kernel for the columns the lanes hand on.  Their launch shapes and
+ * hand-over thresholds are a per-context pms_tuning.  Every valid setting
+ * gives the same low*, pairs and essential simplices (a reduced matrix's
+ * lows are unique, Sec. 2.3); only speed changes, and with it possibly the
+ * arena's history and so the round count.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t lane_blocks;    /* grid of the lane kernel (128-thread blocks), 1..65535 */
+    int32_t chain_blocks;   /* grid of the wavefront kernel (256-thread blocks), 1..65535 */
+    int32_t lane_steps;     /* additions a lane makes to one column before handing it to
+                               the wavefront kernel, when at least lane_many columns are
+                               queued in the round; 0..2^30 */
+    int32_t lane_steps_few; /* the same when fewer are queued; 0..2^30 */
+    int32_t lane_many;      /* queued columns from which the round uses lane_steps; >= 0 */
+    int32_t lane_refill;    /* a wave writes back and refills its lanes once this many
+                               (or all) are free; 1..64 */
+    int32_t lane_flush;     /* a wave merges its lanes' pending entries once this many
+                               (or all busy) lanes have a full pending set; 1..64 */
+    int32_t reserved;       /* 0 */
+} pms_tuning;
+
+/* The built-in setting: 1536, 512, 128, 0, 65536, 32, 16. */
+pms_tuning pms_default_tuning(void);
+/* Make *t the context's setting for later reductions (NULL = the built-in
+ * one).  PMS_ERR_INVALID_ARG, setting unchanged, when a field is out of range. */
+pms_status pms_set_tuning(pms_ctx *ctx, const pms_tuning *t);
+/* The context's current setting into *t (host). */
+pms_status pms_get_tuning(pms_ctx *ctx, pms_tuning *t);
+/* Time n candidates on one boundary matrix and keep the fastest.
+ * Candidate i is (opts[i], tunes[i]) (host arrays of n; opts NULL = the
+ * default options for all); each runs pms_reduce once untimed, then `reps`
+ * (1..64) times timed by the host clock, and scores the median.  ms[i]
+ * (host, optional) receives the scores, *best (host) the winner's index.
+ * On success the context keeps tunes[*best] and res holds the outputs of
+ * one more reduction with the winner; on failure the context's setting is
+ * unchanged and the failing call's status is returned.  The profiler, when
+ * on, adds its overhead to every candidate alike. */
+pms_status pms_autotune(pms_ctx *ctx, const pms_boundary *bnd, int32_t n, const pms_options *opts,
+                        const pms_tuning *tunes, int32_t reps, pms_result *res, double *ms, int32_t *best);
+
+/* ------------------------------------------------------------------------
  * Filtrations built on the device.  A pms_filtration is library-owned
  * device memory holding a filtration in compatible order (Sec. 2.2: the
  * simplices of each sub-complex precede the rest, faces precede cofaces),

@@ -30,7 +30,8 @@ STATUS_NAMES = {
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
-    "pms_reduce", "pms_reduce_batched", "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
+    "pms_reduce", "pms_reduce_batched", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
+    "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
 ]
@@ -47,6 +48,13 @@ class PmsOptions(ctypes.Structure):
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("arena_entries", ctypes.c_int64)]
+
+
+class PmsTuning(ctypes.Structure):
+    _fields_ = [("lane_blocks", ctypes.c_int32), ("chain_blocks", ctypes.c_int32),
+                ("lane_steps", ctypes.c_int32), ("lane_steps_few", ctypes.c_int32),
+                ("lane_many", ctypes.c_int32), ("lane_refill", ctypes.c_int32),
+                ("lane_flush", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PmsFiltrationView(ctypes.Structure):
@@ -101,6 +109,16 @@ def load(path: str = LIB_PATH):
     lib.pms_reduce_batched.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                        ctypes.POINTER(PmsResult), P, P, P]
     lib.pms_reduce_batched.restype = ctypes.c_int
+    lib.pms_default_tuning.argtypes = []
+    lib.pms_default_tuning.restype = PmsTuning
+    lib.pms_set_tuning.argtypes = [P, ctypes.POINTER(PmsTuning)]
+    lib.pms_set_tuning.restype = ctypes.c_int
+    lib.pms_get_tuning.argtypes = [P, ctypes.POINTER(PmsTuning)]
+    lib.pms_get_tuning.restype = ctypes.c_int
+    lib.pms_autotune.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.c_int32, ctypes.POINTER(PmsOptions),
+                                 ctypes.POINTER(PmsTuning), ctypes.c_int32, ctypes.POINTER(PmsResult),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.pms_autotune.restype = ctypes.c_int
     lib.pms_profile_enable.argtypes = [P, ctypes.c_int]
     lib.pms_profile_enable.restype = ctypes.c_int
     lib.pms_profile_kernels.argtypes = []

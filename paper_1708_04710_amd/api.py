@@ -212,28 +212,44 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
 
 
-def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=True, max_rounds=0,
-                 chain=True, tail_active=1024, validate=True, outputs=True, arena_entries=0,
-                 graph_rounds=0, inst_col_off=None) -> ReduceResult:
-    lib = B.load()
-    ctx = _ctx(dev)
+def _options(variant=0, compression=True, max_rounds=0, chain=True, tail_active=1024, validate=True,
+             arena_entries=0, graph_rounds=0):
+    return B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
+                        int(bool(validate)), graph_rounds, 0, arena_entries)
+
+
+def _outputs(dev, m, outputs):
+    """Output tensors and the pms_result pointing at them."""
     low_star = torch.empty(m, dtype=torch.int32, device=dev)
     cap_p = m // 2 + 1 if outputs else 0
     cap_e = m if outputs else 0
-    birth = torch.empty(cap_p, dtype=torch.int32, device=dev)
-    death = torch.empty(cap_p, dtype=torch.int32, device=dev)
-    ess = torch.empty(cap_e, dtype=torch.int32, device=dev)
-    bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
-    opt = B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
-                       int(bool(validate)), graph_rounds, 0, arena_entries)
+    t = dict(low_star=low_star, birth=torch.empty(cap_p, dtype=torch.int32, device=dev),
+             death=torch.empty(cap_p, dtype=torch.int32, device=dev),
+             ess=torch.empty(cap_e, dtype=torch.int32, device=dev))
     res = B.PmsResult()
     res.low_star = low_star.data_ptr() if m else None
     if outputs:
-        res.pair_birth = birth.data_ptr()
-        res.pair_death = death.data_ptr()
+        res.pair_birth = t["birth"].data_ptr()
+        res.pair_death = t["death"].data_ptr()
         res.cap_pairs = cap_p
-        res.essential = ess.data_ptr() if cap_e else None
+        res.essential = t["ess"].data_ptr() if cap_e else None
         res.cap_essential = cap_e
+    return res, t
+
+
+def _result(res, t, **extra) -> ReduceResult:
+    return ReduceResult(low_star=t["low_star"], pair_birth=t["birth"][:res.n_pairs],
+                        pair_death=t["death"][:res.n_pairs], essential=t["ess"][:res.n_essential],
+                        rounds=res.rounds, phase0_pivots=res.phase0_pivots, additions=res.additions,
+                        xor_entries=res.xor_entries, **extra)
+
+
+def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off=None, **kw) -> ReduceResult:
+    lib = B.load()
+    ctx = _ctx(dev)
+    bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
+    opt = _options(**kw)
+    res, t = _outputs(dev, m, outputs)
     extra = {}
     if inst_col_off is None:
         st = lib.pms_reduce(ctx, ctypes.byref(bnd), ctypes.byref(opt), ctypes.byref(res))
@@ -241,15 +257,87 @@ def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, variant=0, compression=Tru
         nb = inst_col_off.numel() - 1
         poff = torch.empty(nb + 1, dtype=torch.int64, device=dev)
         eoff = torch.empty(nb + 1, dtype=torch.int64, device=dev)
-        pinst = torch.empty(max(cap_p, 1), dtype=torch.int32, device=dev)
+        pinst = torch.empty(max(res.cap_pairs, 1), dtype=torch.int32, device=dev)
         st = lib.pms_reduce_batched(ctx, nb, inst_col_off.data_ptr(), ctypes.byref(bnd), ctypes.byref(opt),
                                     ctypes.byref(res), poff.data_ptr(), eoff.data_ptr(),
                                     pinst.data_ptr() if outputs else None)
         extra = dict(inst_pair_off=poff, inst_ess_off=eoff, pair_inst=pinst[:res.n_pairs] if outputs else None)
     B.check(ctx, st)
-    return ReduceResult(low_star=low_star, pair_birth=birth[:res.n_pairs], pair_death=death[:res.n_pairs],
-                        essential=ess[:res.n_essential], rounds=res.rounds, phase0_pivots=res.phase0_pivots,
-                        additions=res.additions, xor_entries=res.xor_entries, **extra)
+    return _result(res, t, **extra)
+
+
+# ------------------------------------------------------------------ tuning
+TUNING_FIELDS = tuple(f for f, _ in B.PmsTuning._fields_ if f != "reserved")
+
+
+def default_tuning() -> dict:
+    """The library's built-in launch shapes of the chaining kernels."""
+    t = B.load().pms_default_tuning()
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def _tuning_struct(tuning: dict | None) -> B.PmsTuning:
+    """A pms_tuning from ``tuning`` (fields it lacks take the built-in values)."""
+    unknown = set(tuning or {}) - set(TUNING_FIELDS)
+    if unknown:
+        raise KeyError(f"unknown tuning fields {sorted(unknown)}")
+    t = B.load().pms_default_tuning()
+    for k, v in (tuning or {}).items():
+        setattr(t, k, int(v))
+    return t
+
+
+def _dev(device):
+    return torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+
+
+def set_tuning(tuning: dict | None = None, device=None):
+    """Set the chaining kernels' shapes for the context of ``device`` and its
+    current stream (``pms_set_tuning``); ``None`` restores the built-in ones."""
+    dev = _dev(device)
+    ctx = _ctx(dev)
+    t = _tuning_struct(tuning)
+    B.check(ctx, B.load().pms_set_tuning(ctx, ctypes.byref(t)))
+
+
+def get_tuning(device=None) -> dict:
+    dev = _dev(device)
+    ctx = _ctx(dev)
+    t = B.PmsTuning()
+    B.check(ctx, B.load().pms_get_tuning(ctx, ctypes.byref(t)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def time_candidates(f: "Filtration", candidates, reps: int = 3, **kw):
+    """Time reductions of filtration ``f`` under each candidate
+    (``pms_autotune``).  A candidate is a dict of tuning fields plus, optionally,
+    ``graph_rounds``; ``kw`` are the other reduce options, common to all.
+    Returns (median ms per candidate, index of the fastest, ReduceResult of
+    one more run with it); the context keeps the fastest tuning."""
+    n = len(candidates)
+    if n < 1:
+        raise ValueError("no candidates")
+    kw = dict(kw)
+    outputs = kw.pop("outputs", True)
+    graph_rounds = kw.pop("graph_rounds", 0)
+    lib = B.load()
+    ctx = _ctx(f.device)
+    v = f.view
+    m = int(v.m)
+    bnd = B.PmsBoundary(m, v.col_ptr, v.rows, v.dim)
+    opts = (B.PmsOptions * n)()
+    tunes = (B.PmsTuning * n)()
+    for i, c in enumerate(candidates):
+        c = dict(c)
+        opts[i] = _options(graph_rounds=int(c.pop("graph_rounds", graph_rounds)), **kw)
+        tunes[i] = _tuning_struct(c)
+    res, t = _outputs(f.device, m, outputs)
+    ms = (ctypes.c_double * n)()
+    best = ctypes.c_int32(-1)
+    st = lib.pms_autotune(ctx, ctypes.byref(bnd), n, opts, tunes, int(reps), ctypes.byref(res), ms,
+                          ctypes.byref(best))
+    B.check(ctx, st)
+    return [ms[i] for i in range(n)], best.value, _result(res, t)
 
 
 def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None = None, **kw) -> ReduceResult:

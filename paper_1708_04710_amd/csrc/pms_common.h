@@ -37,6 +37,30 @@ struct PendingEv {
     double bytes;  // algorithmic bytes of this launch (< 0: filled in later)
 };
 
+// The chaining kernels' built-in shapes (measured on the 64^3 lower-star
+// and the batched Vietoris-Rips workloads).
+inline pms_tuning default_tuning()
+{
+    pms_tuning t;
+    t.lane_blocks = 1536;
+    t.chain_blocks = 512;  // 2 per CU
+    t.lane_steps = 128;
+    t.lane_steps_few = 0;
+    t.lane_many = 65536;
+    t.lane_refill = 32;
+    t.lane_flush = 16;
+    t.reserved = 0;
+    return t;
+}
+
+inline bool tuning_valid(const pms_tuning &t)
+{
+    return t.lane_blocks >= 1 && t.lane_blocks <= 65535 && t.chain_blocks >= 1 && t.chain_blocks <= 65535 &&
+           t.lane_steps >= 0 && t.lane_steps <= (1 << 30) && t.lane_steps_few >= 0 &&
+           t.lane_steps_few <= (1 << 30) && t.lane_many >= 0 && t.lane_refill >= 1 && t.lane_refill <= 64 &&
+           t.lane_flush >= 1 && t.lane_flush <= 64 && t.reserved == 0;
+}
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -61,6 +85,8 @@ struct Ctx {
     // arguments and options it was captured with) is unchanged
     hipGraphExec_t graph_exec = nullptr;
     std::vector<unsigned char> graph_key;
+    // launch shapes and thresholds of the chaining kernels
+    pms_tuning tune = default_tuning();
 };
 
 enum BufId {

@@ -41,6 +41,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <string>
 #include <vector>
@@ -610,7 +611,6 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
 
 // ---------------------------------------------------------------- chaining
 constexpr int kChainWaves = 4;
-constexpr unsigned kChainBlocks = 512;  // 2 per CU; waves take queue entries dynamically
 constexpr int kCapW = 1520;  // LDS entries per working buffer (two per wave); two blocks fit a CU
 constexpr int kCapS = 512;   // LDS entries for the pivot column
 
@@ -678,22 +678,18 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // writes its column back merged into the arena (from a chunk its wave
 // claimed) and takes the wave's next queued column, so short and long chains
 // share a wave without idling it.  Columns that outgrow the buffer, meet a longer
-// pivot or chain longer than kLaneSteps go on to the wavefront kernel.
+// pivot or chain longer than the step cap go on to the wavefront kernel.
 constexpr int kLaneThreads = 128;
 constexpr int kLaneCap = 48;
 constexpr int kLaneP = 16;
-constexpr unsigned kLaneBlocks = 1536;
-// A lane hands a longer chain to a wavefront, whose steps are faster: with
-// many queued columns lanes keep chains longer (throughput), with few the
-// long chains move on early (they are the critical path).
-constexpr int kLaneSteps = 128;
-constexpr int kLaneStepsFew = 8;
-constexpr int32_t kLaneMany = 65536;  // queued columns from which a round counts as throughput-bound
+// The grid, the step caps and the refill / merge thresholds come from the
+// context's pms_tuning.  A lane hands a longer chain to a wavefront, whose
+// steps are faster: with many queued columns (at least tn.lane_many) lanes
+// keep chains longer (throughput, tn.lane_steps), with few the long chains
+// move on early (they are the critical path, tn.lane_steps_few).
 constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
-constexpr int kLaneRefill = 16;    // free lanes that trigger a wave's write-back and refill
-constexpr int kLaneFlushBatch = 8; // lanes with a full P that trigger a wave's merge phase
 
-__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace)
+__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace, pms_tuning tn)
 {
     __shared__ int32_t sL[kLaneCap * kLaneThreads];
     __shared__ int32_t s_pre[kPart];
@@ -706,7 +702,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         for (int p = 1; p < kPart; p++) s_pre[p] += s_pre[p - 1];  // inclusive prefix of the slice sizes
     __syncthreads();
     const int32_t total = s_pre[kPart - 1];
-    const int32_t step_cap = total >= kLaneMany ? kLaneSteps : kLaneStepsFew;
+    const int32_t step_cap = total >= tn.lane_many ? tn.lane_steps : tn.lane_steps_few;
     const unsigned gwave = blockIdx.x * (kLaneThreads / kWave) + (unsigned)bcast_first(tid / kWave);
     int64_t adds = 0, xe = 0, by = 0, bails = 0, tsl = 0, tg16 = 0, tg32 = 0;
     // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
@@ -792,12 +788,12 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     bool wantf = false;             // P is full: this lane waits for a merge phase
     for (;;) {
         // finished lanes are written back and refilled together, once at
-        // least kLaneRefill of them (or every lane) are waiting: the wave-wide
+        // least tn.lane_refill of them (or every lane) are waiting: the wave-wide
         // work is shared by many columns
         const uint64_t finm = __ballot(fin);
         const bool more = !(drained && tb >= te);  // tasks left for this wave
         const uint64_t want = __ballot(fin && (j >= 0 || more));
-        if (__popcll(want) >= kLaneRefill || finm == ~0ull) {
+        if (__popcll(want) >= tn.lane_refill || finm == ~0ull) {
             // write back (B and P merged from the bottom up) from the wave's arena chunk
             const bool wr = fin && j >= 0 && dirty;
             const int32_t need = wr ? LB + np : 0;
@@ -923,7 +919,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         {
             const uint64_t busy = __ballot(!fin);
             const uint64_t nf = __ballot(!fin && wantf);
-            if (nf && (__popcll(nf) >= kLaneFlushBatch || nf == busy)) {
+            if (nf && (__popcll(nf) >= tn.lane_flush || nf == busy)) {
                 if (wantf) {
                     flush();
                     wantf = false;
@@ -1792,6 +1788,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // (they loop over tiles), so `grid_tiles` only bounds their grids: the
     // exact tile count when the host knows it, a fixed size in a graph.
     size_t xor_slot = 0, lane_slot = 0, chain_slot = 0;
+    const pms_tuning tn = c->tune;
     auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
         const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
         const unsigned gA = grid_for(grid_tiles * kBlock, kBlock, 65536);
@@ -1806,12 +1803,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, gT, kBlock, d, a, opt->variant, opt->compression, opt->chain,
                    opt->tail_active);
         xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, kLaneBlocks, kLaneThreads, d, opt->compression, trace);
+        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, (unsigned)tn.lane_blocks, kLaneThreads, d, opt->compression,
+                   trace, tn);
         lane_slot = c->pend.size() - 1;
         if (trace)
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         else
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, kChainBlocks, kChainWaves * kWave, d, opt->compression);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         chain_slot = c->pend.size() - 1;
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
@@ -1839,10 +1837,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_HIP(hipStreamWaitEvent(gs, c->graph_ev, 0));
         // everything the captured launches depend on
         auto make_key = [&]() {
-            std::vector<unsigned char> k(sizeof(Dev) + sizeof(pms_options) + 5 * sizeof(void *) + 2 * sizeof(int64_t));
+            std::vector<unsigned char> k(sizeof(Dev) + sizeof(pms_options) + sizeof(pms_tuning) + 5 * sizeof(void *) +
+                                         2 * sizeof(int64_t));
             unsigned char *p = k.data();
             memcpy(p, &d, sizeof(Dev));
             p += sizeof(Dev);
+            memcpy(p, &tn, sizeof(tn));
+            p += sizeof(tn);
             pms_options o2 = *opt;
             memcpy(p, &o2, sizeof(o2));
             p += sizeof(o2);
@@ -2164,6 +2165,71 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         res->n_pairs = res->n_essential = 0;
     }
     return s;
+}
+
+pms_tuning pms_default_tuning(void) { return pms::default_tuning(); }
+
+pms_status pms_set_tuning(pms_ctx *c, const pms_tuning *t)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    const pms_tuning v = t ? *t : pms::default_tuning();
+    if (!pms::tuning_valid(v)) return pms::set_err(c, PMS_ERR_INVALID_ARG, "tuning field out of range");
+    c->tune = v;
+    return PMS_OK;
+}
+
+pms_status pms_get_tuning(pms_ctx *c, pms_tuning *t)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!t) return pms::set_err(c, PMS_ERR_INVALID_ARG, "null tuning");
+    *t = c->tune;
+    return PMS_OK;
+}
+
+pms_status pms_autotune(pms_ctx *c, const pms_boundary *bnd, int32_t n, const pms_options *opts,
+                        const pms_tuning *tunes, int32_t reps, pms_result *res, double *ms, int32_t *best)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!bnd || !res || !tunes || !best || n < 1 || reps < 1 || reps > 64)
+        return pms::set_err(c, PMS_ERR_INVALID_ARG,
+                            "null boundary / result / candidates / best, n < 1, or reps outside 1..64");
+    for (int32_t i = 0; i < n; i++)
+        if (!pms::tuning_valid(tunes[i]))
+            return pms::set_err(c, PMS_ERR_INVALID_ARG,
+                                "candidate " + std::to_string(i) + ": tuning field out of range");
+    const pms_tuning before = c->tune;
+    auto fail = [&](int32_t i, pms_status s) {
+        c->tune = before;
+        c->err = "candidate " + std::to_string(i) + ": " + c->err;
+        return s;
+    };
+    std::vector<double> score((size_t)n), t((size_t)reps);
+    for (int32_t i = 0; i < n; i++) {
+        c->tune = tunes[i];
+        const pms_options *o = opts ? &opts[i] : nullptr;
+        // one untimed run (scratch growth, graph capture), then the timed ones
+        for (int32_t r = -1; r < reps; r++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const pms_status s = pms_reduce(c, bnd, o, res);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (s != PMS_OK) return fail(i, s);
+            if (r >= 0) t[(size_t)r] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        }
+        std::sort(t.begin(), t.end());
+        score[(size_t)i] = (reps & 1) ? t[(size_t)reps / 2] : 0.5 * (t[(size_t)reps / 2 - 1] + t[(size_t)reps / 2]);
+        if (ms) ms[i] = score[(size_t)i];
+    }
+    int32_t b = 0;
+    for (int32_t i = 1; i < n; i++)
+        if (score[(size_t)i] < score[(size_t)b]) b = i;
+    c->tune = tunes[b];
+    const pms_status s = pms_reduce(c, bnd, opts ? &opts[b] : nullptr, res);
+    if (s != PMS_OK) return fail(b, s);
+    *best = b;
+    return PMS_OK;
 }
 
 pms_status pms_reduce_batched(pms_ctx *c, int32_t count, const int64_t *inst_col_off, const pms_boundary *bnd,
