@@ -54,7 +54,8 @@ class PmsTuning(ctypes.Structure):
     _fields_ = [("lane_blocks", ctypes.c_int32), ("chain_blocks", ctypes.c_int32),
                 ("lane_steps", ctypes.c_int32), ("lane_steps_few", ctypes.c_int32),
                 ("lane_many", ctypes.c_int32), ("lane_refill", ctypes.c_int32),
-                ("lane_flush", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lane_flush", ctypes.c_int32), ("wide_blocks", ctypes.c_int32),
+                ("lane_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PmsFiltrationView(ctypes.Structure):

@@ -38,6 +38,8 @@ GRID = {
     "lane_steps_few": (0, 8, 32),
     "lane_refill": (16, 32, 48),
     "lane_flush": (8, 16, 32),
+    "wide_blocks": (512, 1024, 2048),
+    "lane_cap": (32, 40, 48),
     "graph_rounds": (0, 8),
 }
 

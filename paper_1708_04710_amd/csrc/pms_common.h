@@ -27,7 +27,7 @@ struct Buf {
 enum KernelId {
     K_INIT = 0, K_BETA, K_LOW, K_COLLIDE, K_SCAN, K_PIVOTS, K_XOR, K_COMPACT, K_FINAL, K_FILL, K_DEFRAG,
     K_LS_KEYS, K_SORT, K_LS_INDEX, K_BUILD_SCAN, K_LS_ROWS, K_VR_EDGES, K_VR_TRI, K_VR_INDEX, K_VR_ROWS,
-    K_BACKWARD, K_CHAIN, K_CHAIN_LANE,
+    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE,
     K_NUM
 };
 
@@ -49,6 +49,8 @@ inline pms_tuning default_tuning()
     t.lane_many = 65536;
     t.lane_refill = 32;
     t.lane_flush = 16;
+    t.wide_blocks = 1024;  // 4 per CU
+    t.lane_cap = 48;
     t.reserved = 0;
     return t;
 }
@@ -58,7 +60,8 @@ inline bool tuning_valid(const pms_tuning &t)
     return t.lane_blocks >= 1 && t.lane_blocks <= 65535 && t.chain_blocks >= 1 && t.chain_blocks <= 65535 &&
            t.lane_steps >= 0 && t.lane_steps <= (1 << 30) && t.lane_steps_few >= 0 &&
            t.lane_steps_few <= (1 << 30) && t.lane_many >= 0 && t.lane_refill >= 1 && t.lane_refill <= 64 &&
-           t.lane_flush >= 1 && t.lane_flush <= 64 && t.reserved == 0;
+           t.lane_flush >= 1 && t.lane_flush <= 64 && t.wide_blocks >= 1 && t.wide_blocks <= 65535 &&
+           t.lane_cap >= 0 && t.lane_cap <= 48 && t.reserved == 0;
 }
 
 struct Ctx {
@@ -93,7 +96,7 @@ enum BufId {
     B_OFF = 0, B_LEN, B_LOW, B_STATE, B_BETA, B_LEFT, B_PIV, B_T, B_NEG, B_ACT0, B_ACT1,
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
-    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_STATS, B_PART, B_CQN, B_PREC, B_WQ,
+    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_STATS, B_PART, B_CQN, B_PREC, B_WQ, B_WQ2,
     B_NUM
 };
 

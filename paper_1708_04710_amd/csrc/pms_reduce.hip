@@ -62,6 +62,7 @@ enum StatId {
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
     S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
+    S_WBYTES, S_T_WIDE, S_T_TOWIDE,
     S_NUM
 };
 
@@ -72,6 +73,7 @@ struct Counters {
     unsigned long long xor_bytes;    // algorithmic bytes moved by k_xor
     unsigned long long chain_bytes;  // algorithmic bytes moved by k_chain
     unsigned long long lane_bytes;   // algorithmic bytes moved by k_chain_lane
+    unsigned long long wide_bytes;   // algorithmic bytes moved by k_chain_wide
     int32_t error;       // 1 = not compatible
     int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
@@ -126,9 +128,11 @@ struct Dev {
     unsigned long long part_base, part_size;
     PivRec *prec;      // [m] pivot records by row
     int32_t *cq;       // chain queue, kPart slices of cq_slice entries
-    int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]; cq_n[kPart*32] = wq entries
+    int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]; cq_n[kPart*32] = wq entries,
+                       // cq_n[(kPart+1)*32] = wq2 entries
     int64_t cq_slice;
-    int32_t *wq;       // columns handed from the lane chain kernel to the wavefront one
+    int32_t *wq;       // columns handed from the lane chain passes to the wavefront kernel
+    int32_t *wq2;      // columns the first lane pass hands to the wide one (too long for its buffer)
 };
 
 constexpr int kStripe = 64;
@@ -285,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
 {
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
-    if (blockIdx.x == 0 && threadIdx.x <= kPart) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
+    if (blockIdx.x == 0 && threadIdx.x <= kPart + 1) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
     if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -677,10 +681,17 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // iteration every busy lane takes one step, and a lane whose chain ends
 // writes its column back merged into the arena (from a chunk its wave
 // claimed) and takes the wave's next queued column, so short and long chains
-// share a wave without idling it.  Columns that outgrow the buffer, meet a longer
-// pivot or chain longer than the step cap go on to the wavefront kernel.
+// share a wave without idling it.  Columns that meet a longer pivot or chain
+// longer than the step cap go on to the wavefront kernel.  The kernel runs in
+// two passes: the first (k_chain_lane, 48 entries per lane, two waves per
+// block) takes the round's queued columns and hands those that outgrow its
+// buffer to the second (k_chain_wide, 128 entries per lane, one wave per
+// block: fewer lanes per CU, for the fewer long columns); what outgrows that
+// goes to the wavefront kernel too.
 constexpr int kLaneThreads = 128;
 constexpr int kLaneCap = 48;
+constexpr int kWideThreads = 64;
+constexpr int kWideCap = 128;
 constexpr int kLaneP = 16;
 // The grid, the step caps and the refill / merge thresholds come from the
 // context's pms_tuning.  A lane hands a longer chain to a wavefront, whose
@@ -689,25 +700,34 @@ constexpr int kLaneP = 16;
 // move on early (they are the critical path, tn.lane_steps_few).
 constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
 
-__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace, pms_tuning tn)
+template <int kCap, int kThreads, bool kWide>
+__device__ __forceinline__ void lane_chain(const Dev &d, int compression, int trace, const pms_tuning &tn)
 {
-    __shared__ int32_t sL[kLaneCap * kLaneThreads];
+    __shared__ int32_t sL[kCap * kThreads];
     __shared__ int32_t s_pre[kPart];
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // the lanes under this one
-#define LW(e) sL[(e) * kLaneThreads + tid]
-    if (tid < kPart) s_pre[tid] = d.cq_n[tid * 32];
-    __syncthreads();
-    if (tid == 0)
-        for (int p = 1; p < kPart; p++) s_pre[p] += s_pre[p - 1];  // inclusive prefix of the slice sizes
-    __syncthreads();
-    const int32_t total = s_pre[kPart - 1];
+#define LW(e) sL[(e) * kThreads + tid]
+    int32_t total;
+    if (!kWide) {  // the round's queue: kPart slices
+        if (tid < kPart) s_pre[tid] = d.cq_n[tid * 32];
+        __syncthreads();
+        if (tid == 0)
+            for (int p = 1; p < kPart; p++) s_pre[p] += s_pre[p - 1];  // inclusive prefix of the slice sizes
+        __syncthreads();
+        total = s_pre[kPart - 1];
+    } else {  // the first pass's hand-overs, one list
+        total = d.cq_n[(kPart + 1) * 32];
+    }
     const int32_t step_cap = total >= tn.lane_many ? tn.lane_steps : tn.lane_steps_few;
-    const unsigned gwave = blockIdx.x * (kLaneThreads / kWave) + (unsigned)bcast_first(tid / kWave);
-    int64_t adds = 0, xe = 0, by = 0, bails = 0, tsl = 0, tg16 = 0, tg32 = 0;
+    // entries a lane's buffer may hold: the first pass may use less than its
+    // LDS room (tn.lane_cap), handing longer columns to the wide pass
+    const int32_t cap = kWide ? kCap : min(kCap, tn.lane_cap);
+    const unsigned gwave = blockIdx.x * (kThreads / kWave) + (unsigned)bcast_first(tid / kWave);
+    int64_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0, tsl = 0, tg16 = 0, tg32 = 0;
     // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
     // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ...
-    const int64_t nwaves = (int64_t)gridDim.x * (kLaneThreads / kWave);
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / kWave);
     int64_t kc = gwave;
     int32_t tb = 0, te = 0;
     bool drained = false;
@@ -752,7 +772,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         for (int u = 0; u < kLaneP; u++) p[u] = q[u];
         np += pres ? -1 : 1;
     };
-    // B := B xor P in place, from the top down (needs LB + np <= kLaneCap);
+    // B := B xor P in place, from the top down (needs LB + np <= cap);
     // cancelled pairs close the gap by moving the merged top part down
     auto flush = [&]() {
         int32_t r = LB - 1, w = LB + np - 1, c = 0;
@@ -785,6 +805,7 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
         np = 0;
     };
     bool fin = true, bail = false;  // fin: no column in progress (finished, or never given one)
+    bool roomb = false;             // the bail is for want of buffer room (first pass: to the wide one)
     bool wantf = false;             // P is full: this lane waits for a merge phase
     for (;;) {
         // finished lanes are written back and refilled together, once at
@@ -839,18 +860,30 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 by += 4 * (int64_t)w + 16;
             }
             if (room) cb += wtot;
-            // hand the bailing columns over to the wavefront kernel
-            const uint64_t bal = __ballot(fin && bail);
+            // hand the bailing columns over to the wavefront kernel, or (first
+            // pass, too long for the buffer) to the wide pass
+            const uint64_t bal = __ballot(fin && bail && !roomb);
             if (bal) {
                 int32_t qb = 0;
                 if (lane == 0) qb = atomicAdd(&d.cq_n[kPart * 32], (int32_t)__popcll(bal));
                 qb = bcast_first(qb);
-                if (fin && bail) d.wq[qb + __popcll(bal & below)] = j;
-                bails += (fin && bail) ? 1 : 0;
+                if (fin && bail && !roomb) d.wq[qb + __popcll(bal & below)] = j;
+                bails += (fin && bail && !roomb) ? 1 : 0;
+            }
+            if (!kWide) {
+                const uint64_t balw = __ballot(fin && bail && roomb);
+                if (balw) {
+                    int32_t qb = 0;
+                    if (lane == 0) qb = atomicAdd(&d.cq_n[(kPart + 1) * 32], (int32_t)__popcll(balw));
+                    qb = bcast_first(qb);
+                    if (fin && bail && roomb) d.wq2[qb + __popcll(balw & below)] = j;
+                    towide += (fin && bail && roomb) ? 1 : 0;
+                }
             }
             if (fin) {
                 j = -1;
                 bail = false;
+                roomb = false;
             }
             // refill: the wave's next tasks to the free lanes
             uint64_t idle = finm;
@@ -869,14 +902,18 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 const int32_t avail = te - tb;
                 if (((idle >> lane) & 1ull) && rank < avail) {
                     const int32_t t = tb + rank;
-                    int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_pre[mid] > t) hi = mid;
-                        else lo = mid + 1;
+                    if (kWide) {
+                        j = d.wq2[t];
+                    } else {
+                        int lo = 0, hi = kPart - 1;  // first slice whose prefix exceeds t
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_pre[mid] > t) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        const int32_t before = lo > 0 ? s_pre[lo - 1] : 0;
+                        j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
                     }
-                    const int32_t before = lo > 0 ? s_pre[lo - 1] : 0;
-                    j = d.cq[(int64_t)lo * d.cq_slice + (t - before)];
                     fin = false;
                 }
                 tb += min(__popcll(idle), avail);
@@ -894,8 +931,9 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 dirty = false;
                 wantf = false;
                 steps = 0;
-                if (L > kLaneCap) {
-                    bail = true;  // too long for a lane: straight to the wavefront kernel
+                if (L > cap) {
+                    bail = true;  // too long for a lane: straight to the next pass
+                    roomb = !kWide;
                     fin = true;
                     LB = 0;
                 } else {
@@ -949,8 +987,9 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
                 }
             } else {
                 const int32_t kk = lk.k - 1;
-                if (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > kLaneCap)) {
+                if (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > cap)) {
                     bail = true;
+                    roomb = !kWide && kk <= kRecInline && steps < step_cap;  // only room is lacking
                     fin = true;
                 } else if (np + kk > kLaneP) {
                     wantf = true;  // P is full: wait for the wave's next merge phase
@@ -988,19 +1027,30 @@ __global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compress
     const int64_t wadds = wave_incl_sum64(adds), wxe = wave_incl_sum64(xe), wby = wave_incl_sum64(by),
                   wb = wave_incl_sum64(bails);
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
-                  wg32 = trace ? wave_incl_sum64(tg32) : 0;
+                  wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64(towide) : 0;
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, gwave);
-        stat_add(d, S_LBYTES, (unsigned long long)wby, gwave);
+        stat_add(d, kWide ? S_WBYTES : S_LBYTES, (unsigned long long)wby, gwave);
         if (trace) {
-            stat_add(d, S_T_LANE, (unsigned long long)wadds, gwave);
+            stat_add(d, kWide ? S_T_WIDE : S_T_LANE, (unsigned long long)wadds, gwave);
+            stat_add(d, S_T_TOWIDE, (unsigned long long)wtw, gwave);
             stat_add(d, S_T_BAIL, (unsigned long long)wb, gwave);
             stat_add(d, S_T_LSUML, (unsigned long long)wsl, gwave);
             stat_add(d, S_T_LGT16, (unsigned long long)wg16, gwave);
             stat_add(d, S_T_LGT32, (unsigned long long)wg32, gwave);
         }
     }
+}
+
+__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace, pms_tuning tn)
+{
+    lane_chain<kLaneCap, kLaneThreads, false>(d, compression, trace, tn);
+}
+
+__global__ void __launch_bounds__(kWideThreads) k_chain_wide(Dev d, int compression, int trace, pms_tuning tn)
+{
+    lane_chain<kWideCap, kWideThreads, true>(d, compression, trace, tn);
 }
 
 // Wavefront chaining, for the columns the lane kernel hands over (long
@@ -1564,6 +1614,7 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->xor_bytes = s_sum[S_XBYTES];
         d.cnt->chain_bytes = s_sum[S_CBYTES];
         d.cnt->lane_bytes = s_sum[S_LBYTES];
+        d.cnt->wide_bytes = s_sum[S_WBYTES];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
         for (int q = 0; q < S_NUM; q++) d.cnt->trace[q] = s_sum[q];
@@ -1725,13 +1776,15 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t *keep2 = (int32_t *)scratch(c, B_FLAGS, (nblk + 1) * 4);
     d.cq_slice = (nblk + kPart - 1) / kPart * kBlock;  // a slice takes every kPart-th tile
     d.cq = (int32_t *)scratch(c, B_TMP0, (size_t)kPart * d.cq_slice * 4);
-    d.cq_n = (int32_t *)scratch(c, B_CQN, (kPart + 1) * 32 * 4);
+    d.cq_n = (int32_t *)scratch(c, B_CQN, (kPart + 2) * 32 * 4);
     d.wq = (int32_t *)scratch(c, B_WQ, (size_t)m * 4);
+    d.wq2 = (int32_t *)scratch(c, B_WQ2, (size_t)m * 4);
     d.stats = (unsigned long long *)scratch(c, B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
     d.part = (unsigned long long *)scratch(c, B_PART, kPart * 16 * 8);
     d.prec = (PivRec *)scratch(c, B_PREC, (size_t)m * sizeof(PivRec));
     if (!d.off || !d.len || !d.low || !d.state || !d.beta || !d.left || !d.piv || !d.T || !d.neg || !d.coll ||
-        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec || !d.wq)
+        !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec || !d.wq ||
+        !d.wq2)
         return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
 
     // arena: sized for the first rounds' fill-in, grown on demand
@@ -1777,7 +1830,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
-    unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0;
+    unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0, wide_bytes_prev = 0;
     const char *tr_env = getenv("PMS_TRACE");
     const int trace = tr_env && tr_env[0] == '1';
     unsigned long long tprev[S_NUM] = {};
@@ -1787,7 +1840,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // The kernels read the round's active count and number from the device
     // (they loop over tiles), so `grid_tiles` only bounds their grids: the
     // exact tile count when the host knows it, a fixed size in a graph.
-    size_t xor_slot = 0, lane_slot = 0, chain_slot = 0;
+    size_t xor_slot = 0, lane_slot = 0, wide_slot = 0, chain_slot = 0;
     const pms_tuning tn = c->tune;
     auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
         const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
@@ -1806,6 +1859,9 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, (unsigned)tn.lane_blocks, kLaneThreads, d, opt->compression,
                    trace, tn);
         lane_slot = c->pend.size() - 1;
+        PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide, (unsigned)tn.wide_blocks, kWideThreads, d, opt->compression,
+                   trace, tn);
+        wide_slot = c->pend.size() - 1;
         if (trace)
             PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         else
@@ -1925,6 +1981,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             chain_bytes_prev = h->chain_bytes;
             c->pend[lane_slot].bytes = (double)(h->lane_bytes - lane_bytes_prev);
             lane_bytes_prev = h->lane_bytes;
+            c->pend[wide_slot].bytes = (double)(h->wide_bytes - wide_bytes_prev);
+            wide_bytes_prev = h->wide_bytes;
             prof_flush(c);
         }
         if (trace) {
@@ -1932,11 +1990,13 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             for (int q = 0; q < S_NUM; q++) { dl[q] = h->trace[q] - tprev[q]; tprev[q] = h->trace[q]; }
             const double st = (double)(dl[S_T_SHORT] ? dl[S_T_SHORT] : 1);
             fprintf(stderr,
-                    "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, handed to waves "
+                    "pms round %u: active %d -> %d, new pivots %llu, additions %llu, lane steps %llu, to the wide "
+                    "pass %llu, wide steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
                     "mean L %.1f, L>16 %llu, L>32 %llu\n",
-                    round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_QUEUED], dl[S_T_SHORT],
+                    round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
+                    dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
                     dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st,
@@ -2093,7 +2153,7 @@ void pms_destroy(pms_ctx *c)
 static const char *const kKernelNames[pms::K_NUM] = {
     "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
     "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
-    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane"};
+    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide"};
 
 pms_status pms_profile_enable(pms_ctx *c, int enable)
 {

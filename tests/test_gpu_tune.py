@@ -18,10 +18,12 @@ SETTINGS = [
     dict(),                                    # built-in
     dict(lane_steps=0, lane_steps_few=0),      # every chain moves to the wavefront kernel at its first pivot
     dict(lane_many=0, lane_steps=1 << 30),     # lanes keep every chain they can hold
-    dict(lane_blocks=1, chain_blocks=1),       # two lane waves, four wavefront waves
+    dict(lane_blocks=1, chain_blocks=1, wide_blocks=1),  # two lane waves, one wide, four wavefront waves
     dict(lane_refill=1, lane_flush=1),
     dict(lane_refill=64, lane_flush=64),
     dict(lane_blocks=65535, chain_blocks=4096, lane_steps=3, lane_steps_few=1),
+    dict(lane_cap=4),                          # most columns go through the wide pass
+    dict(lane_cap=0, wide_blocks=2, lane_refill=1),  # every column does
 ]
 
 
@@ -70,13 +72,42 @@ def test_every_setting_gives_the_oracle_pairs(gpu, builtin_after, work):
             _check(res, low_ref)
 
 
+def test_wide_pass_takes_the_long_columns(gpu, builtin_after):
+    """With the first lane pass's buffer cut to 6 entries (and the long step
+    cap in force at any queue length), the working
+    columns of full 2-skeletons of 64-point circles outgrow it: the wide pass
+    takes them (it moves bytes) and the pairs stay the oracle's, also with the
+    wide pass on one block, with a late refill, and with every chain handed to
+    wavefronts at once."""
+    api.set_tuning(dict(lane_cap=6, lane_many=0), device=gpu)
+    x = synth.circle_batch(seed=53, clouds=2, n=64)
+    f, off = api.build_vr([torch.as_tensor(c, device=gpu) for c in x], [-1.0] * len(x), 2)
+    want = []
+    for b, c in enumerate(x):
+        ref = oracle.build_vr_f32(c, -1.0, 2)
+        low = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        want.append(np.where(low >= 0, low + off[b], -1))
+    low_ref = np.concatenate(want).astype(np.int32)
+    api.profile_enable(True, gpu)
+    res = api.reduce_filtration(f)
+    prof = api.profile_read(gpu)
+    api.profile_enable(False, gpu)
+    assert prof["k_chain_wide"][2] > 0
+    _check(res, low_ref)
+    for s in (dict(lane_cap=6, lane_many=0, wide_blocks=1), dict(lane_cap=6, lane_many=0, wide_blocks=3, lane_refill=64),
+              dict(lane_cap=6, lane_steps=0, lane_steps_few=0)):
+        api.set_tuning(s, device=gpu)
+        _check(api.reduce_filtration(f), low_ref)
+
+
 def test_invalid_settings_are_rejected_and_change_nothing(gpu, builtin_after):
     keep = dict(lane_blocks=777, lane_refill=5)
     api.set_tuning(keep, device=gpu)
     want = {**api.default_tuning(), **keep}
     for bad in (dict(lane_refill=0), dict(lane_refill=65), dict(lane_flush=0), dict(lane_flush=65),
                 dict(lane_blocks=0), dict(lane_blocks=65536), dict(chain_blocks=0), dict(chain_blocks=65536),
-                dict(lane_steps=-1), dict(lane_steps_few=(1 << 30) + 1), dict(lane_many=-1)):
+                dict(lane_steps=-1), dict(lane_steps_few=(1 << 30) + 1), dict(lane_many=-1),
+                dict(wide_blocks=0), dict(wide_blocks=65536), dict(lane_cap=-1), dict(lane_cap=49)):
         with pytest.raises(_binding.PmsError) as e:
             api.set_tuning(bad, device=gpu)
         assert e.value.status == _binding.PMS_ERR_INVALID_ARG, bad
