@@ -638,9 +638,8 @@ __device__ inline int32_t lower_bound_i32(const int32_t *a, int32_t n, int32_t x
 
 // Everything a chain step needs about row i: its record, one load.
 struct Look {
-    int32_t s, k;
+    int32_t s, k;  // k < 0: the row is known negative
     int32_t e[kRecInline];
-    int32_t neg;
 };
 
 __device__ inline Look look_up(const Dev &d, int32_t i)
@@ -651,7 +650,6 @@ __device__ inline Look look_up(const Dev &d, int32_t i)
     r.k = rec.k;
 #pragma unroll
     for (int t = 0; t < kRecInline; t++) r.e[t] = rec.e[t];
-    r.neg = rec.k < 0 ? 1 : 0;
     return r;
 }
 
@@ -756,7 +754,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
             LB--;
         }
     };
-    // P := P xor {x}
+    // P := P xor {x}; x = -2 (above the -1 padding, below every row) leaves P
+    // as it is, so lanes with fewer toggles run the same instructions
     auto toggle = [&](int32_t x) {
         bool pres = false;
 #pragma unroll
@@ -770,7 +769,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
         }
 #pragma unroll
         for (int u = 0; u < kLaneP; u++) p[u] = q[u];
-        np += pres ? -1 : 1;
+        np += x < 0 ? 0 : (pres ? -1 : 1);
     };
     // B := B xor P in place, from the top down (needs LB + np <= cap);
     // cancelled pairs close the gap by moving the merged top part down
@@ -964,60 +963,62 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
                 }
             }
         }
-        // one step for every lane with a column in progress
-        if (!fin && !wantf) {
-            if (i < 0) {
-                fin = true;  // W is zero
-            } else if (lk.s < 0) {
-                if (compression && lk.neg) {  // a known-negative row: delete it
-                    if (p[0] == i) shift_p();
-                    else LB--;
-                    dirty = true;
-                    const int32_t ni = top();
-                    if (ni >= i) {  // the low must drop; stop rather than spin
-                        atomicExch(&d.cnt->bad_source, 2);
-                        dirty = false;
-                        fin = true;
-                    } else {
-                        i = ni;
-                        if (i >= 0) lk = look_up(d, i);
-                    }
-                } else {
-                    fin = true;  // no pivot owns the low: the chain ends here
+        // one step for every lane with a column in progress.  The pending-set
+        // updates are selects run by every lane (per-lane branches around
+        // them cost more in exec-mask handling and register copies than the
+        // selects themselves); only the search for the next low branches.
+        {
+            const bool act = !fin && !wantf;
+            const int32_t kk = lk.k - 1;
+            const bool has = act && i >= 0;
+            const bool piv = has && lk.s >= 0;
+            const bool del = has && lk.s < 0 && compression && lk.k < 0;  // a known-negative row: delete it
+            // W is zero, or no pivot owns its low: the chain ends here
+            if (act && !piv && !del) fin = true;
+            const bool over = piv && (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > cap));
+            if (over) {
+                bail = true;
+                roomb = !kWide && kk <= kRecInline && steps < step_cap;  // only room is lacking
+                fin = true;
+            }
+            const bool full = piv && !over && np + kk > kLaneP;
+            if (full) wantf = true;  // P is full: wait for the wave's next merge phase
+            const bool go = piv && !over && !full;
+            if (go) {
+                steps++;
+                adds++;
+                xe += (int64_t)LB + np + kk + 1;
+                by += 32;
+                if (trace) {
+                    tsl += LB + np;
+                    tg16 += LB + np > 16 ? 1 : 0;
+                    tg32 += LB + np > 32 ? 1 : 0;
                 }
-            } else {
-                const int32_t kk = lk.k - 1;
-                if (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > cap)) {
-                    bail = true;
-                    roomb = !kWide && kk <= kRecInline && steps < step_cap;  // only room is lacking
-                    fin = true;
-                } else if (np + kk > kLaneP) {
-                    wantf = true;  // P is full: wait for the wave's next merge phase
-                } else {
-                    steps++;
-                    adds++;
-                    xe += (int64_t)LB + np + kk + 1;
-                    by += 32;
-                    if (trace) {
-                        tsl += LB + np;
-                        tg16 += LB + np > 16 ? 1 : 0;
-                        tg32 += LB + np > 32 ? 1 : 0;
-                    }
-                    if (p[0] == i) shift_p();
-                    else LB--;
+            }
+            // the low leaves W: from P when it is P's top, else from B's top
+            const bool rm = go || del;
+            const bool fromp = rm && p[0] == i;
 #pragma unroll
-                    for (int q = 0; q < kRecInline; q++)
-                        if (q < kk) toggle(lk.e[q]);
-                    dirty = true;
-                    const int32_t ni = top();
-                    if (ni >= i) {
-                        atomicExch(&d.cnt->bad_source, 2);
-                        dirty = false;
-                        fin = true;
-                    } else {
-                        i = ni;
-                        if (i >= 0) lk = look_up(d, i);
-                    }
+            for (int u = 0; u < kLaneP; u++) p[u] = fromp ? (u + 1 < kLaneP ? p[u + 1] : -1) : p[u];
+            np -= fromp ? 1 : 0;
+            LB -= (rm && !fromp) ? 1 : 0;
+            // the pivot's entries below the low, as many rounds as the wave's
+            // longest record needs
+#pragma unroll
+            for (int q = 0; q < kRecInline; q++) {
+                if (__ballot(go && q < kk) == 0) break;
+                toggle(go && q < kk ? lk.e[q] : -2);
+            }
+            if (rm) {
+                dirty = true;
+                const int32_t ni = top();
+                if (ni >= i) {  // the low must drop; stop rather than spin
+                    atomicExch(&d.cnt->bad_source, 2);
+                    dirty = false;
+                    fin = true;
+                } else {
+                    i = ni;
+                    if (i >= 0) lk = look_up(d, i);
                 }
             }
         }
