@@ -200,6 +200,27 @@ __device__ inline int32_t wave_max_dpp(int32_t v)
 
 // Broadcasts whose result the compiler knows to be wave-uniform (scalar
 // registers), unlike __shfl: control flow that depends on them stays scalar.
+// Workgroups are dispatched to the 8 XCDs, each with its own L2, in
+// round-robin order of their index.  xcd_split gives the workgroups of XCD x
+// the x-th eighth of the units [0, n), walked from `first` in steps of `step`
+// up to `end`: neighbouring columns then share an XCD and its cached lines
+// (a grid of fewer than 8 blocks splits into as many parts as blocks).
+constexpr unsigned kXcds = 8;
+struct XcdSplit {
+    int64_t first, end, step;
+};
+__device__ inline XcdSplit xcd_split(int64_t n)
+{
+    const unsigned g = gridDim.x;
+    const unsigned nx = g < kXcds ? g : kXcds;
+    const unsigned x = blockIdx.x % nx;
+    XcdSplit s;
+    s.first = n * x / nx + blockIdx.x / nx;
+    s.end = n * (x + 1) / nx;
+    s.step = (g - x + nx - 1) / nx;  // the blocks on part x
+    return s;
+}
+
 __device__ inline int32_t bcast_first(int32_t x)
 {
     return __builtin_amdgcn_readfirstlane(x);

@@ -62,7 +62,7 @@ enum StatId {
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
     S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
-    S_WBYTES, S_T_WIDE, S_T_TOWIDE,
+    S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY,
     S_NUM
 };
 
@@ -209,7 +209,10 @@ __global__ void k_iota(int32_t *p, int64_t n)
 __global__ void k_init(Dev d, int64_t nnz, int validate)
 {
     int top = 0;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+    const XcdSplit xs = xcd_split((d.m + blockDim.x - 1) / blockDim.x);
+    for (int64_t t = xs.first; t < xs.end; t += xs.step) {
+        const int64_t j = t * blockDim.x + threadIdx.x;
+        if (j >= d.m) continue;
         const int64_t s = d.col_ptr[j], e = d.col_ptr[j + 1];
         bool bad = e < s || s < 0 || e > nnz || (j == 0 && s != 0) || e - s > 0x7FFFFFFF;
         int32_t n = bad ? 0 : (int32_t)(e - s);
@@ -242,7 +245,10 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
 // negative (Thm. "Properties of beta_j" P.3), so its row can be compressed.
 __global__ void k_beta(Dev d, int compression)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+    const XcdSplit xs = xcd_split((d.m + blockDim.x - 1) / blockDim.x);
+    for (int64_t t = xs.first; t < xs.end; t += xs.step) {
+        const int64_t j = t * blockDim.x + threadIdx.x;
+        if (j >= d.m) continue;
         const int64_t s = d.col_ptr[j];
         int32_t b = -1;
         for (int64_t p = s + d.len[j] - 1; p >= s; p--) {
@@ -262,7 +268,10 @@ __global__ void k_low(Dev d, const int32_t *act)
 {
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nA; q += (int64_t)gridDim.x * blockDim.x) {
+    const XcdSplit xs = xcd_split(((int64_t)nA + blockDim.x - 1) / blockDim.x);
+    for (int64_t t = xs.first; t < xs.end; t += xs.step) {
+        const int64_t q = t * blockDim.x + threadIdx.x;
+        if (q >= nA) continue;
         const int32_t j = act[q];
         int32_t n = d.len[j];
         const int32_t *c = col_base(d, d.off[j]);
@@ -292,7 +301,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
     if (blockIdx.x == 0 && threadIdx.x <= kPart + 1) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
     if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const XcdSplit xs = xcd_split(tiles);
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
     const int64_t q = tile * kBlock + threadIdx.x;
     I4 e = i4_fill(-1);
     if (q < nA) {
@@ -381,7 +391,8 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
     const int32_t nA = d.cnt->n_cur;
     const int count_beta = d.cnt->round == 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const XcdSplit xs = xcd_split(tiles);
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
     const int64_t q = tile * kBlock + threadIdx.x;
     I4 e = i4_fill(-1);
     int32_t j = -1, i = -1;
@@ -535,6 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    // strided: per-tile work varies widely (long merges cluster), so fixed parts would leave a tail
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t q = tile * kBlock + threadIdx.x;
     int32_t j = -1, s = -1, tlen = 0, slen = 0;
@@ -724,7 +736,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
     const unsigned gwave = blockIdx.x * (kThreads / kWave) + (unsigned)bcast_first(tid / kWave);
     int64_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0, tsl = 0, tg16 = 0, tg32 = 0;
     // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
-    // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ...
+    // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ... (shared
+    // by the whole grid: chain lengths vary, and fixed parts would idle at the end)
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / kWave);
     int64_t kc = gwave;
     int32_t tb = 0, te = 0;
@@ -806,7 +819,9 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
     bool fin = true, bail = false;  // fin: no column in progress (finished, or never given one)
     bool roomb = false;             // the bail is for want of buffer room (first pass: to the wide one)
     bool wantf = false;             // P is full: this lane waits for a merge phase
+    int64_t titer = 0, trefill = 0, tflush = 0, tbusy = 0;  // trace: wave iterations, phases, busy lanes
     for (;;) {
+        if (trace) titer++;
         // finished lanes are written back and refilled together, once at
         // least tn.lane_refill of them (or every lane) are waiting: the wave-wide
         // work is shared by many columns
@@ -814,6 +829,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
         const bool more = !(drained && tb >= te);  // tasks left for this wave
         const uint64_t want = __ballot(fin && (j >= 0 || more));
         if (__popcll(want) >= tn.lane_refill || finm == ~0ull) {
+            if (trace) trefill++;
             // write back (B and P merged from the bottom up) from the wave's arena chunk
             const bool wr = fin && j >= 0 && dirty;
             const int32_t need = wr ? LB + np : 0;
@@ -956,7 +972,9 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
         {
             const uint64_t busy = __ballot(!fin);
             const uint64_t nf = __ballot(!fin && wantf);
+            if (trace) tbusy += __popcll(busy);
             if (nf && (__popcll(nf) >= tn.lane_flush || nf == busy)) {
+                if (trace) tflush++;
                 if (wantf) {
                     flush();
                     wantf = false;
@@ -1036,6 +1054,12 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
         if (trace) {
             stat_add(d, kWide ? S_T_WIDE : S_T_LANE, (unsigned long long)wadds, gwave);
             stat_add(d, S_T_TOWIDE, (unsigned long long)wtw, gwave);
+            if (!kWide) {  // wave-uniform counts, once per wave
+                stat_add(d, S_T_LITER, (unsigned long long)titer, gwave);
+                stat_add(d, S_T_LREFILL, (unsigned long long)trefill, gwave);
+                stat_add(d, S_T_LFLUSH, (unsigned long long)tflush, gwave);
+                stat_add(d, S_T_LBUSY, (unsigned long long)tbusy, gwave);
+            }
             stat_add(d, S_T_BAIL, (unsigned long long)wb, gwave);
             stat_add(d, S_T_LSUML, (unsigned long long)wsl, gwave);
             stat_add(d, S_T_LGT16, (unsigned long long)wg16, gwave);
@@ -1477,7 +1501,8 @@ __global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act
 {
     const int32_t nA = d.cnt->n_cur;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const XcdSplit xs = xcd_split(tiles);
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
         const int64_t q = tile * kBlock + threadIdx.x;
         const int keep = (q < nA && d.state[act[q]] == ST_ACTIVE) ? 1 : 0;
         int32_t tk;
@@ -1493,7 +1518,8 @@ __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, c
 {
     const int32_t nA = d.cnt->n_cur;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const XcdSplit xs = xcd_split(tiles);
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
     const int64_t q = tile * kBlock + threadIdx.x;
     int keep = 0;
     int32_t j = -1;
@@ -1995,13 +2021,17 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "pass %llu, wide steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
-                    "mean L %.1f, L>16 %llu, L>32 %llu\n",
+                    "mean L %.1f, L>16 %llu, L>32 %llu; first lane pass: wave iterations %llu, refill phases %llu, "
+                    "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
                     dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st,
-                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32]);
+                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32],
+                    dl[S_T_LITER], dl[S_T_LREFILL], dl[S_T_LFLUSH],
+                    (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
+                    (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1));
         }
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
