@@ -482,23 +482,56 @@ __device__ inline int32_t merge_add(const int32_t *__restrict__ x, int32_t nx, c
 // The same symmetric difference for one lane with long inputs in global
 // memory: both lists are read in blocks of kMB entries held in registers
 // (a block's loads are independent, so one memory latency per block rather
-// than per entry), the negative-row bits of a block fetched with it; the
-// head of each list is element 0 of its block, consumed by shifting.
+// than per entry, and the next block is requested while the current one is
+// merged), the negative-row bits of a block fetched when it becomes current;
+// the head of each list is element 0 of its block, consumed by shifting.
 constexpr int kMB = 4;
 __device__ inline int32_t merge_add_stream(const int32_t *__restrict__ x, int32_t nx, const int32_t *__restrict__ y,
                                            int32_t ny, int32_t *__restrict__ out, const uint32_t *neg, int compression)
 {
     constexpr int32_t kEnd = 0x7FFFFFFF;
-    int32_t xb[kMB], yb[kMB], xn[kMB], yn[kMB];
-    auto load = [&](const int32_t *a, int32_t n, int32_t pos, int32_t *b, int32_t *nb) {
+    // per list: the block being merged (b, with its negative-row flags n) and
+    // the next block (q, raw entries), requested one block ahead so that its
+    // entries arrive while the current block is consumed
+    int32_t xb[kMB], yb[kMB], xn[kMB], yn[kMB], xq[kMB], yq[kMB];
+    // Loads without conditions, so that a block's loads go out together and
+    // are waited for once: positions past the end read the list's last entry
+    // (kEnd is put in when the block becomes current), the end marker's flag
+    // word is word 0, and the flag words are read even without compression.
+    auto fetch = [&](const int32_t *a, int32_t n, int32_t pos, int32_t *q) {
+        const int32_t *src = n > 0 ? a : reinterpret_cast<const int32_t *>(neg);  // an empty list reads a valid word
+        const int32_t last = n > 0 ? n - 1 : 0;
 #pragma unroll
-        for (int u = 0; u < kMB; u++) b[u] = pos + u < n ? a[pos + u] : kEnd;
-#pragma unroll
-        for (int u = 0; u < kMB; u++) nb[u] = (compression && b[u] != kEnd) ? (int32_t)((neg[b[u] >> 5] >> (b[u] & 31)) & 1u) : 0;
+        for (int u = 0; u < kMB; u++) q[u] = src[min(pos + u, last)];
     };
-    load(x, nx, 0, xb, xn);
-    load(y, ny, 0, yb, yn);
-    int32_t xp = kMB, yp = kMB, k = 0;
+    auto current = [&](const int32_t *q, int32_t n, int32_t pos, int32_t *b) {
+#pragma unroll
+        for (int u = 0; u < kMB; u++) b[u] = pos + u < n ? q[u] : kEnd;
+    };
+    // a block's flag words (loaded), then its flags (the words used)
+    auto words = [&](const int32_t *b, uint32_t *w) {
+#pragma unroll
+        for (int u = 0; u < kMB; u++) w[u] = neg[(b[u] != kEnd ? b[u] : 0) >> 5];
+    };
+    auto flags = [&](const int32_t *b, const uint32_t *w, int32_t *nb) {
+#pragma unroll
+        for (int u = 0; u < kMB; u++)
+            nb[u] = (compression && b[u] != kEnd) ? (int32_t)((w[u] >> (b[u] & 31)) & 1u) : 0;
+    };
+    uint32_t wx[kMB], wy[kMB];
+    fetch(x, nx, 0, xq);
+    fetch(y, ny, 0, yq);
+    current(xq, nx, 0, xb);
+    current(yq, ny, 0, yb);
+    words(xb, wx);
+    words(yb, wy);
+    __builtin_amdgcn_sched_barrier(0);  // the flag words go out before the next blocks: loads complete in order
+    fetch(x, nx, kMB, xq);
+    fetch(y, ny, kMB, yq);
+    __builtin_amdgcn_sched_barrier(0);
+    flags(xb, wx, xn);
+    flags(yb, wy, yn);
+    int32_t xp = 2 * kMB, yp = 2 * kMB, k = 0;  // the next positions to request
     while (xb[0] != kEnd || yb[0] != kEnd) {
         const int32_t u = xb[0], v = yb[0];
         if (u < v) {
@@ -514,8 +547,14 @@ __device__ inline int32_t merge_add_stream(const int32_t *__restrict__ x, int32_
             }
             xb[kMB - 1] = kEnd;
             xn[kMB - 1] = 0;
-            if (xb[0] == kEnd && xp < nx) {
-                load(x, nx, xp, xb, xn);
+            if (xb[0] == kEnd && xp - kMB < nx) {
+                current(xq, nx, xp - kMB, xb);
+                uint32_t w[kMB];
+                words(xb, w);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(x, nx, xp, xq);
+                __builtin_amdgcn_sched_barrier(0);
+                flags(xb, w, xn);
                 xp += kMB;
             }
         }
@@ -527,8 +566,14 @@ __device__ inline int32_t merge_add_stream(const int32_t *__restrict__ x, int32_
             }
             yb[kMB - 1] = kEnd;
             yn[kMB - 1] = 0;
-            if (yb[0] == kEnd && yp < ny) {
-                load(y, ny, yp, yb, yn);
+            if (yb[0] == kEnd && yp - kMB < ny) {
+                current(yq, ny, yp - kMB, yb);
+                uint32_t w[kMB];
+                words(yb, w);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(y, ny, yp, yq);
+                __builtin_amdgcn_sched_barrier(0);
+                flags(yb, w, yn);
                 yp += kMB;
             }
         }
