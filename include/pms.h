@@ -187,15 +187,15 @@ typedef struct {
                                (or all) are free; 1..64 */
     int32_t lane_flush;     /* a wave merges its lanes' pending entries once this many
                                (or all busy) lanes have a full pending set; 1..64 */
-    int32_t wide_blocks;    /* grid of the lane kernel's second pass (64-thread blocks, a
-                               4x longer buffer per lane) for the columns too long for the
+    int32_t wide_blocks;    /* grid of the lane kernel's second pass (64-thread blocks, an
+                               80-entry buffer per lane) for the columns too long for the
                                first pass; 1..65535 */
     int32_t lane_cap;       /* entries of the first pass's per-lane buffer in use (longer
-                               columns go to the second pass); 0..48 */
+                               columns go to the second pass); 0..39 */
     int32_t reserved;       /* 0 */
 } pms_tuning;
 
-/* The built-in setting: 1536, 512, 128, 0, 65536, 32, 16, 1024, 48. */
+/* The built-in setting: 2048, 512, 128, 0, 65536, 32, 16, 2048, 39. */
 pms_tuning pms_default_tuning(void);
 /* Make *t the context's setting for later reductions (NULL = the built-in
  * one).  PMS_ERR_INVALID_ARG, setting unchanged, when a field is out of range. */

@@ -32,14 +32,14 @@ from . import api
 
 # values swept per parameter (the built-in value of each is among them)
 GRID = {
-    "lane_blocks": (768, 1536, 3072),
+    "lane_blocks": (1024, 2048, 4096),
     "chain_blocks": (256, 512, 1024),
     "lane_steps": (32, 128, 512),
     "lane_steps_few": (0, 8, 32),
     "lane_refill": (16, 32, 48),
     "lane_flush": (8, 16, 32),
-    "wide_blocks": (512, 1024, 2048),
-    "lane_cap": (32, 40, 48),
+    "wide_blocks": (1024, 2048, 4096),
+    "lane_cap": (24, 32, 39),
     "graph_rounds": (0, 8),
 }
 

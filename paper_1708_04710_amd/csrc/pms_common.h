@@ -37,20 +37,25 @@ struct PendingEv {
     double bytes;  // algorithmic bytes of this launch (< 0: filled in later)
 };
 
+// Entries of the first lane chaining pass's per-lane LDS buffer: 39 x 128
+// lanes x 4 bytes lets 8 two-wave blocks share a CU's 160 KB, the 4 waves per
+// SIMD its registers allow.
+constexpr int kLaneCap = 39;
+
 // The chaining kernels' built-in shapes (measured on the 64^3 lower-star
 // and the batched Vietoris-Rips workloads).
 inline pms_tuning default_tuning()
 {
     pms_tuning t;
-    t.lane_blocks = 1536;
+    t.lane_blocks = 2048;  // 8 per CU
     t.chain_blocks = 512;  // 2 per CU
     t.lane_steps = 128;
     t.lane_steps_few = 0;
     t.lane_many = 65536;
     t.lane_refill = 32;
     t.lane_flush = 16;
-    t.wide_blocks = 1024;  // 4 per CU
-    t.lane_cap = 48;
+    t.wide_blocks = 2048;
+    t.lane_cap = kLaneCap;
     t.reserved = 0;
     return t;
 }
@@ -61,7 +66,7 @@ inline bool tuning_valid(const pms_tuning &t)
            t.lane_steps >= 0 && t.lane_steps <= (1 << 30) && t.lane_steps_few >= 0 &&
            t.lane_steps_few <= (1 << 30) && t.lane_many >= 0 && t.lane_refill >= 1 && t.lane_refill <= 64 &&
            t.lane_flush >= 1 && t.lane_flush <= 64 && t.wide_blocks >= 1 && t.wide_blocks <= 65535 &&
-           t.lane_cap >= 0 && t.lane_cap <= 48 && t.reserved == 0;
+           t.lane_cap >= 0 && t.lane_cap <= kLaneCap && t.reserved == 0;
 }
 
 struct Ctx {

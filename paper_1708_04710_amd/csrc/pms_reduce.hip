@@ -738,15 +738,16 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // claimed) and takes the wave's next queued column, so short and long chains
 // share a wave without idling it.  Columns that meet a longer pivot or chain
 // longer than the step cap go on to the wavefront kernel.  The kernel runs in
-// two passes: the first (k_chain_lane, 48 entries per lane, two waves per
+// two passes: the first (k_chain_lane, kLaneCap = 39 entries per lane, two waves per
 // block) takes the round's queued columns and hands those that outgrow its
-// buffer to the second (k_chain_wide, 128 entries per lane, one wave per
+// buffer to the second (k_chain_wide, 80 entries per lane, one wave per
 // block: fewer lanes per CU, for the fewer long columns); what outgrows that
-// goes to the wavefront kernel too.
+// goes to the wavefront kernel too.  Both passes wait on one record load per
+// step, so their speed follows the lanes resident per CU: the buffer sizes
+// are those at which LDS allows as many waves as the registers do.
 constexpr int kLaneThreads = 128;
-constexpr int kLaneCap = 48;
 constexpr int kWideThreads = 64;
-constexpr int kWideCap = 128;
+constexpr int kWideCap = 80;
 constexpr int kLaneP = 16;
 // The grid, the step caps and the refill / merge thresholds come from the
 // context's pms_tuning.  A lane hands a longer chain to a wavefront, whose
@@ -802,9 +803,17 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
         p[kLaneP - 1] = -1;
         np--;
     };
-    // the low of W: equal tops of B and P cancel
+    // the low of W: an equal pair on top of P cancels (1 + 1 = 0), and so do
+    // equal tops of B and P
     auto top = [&]() -> int32_t {
         for (;;) {
+            if (p[0] >= 0 && p[0] == p[1]) {
+#pragma unroll
+                for (int u = 0; u < kLaneP - 2; u++) p[u] = p[u + 2];
+                p[kLaneP - 2] = p[kLaneP - 1] = -1;
+                np -= 2;
+                continue;
+            }
             const int32_t bt = LB > 0 ? LW(LB - 1) : -1;
             if (p[0] != bt) return p[0] > bt ? p[0] : bt;
             if (bt < 0) return -1;
@@ -812,30 +821,34 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
             LB--;
         }
     };
-    // P := P xor {x}; x = -2 (above the -1 padding, below every row) leaves P
-    // as it is, so lanes with fewer toggles run the same instructions
+    // P := P + {x}: x is inserted in order even when P holds it already, the
+    // equal entries then sit side by side and cancel when they reach the top
+    // of P or are merged (P is W's toggles counted mod 2).  One max and one
+    // min per entry; x = -2 (above the -1 padding, below every row) leaves P
+    // as it is, so lanes with fewer toggles run the same instructions.
     auto toggle = [&](int32_t x) {
-        bool pres = false;
-#pragma unroll
-        for (int u = 0; u < kLaneP; u++) pres = pres || p[u] == x;
-        int32_t q[kLaneP];
+        int32_t c = x;
 #pragma unroll
         for (int u = 0; u < kLaneP; u++) {
-            const int32_t nxt = u + 1 < kLaneP ? p[u + 1] : -1;
-            const int32_t prv = u > 0 ? p[u - 1] : 0x7FFFFFFF;
-            q[u] = p[u] > x ? p[u] : (pres ? nxt : (prv < x ? prv : x));
+            const int32_t hi = max(p[u], c);
+            c = min(p[u], c);
+            p[u] = hi;
         }
-#pragma unroll
-        for (int u = 0; u < kLaneP; u++) p[u] = q[u];
-        np += x < 0 ? 0 : (pres ? -1 : 1);
+        np += x < 0 ? 0 : 1;
     };
     // B := B xor P in place, from the top down (needs LB + np <= cap);
     // cancelled pairs close the gap by moving the merged top part down
     auto flush = [&]() {
         int32_t r = LB - 1, w = LB + np - 1, c = 0;
+        bool pair = false;  // p[u] is the second of an equal pair of P, skipped with the first
 #pragma unroll
         for (int u = 0; u < kLaneP; u++) {
-            if (u < np) {
+            if (u < np && pair) {
+                pair = false;
+            } else if (u < np && u + 1 < np && p[u] == p[(u + 1) & (kLaneP - 1)]) {
+                pair = true;  // x + x = 0: neither enters B (counted like a cancellation)
+                c++;
+            } else if (u < np) {
                 const int32_t x = p[u];
                 int32_t y = r >= 0 ? LW(r) : -1;
                 while (y > x) {
@@ -898,9 +911,14 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
                 const long long o = cb + incl - need;
                 int32_t *out = d.arena + o;
                 int32_t w = 0, r = 0;
+                bool pair = false;  // as in the merge phase: equal pairs of P cancel
 #pragma unroll
                 for (int u = kLaneP - 1; u >= 0; u--) {
-                    if (u < np) {
+                    if (u < np && pair) {
+                        pair = false;
+                    } else if (u < np && u >= 1 && p[u] == p[(u + kLaneP - 1) & (kLaneP - 1)]) {
+                        pair = true;
+                    } else if (u < np) {
                         const int32_t x = p[u];
                         while (r < LB && LW(r) < x) out[w++] = LW(r++);
                         if (r < LB && LW(r) == x) r++;  // 1 + 1 = 0

@@ -107,7 +107,7 @@ def test_invalid_settings_are_rejected_and_change_nothing(gpu, builtin_after):
     for bad in (dict(lane_refill=0), dict(lane_refill=65), dict(lane_flush=0), dict(lane_flush=65),
                 dict(lane_blocks=0), dict(lane_blocks=65536), dict(chain_blocks=0), dict(chain_blocks=65536),
                 dict(lane_steps=-1), dict(lane_steps_few=(1 << 30) + 1), dict(lane_many=-1),
-                dict(wide_blocks=0), dict(wide_blocks=65536), dict(lane_cap=-1), dict(lane_cap=49)):
+                dict(wide_blocks=0), dict(wide_blocks=65536), dict(lane_cap=-1), dict(lane_cap=40)):
         with pytest.raises(_binding.PmsError) as e:
             api.set_tuning(bad, device=gpu)
         assert e.value.status == _binding.PMS_ERR_INVALID_ARG, bad
@@ -145,10 +145,10 @@ def test_time_candidates_rejects_a_bad_candidate_before_running(gpu, builtin_aft
 def test_autotune_search_and_cache(gpu, builtin_after, tmp_path):
     f, low_ref = _circles(gpu)
     path = tmp_path / "tune.json"
-    grid = {"lane_blocks": (768, 1536), "lane_steps_few": (8, 0), "graph_rounds": (0, 4)}
+    grid = {"lane_blocks": (1024, 2048), "lane_steps_few": (8, 0), "graph_rounds": (0, 4)}
     rec = autotune.autotune(f, count=4, cache=str(path), reps=1, grid=grid)
     assert not rec["cached"] and rec["scored"] == 6
-    assert rec["tuning"]["lane_blocks"] in (768, 1536) and rec["graph_rounds"] in (0, 4)
+    assert rec["tuning"]["lane_blocks"] in (1024, 2048) and rec["graph_rounds"] in (0, 4)
     assert api.get_tuning(device=gpu) == rec["tuning"]
     stored = json.load(open(path))
     assert stored[rec["key"]]["tuning"] == rec["tuning"]
