@@ -100,6 +100,8 @@ def measured_traffic(kernel):
 
 
 def _timed(fn, torch, reps=3):
+    """Best of `reps` timed calls after one warm-up (both sides of every
+    batched-vs-plain comparison are timed alike)."""
     fn()  # warm-up (allocations, first launches)
     ts = []
     for _ in range(reps):
@@ -151,7 +153,7 @@ def batched_vs_plain(api, autograd, synth, torch, dev, tune):
     _tune(tune, f, len(clouds))
     tb = _timed(batch3, torch)
     _tune(tune, f1)
-    tp = _timed(plain3, torch, reps=1)
+    tp = _timed(plain3, torch)
     out["vr512"] = {"clouds": len(clouds), "m": meta["m"], "rounds": meta["rounds"], "additions": meta["adds"],
                     "batched_s": round(tb, 5), "plain_s": round(tp, 5), "speedup": round(tp / tb, 3),
                     "batched_simplices_per_s": meta["m"] / tb, "tuning_batched": rec_b, "tuning_plain": rec_p}
@@ -176,7 +178,7 @@ def batched_vs_plain(api, autograd, synth, torch, dev, tune):
     _tune(tune, f, x.shape[0])
     tb = _timed(batch4, torch)
     _tune(tune, f1)
-    tp = _timed(plain4, torch, reps=1)
+    tp = _timed(plain4, torch)
     out["circles64"] = {"clouds": int(x.shape[0]), "m": meta["m4"], "batched_with_backward_s": round(tb, 5),
                         "plain_reduce_only_s": round(tp, 5), "speedup": round(tp / tb, 3),
                         "batched_simplices_per_s": meta["m4"] / tb, "tuning_batched": rec_b,

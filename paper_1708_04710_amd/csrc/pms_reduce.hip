@@ -245,10 +245,7 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
 // negative (Thm. "Properties of beta_j" P.3), so its row can be compressed.
 __global__ void k_beta(Dev d, int compression)
 {
-    const XcdSplit xs = xcd_split((d.m + blockDim.x - 1) / blockDim.x);
-    for (int64_t t = xs.first; t < xs.end; t += xs.step) {
-        const int64_t j = t * blockDim.x + threadIdx.x;
-        if (j >= d.m) continue;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = d.col_ptr[j];
         int32_t b = -1;
         for (int64_t p = s + d.len[j] - 1; p >= s; p--) {
@@ -391,8 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
     const int32_t nA = d.cnt->n_cur;
     const int count_beta = d.cnt->round == 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
-    const XcdSplit xs = xcd_split(tiles);
-    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t q = tile * kBlock + threadIdx.x;
     I4 e = i4_fill(-1);
     int32_t j = -1, i = -1;
