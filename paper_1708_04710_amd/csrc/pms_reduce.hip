@@ -283,10 +283,14 @@ __global__ void k_low(Dev d, const int32_t *act)
         }
         const int32_t i = c[n - 1];
         d.low[j] = i;
-        // T only ever decreases: a plain read that already shows a smaller
-        // key saves the atomic (many columns share a low)
-        const unsigned long long key = t_key(round, j);
-        if (key < d.T[i]) atomicMin(&d.T[i], key);
+        // T (the leftmost column per low) is read only for lows without a
+        // known pivot (a pivot's low collides, and Phase II adds the pivot);
+        // T only ever decreases, so a plain read that already shows a
+        // smaller key saves the atomic (many columns share a low)
+        if (d.piv[i] < 0) {
+            const unsigned long long key = t_key(round, j);
+            if (key < d.T[i]) atomicMin(&d.T[i], key);
+        }
     }
 }
 
@@ -307,8 +311,9 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
         int8_t cl = kNotLive;  // the state as of this kernel, for the rest of the round
         if (d.state[j] == ST_ACTIVE) {
             const int32_t i = d.low[j];
-            const int32_t t = t_decode(d.T[i], round);
-            cl = (d.piv[i] >= 0 || t != j) ? 1 : 0;
+            // a known pivot of the low makes j collide; else T decides (k_low
+            // updated it for such lows this round)
+            cl = (d.piv[i] >= 0 || t_decode(d.T[i], round) != j) ? 1 : 0;
             if (cl) e.v[slot_of(d, j)] = i;
         }
         d.coll[q] = cl;
