@@ -19,6 +19,8 @@
 #include <stdint.h>
 
 #include <new>
+#include <algorithm>
+
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 #include <vector>
@@ -45,13 +47,17 @@ struct VrInst {
     int64_t E, T;       // edges and triangles of cloud b
 };
 
-constexpr int kLexBitsI = 27, kLexBitsF = 30;
+// The order key (value, dimension, lexicographic vertex tuple) in one
+// unsigned 64-bit word: the value on top (raw bits of a non-negative FP32
+// value, 31 bits; an integer squared distance, < 2^35), then 2 bits of
+// dimension, then lexb bits of the vertex tuple's rank a*n^2 + b*n + c
+// (lexb: enough for the batch's largest n^3).  A batch sorted in one pass
+// also carries its cloud above the key.
+constexpr int kValueBitsF = 31, kValueBitsI = 35;
 
-template <bool F32>
-__device__ inline unsigned long long vr_key(unsigned long long value, int dim, unsigned long long lex)
+__device__ inline unsigned long long vr_key(unsigned long long value, int dim, unsigned long long lex, int lexb)
 {
-    if (F32) return (value << 32) | ((unsigned long long)dim << 30) | lex;
-    return (value << 29) | ((unsigned long long)dim << 27) | lex;
+    return (value << (lexb + 2)) | ((unsigned long long)dim << lexb) | lex;
 }
 
 // Squared distances and adjacency, one thread per slot (a, b), a < b.
@@ -140,14 +146,16 @@ __global__ void k_vr_bounds(VrInst *inst, int32_t B, const int64_t *escan, const
 template <bool F32>
 __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, const unsigned long long *adj,
                           const int64_t *escan, const int64_t *tscan, unsigned long long *keys, uint16_t *cl,
-                          int maxdim)
+                          int maxdim, int lexb, int cshift)
 {
-    // cl (batches): the cloud of every key, for the sort by (cloud, key)
+    // cl (batches sorted in two passes): the cloud of every key; cshift > 0
+    // (batches sorted in one): the cloud goes into the key's bits from cshift
     const VrInst I = inst[blockIdx.y];
     const uint16_t cb = (uint16_t)blockIdx.y;
+    const unsigned long long ck = cshift > 0 ? (unsigned long long)blockIdx.y << cshift : 0ull;
     const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (sl < I.n) {
-        keys[I.col_base + sl] = vr_key<F32>(0, 0, (unsigned long long)sl);  // vertex sl
+        keys[I.col_base + sl] = ck | vr_key(0, 0, (unsigned long long)sl, lexb);  // vertex sl
         if (cl) cl[I.col_base + sl] = cb;
     }
     if (sl >= (int64_t)I.n * I.n) return;
@@ -159,7 +167,7 @@ __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, con
     const unsigned long long n = (unsigned long long)I.n;
     const unsigned long long vab = val[I.slot_base + sl];
     const int64_t pe = I.col_base + I.n + (escan[I.slot_base + sl] - I.e_first);
-    keys[pe] = vr_key<F32>(vab, 1, (unsigned long long)a * n + (unsigned long long)b);
+    keys[pe] = ck | vr_key(vab, 1, (unsigned long long)a * n + (unsigned long long)b, lexb);
     if (cl) cl[pe] = cb;
     if (maxdim < 2) return;
     int64_t pos = I.col_base + I.n + I.E + (tscan[I.slot_base + sl] - I.t_first);
@@ -176,7 +184,7 @@ __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, con
             v = v > vac ? v : vac;
             v = v > vbc ? v : vbc;
             if (cl) cl[pos] = cb;
-            keys[pos++] = vr_key<F32>(v, 2, ((unsigned long long)a * n + (unsigned long long)b) * n + (unsigned long long)c);
+            keys[pos++] = ck | vr_key(v, 2, ((unsigned long long)a * n + (unsigned long long)b) * n + (unsigned long long)c, lexb);
         }
     }
 }
@@ -196,9 +204,9 @@ __device__ inline int find_inst(const int64_t *col_base, int32_t B, int64_t p)
 // the facet counts of each tile (for col_ptr).
 template <bool F32>
 __global__ void __launch_bounds__(kBlock) k_vr_index(const VrInst *inst, const int64_t *col_base, int32_t B,
-                                                     const unsigned long long *keys, int64_t m, int32_t *vidx,
-                                                     int32_t *eidx, int8_t *dim, void *value, int32_t *verts,
-                                                     int64_t *tile_sum)
+                                                     const unsigned long long *keys, int64_t m, int lexb,
+                                                     int32_t *vidx, int32_t *eidx, int8_t *dim, void *value,
+                                                     int32_t *verts, int64_t *tile_sum)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t nf = 0;
@@ -206,10 +214,9 @@ __global__ void __launch_bounds__(kBlock) k_vr_index(const VrInst *inst, const i
         const int b = find_inst(col_base, B, p);
         const VrInst &I = inst[b];
         const unsigned long long key = keys[p];
-        const int lexb = F32 ? kLexBitsF : kLexBitsI;
         const unsigned long long lex = key & ((1ull << lexb) - 1ull);
         const int dm = (int)((key >> lexb) & 3ull);
-        const unsigned long long v = key >> (lexb + 2);
+        const unsigned long long v = (key >> (lexb + 2)) & ((1ull << (F32 ? kValueBitsF : kValueBitsI)) - 1ull);
         const unsigned long long n = (unsigned long long)I.n;
         int32_t x[3] = {-1, -1, -1};
         if (dm == 0) x[0] = (int32_t)lex;
@@ -229,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_vr_index(const VrInst *inst, const i
 
 template <bool F32>
 __global__ void __launch_bounds__(kBlock) k_vr_rows(const VrInst *inst, const int64_t *col_base, int32_t B,
-                                                    const unsigned long long *keys, int64_t m, int64_t nnz,
+                                                    const unsigned long long *keys, int64_t m, int lexb, int64_t nnz,
                                                     const int32_t *vidx, const int32_t *eidx, const int64_t *tile_off,
                                                     int64_t *col_ptr, int32_t *rows, int32_t *crit)
 {
@@ -240,7 +247,6 @@ __global__ void __launch_bounds__(kBlock) k_vr_rows(const VrInst *inst, const in
     if (p < m) {
         b = find_inst(col_base, B, p);
         const unsigned long long key = keys[p];
-        const int lexb = F32 ? kLexBitsF : kLexBitsI;
         const unsigned long long lex = key & ((1ull << lexb) - 1ull);
         dm = (int)((key >> lexb) & 3ull);
         const unsigned long long n = (unsigned long long)inst[b].n;
@@ -397,10 +403,21 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         return PMS_OK;
     }
     const dim3 g3((unsigned)((maxnn + kBlock - 1) / kBlock > 0 ? (maxnn + kBlock - 1) / kBlock : 1), (unsigned)B);
-    // batches: one stable sort of all keys (carrying their cloud) by key,
-    // then a stable sort by cloud, so each cloud's columns come out in key
-    // order; the whole device sorts, not one workgroup per cloud
-    const bool by_cloud = B > 1 && B <= 65536;
+    // key widths: lex for the largest cloud's n^3, the value's bits, and the
+    // cloud's when a batch is sorted in one pass
+    int64_t n_hi = 1;
+    for (int b = 0; b < B; b++) n_hi = std::max<int64_t>(n_hi, h[b].n);
+    int lexb = 1;
+    while (lexb < 62 && (1ll << lexb) < n_hi * n_hi * n_hi) lexb++;
+    const int keybits = (f32 ? kValueBitsF : kValueBitsI) + 2 + lexb;
+    int cbits = 1;
+    while ((1 << cbits) < B) cbits++;
+    // batches: the whole device sorts, not one workgroup per cloud.  When the
+    // cloud fits above the key, one sort of (cloud, key) words; else one
+    // stable sort of all keys (carrying their cloud) by key, then a stable
+    // sort by cloud, so each cloud's columns come out in key order
+    const bool one_pass = B > 1 && keybits + cbits <= 64;
+    const bool by_cloud = B > 1 && !one_pass && B <= 65536;
     uint16_t *cl = nullptr, *cl2 = nullptr;
     if (by_cloud) {
         cl = (uint16_t *)scratch(c, B_BUILD12, M * 2);
@@ -408,38 +425,39 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         if (!cl || !cl2) return set_err(c, PMS_ERR_OOM, "builder scratch");
     }
     if (f32)
-        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<true>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim);
+        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<true>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim,
+                   lexb, one_pass ? keybits : 0);
     else
-        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<false>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim);
+        PMS_LAUNCH(c, K_VR_TRI, 8.0 * m, k_vr_emit<false>, g3, kBlock, dinst, val, adj, ecnt, tcnt, keys, cl, maxdim,
+                   lexb, one_pass ? keybits : 0);
     PMS_LAUNCH(c, K_FILL, 0, k_vr_colbase, (unsigned)((B + 255) / 256), 256, dinst, B, colb, seg, seg + B);
     const unsigned long long *sorted = keys2;
     {
         hipEvent_t e0 = nullptr;
         if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
         size_t tb = 0;
-        if (B == 1) {
-            PMS_HIP(rocprim::radix_sort_keys(nullptr, tb, keys, keys2, (size_t)m, 0, 64, s));
+        if (B == 1 || one_pass) {
+            const int bits = keybits + (one_pass ? cbits : 0);
+            PMS_HIP(rocprim::radix_sort_keys(nullptr, tb, keys, keys2, (size_t)m, 0, bits, s));
             void *tmps = scratch(c, B_AGG, tb);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-            PMS_HIP(rocprim::radix_sort_keys(tmps, tb, keys, keys2, (size_t)m, 0, 64, s));
+            PMS_HIP(rocprim::radix_sort_keys(tmps, tb, keys, keys2, (size_t)m, 0, bits, s));
         } else if (by_cloud) {
-            int cbits = 1;
-            while ((1 << cbits) < B) cbits++;
             size_t tb2 = 0;
-            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, cl, cl2, (size_t)m, 0, 64, s));
+            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
             PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
             void *tmps = scratch(c, B_AGG, tb > tb2 ? tb : tb2);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, cl, cl2, (size_t)m, 0, 64, s));
+            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
             PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
             sorted = keys;
         } else {
             PMS_HIP(rocprim::segmented_radix_sort_keys(nullptr, tb, keys, keys2, (unsigned)m, (unsigned)B, seg,
-                                                       seg + B, 0, 64, s));
+                                                       seg + B, 0, keybits, s));
             void *tmps = scratch(c, B_AGG, tb);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
             PMS_HIP(rocprim::segmented_radix_sort_keys(tmps, tb, keys, keys2, (unsigned)m, (unsigned)B, seg, seg + B,
-                                                       0, 64, s));
+                                                       0, keybits, s));
         }
         if (c->prof_on) {
             hipEvent_t e1 = prof_event(c);
@@ -448,18 +466,18 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         }
     }
     if (f32)
-        PMS_LAUNCH(c, K_VR_INDEX, 41.0 * m, k_vr_index<true>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, vidx,
+        PMS_LAUNCH(c, K_VR_INDEX, 41.0 * m, k_vr_index<true>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, lexb, vidx,
                    eidx, f->dim, f->value, f->verts, tsum);
     else
-        PMS_LAUNCH(c, K_VR_INDEX, 45.0 * m, k_vr_index<false>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, vidx,
+        PMS_LAUNCH(c, K_VR_INDEX, 45.0 * m, k_vr_index<false>, (unsigned)tiles, kBlock, dinst, colb, B, sorted, m, lexb, vidx,
                    eidx, f->dim, f->value, f->verts, tsum);
     PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * tiles, k_scan_i64, 1, 1024, tsum, tiles);
     if (f32)
         PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<true>, (unsigned)tiles, kBlock, dinst, colb, B, sorted,
-                   m, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
+                   m, lexb, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
     else
         PMS_LAUNCH(c, K_VR_ROWS, 24.0 * m + 8.0 * nnz, k_vr_rows<false>, (unsigned)tiles, kBlock, dinst, colb, B, sorted,
-                   m, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
+                   m, lexb, nnz, vidx, eidx, tsum, f->col_ptr, f->rows, f->crit);
     PMS_HIP(hipGetLastError());
     PMS_HIP(hipStreamSynchronize(s));
     if (c->prof_on) prof_flush(c);
