@@ -28,7 +28,10 @@ peak; the per-kernel times come from a second pass of the same K steps
 with a HIP event pair around every launch (the events slow the step, so
 ``value`` and ``ms_per_step`` come from the first pass, without them).
 ``phases`` splits the step (build, reduction alone, the rest) and prices
-the whole step's bytes against the peak.  ``cpu_baseline`` times the
+the whole step's bytes against the peak.  ``multiscale`` gives the paper's
+per-iteration measures (Sec. 4) from one more reduction with diagnostics:
+relative l1-error of low (eq. "rel_error"), proportion of unreduced
+columns and precision of the essential estimate, per round.  ``cpu_baseline`` times the
 CPU oracle (filtration build + standard reduction) on the same grid.
 """
 from __future__ import annotations
@@ -191,11 +194,11 @@ def batched_vs_plain(api, autograd, synth, torch, dev, tune):
 PROFILE_CMDS = [
     "python3 bench.py --steps 10 --warmup 2 --tune-cache <C>",
     "rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o ls64 -- python3 bench.py --steps 3 "
-    "--warmup 1 --no-cpu-baseline --no-batched --calibrate-copy --tune-cache <C>",
+    "--warmup 1 --no-cpu-baseline --no-batched --no-multiscale --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o f -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy --tune-cache <C>",
+    "--no-cpu-baseline --no-batched --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o w -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --calibrate-copy --tune-cache <C>",
+    "--no-cpu-baseline --no-batched --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
 ]
 COPY_BYTES = 256 << 20
 
@@ -304,6 +307,7 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of autotuned shapes by size class (read, and written on a miss)")
     ap.add_argument("--no-autotune", action="store_true", help="run with the library's built-in shapes")
+    ap.add_argument("--no-multiscale", action="store_true", help="skip the reduction with per-round diagnostics")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to scale rocprof's FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -397,6 +401,24 @@ def main():
               "pairs_gather_backward_ms": round(max(ms - build_ms - reduce_ms, 0.0), 3),
               "reduce_only_simplices_per_s": m / (reduce_ms / 1000.0)}
 
+    # the paper's per-iteration measures (Sec. 4) on this filtration: one more
+    # reduction with diagnostics, outside every timed region
+    multiscale = None
+    if not args.no_multiscale:
+        dres = api.reduce_filtration(f, diagnostics=True, **rkw)
+        ms_rows = api.multiscale(dres.round_stats, m, int(dres.essential.numel()))
+
+        def first_round(pred):
+            return next((r["round"] for r in ms_rows if pred(r)), None)
+
+        multiscale = {
+            "rounds": dres.rounds,
+            "rounds_to_rel_l1_error": {f"1e-{k}": first_round(lambda r, k=k: r["rel_error"] <= 10.0 ** -k)
+                                       for k in (1, 2, 3, 4)},
+            "rounds_to_unreduced": {str(p): first_round(lambda r, p=p: r["unreduced"] <= p) for p in (0.5, 0.1, 0.01)},
+            "per_round": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for r in ms_rows],
+        }
+
     roof = None
     kernels = {}
     if prof:
@@ -451,6 +473,7 @@ def main():
                    "tuning": tune_rec},
         "roofline": roof,
         "phases": phases,
+        "multiscale": multiscale,
         "kernels": kernels,
         "cpu_baseline": None,
     }

@@ -108,7 +108,10 @@ typedef struct {
      * instead of one per round; rounds after convergence do nothing.  Used
      * only with max_rounds = 0 and the profiler off.  0 = one round at a time. */
     int32_t graph_rounds;
-    int32_t reserved;       /* 0 */
+    /* 1 = record the per-round diagnostics (pms_round_stats_read) and the
+     * essential estimate (pms_essential_estimate); runs one round at a time
+     * (no graph), with two extra passes over the columns per round. */
+    int32_t diagnostics;
     /* Initial capacity of the column arena in int32 entries; 0 = automatic.
      * A non-zero value reallocates the arena to exactly this size (the
      * arena still grows when fill-in exceeds it). */
@@ -164,6 +167,42 @@ pms_status pms_reduce(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *
 pms_status pms_reduce_batched(pms_ctx *ctx, int32_t count, const int64_t *inst_col_off, const pms_boundary *bnd,
                               const pms_options *opt, pms_result *res, int64_t *inst_pair_off, int64_t *inst_ess_off,
                               int32_t *pair_inst);
+
+/* ------------------------------------------------------------------------
+ * Multi-scale diagnostics (Sec. 4's measurements of the iteration).  With
+ * pms_options.diagnostics = 1 a reduction records one entry after Phase 0
+ * (round 0: beta known, no column added) and one after every round l,
+ * describing low^l, the lows at that point (a column's low with the rows of
+ * simplices known negative deleted, compression; -1 for a zero column):
+ *   - low_l1 = sum_j (low^l(j) + 1), ||low^l||_1 in the paper's 1-based
+ *     indexing.  Lows only decrease and end at low*, so the relative l1-error
+ *     of eq. "rel_error" is (low_l1 - ||low*||_1) / ||low*||_1, with
+ *     ||low*||_1 the last entry's low_l1 of a converged reduction;
+ *   - active: columns not yet reduced (neither a pivot nor zero), the
+ *     proportion of unreduced columns times m;
+ *   - ess_estimate = |E^l|, eq. "essential_iteration": E^0 = [m] and
+ *     E^{l+1} = (E^l minus the indices known paired -- columns known negative
+ *     and the lows of the pivots) minus {low^l(j)}.  By Lemma "Essential
+ *     estimation" Ess is a subset of every E^l; at convergence E = Ess.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t round;          /* l (0 = after Phase 0) */
+    int32_t active;         /* columns neither pivot nor zero */
+    int64_t new_pivots;     /* pivots found in the round */
+    int64_t additions;      /* column additions in the round */
+    int64_t xor_entries;    /* entries those additions read */
+    int64_t low_l1;         /* sum_j (low^l(j) + 1) */
+    int64_t ess_estimate;   /* |E^l| */
+} pms_round_stats;
+
+/* The entries recorded by the context's last reduction with diagnostics
+ * (host array out[cap]); *count receives their number (cap = 0 to ask). */
+pms_status pms_round_stats_read(pms_ctx *ctx, int32_t cap, pms_round_stats *out, int32_t *count);
+/* E^l of the last recorded entry as a bitmask: bit i of word i / 32 set iff
+ * i is in E^l.  bits: device, (m + 31) / 32 words; m must be the last
+ * reduction's.  A reduction stopped by max_rounds leaves the estimate of its
+ * last completed round. */
+pms_status pms_essential_estimate(pms_ctx *ctx, int64_t m, uint32_t *bits);
 
 /* ------------------------------------------------------------------------
  * Tuning.  Pivot chaining (an addition to Phase II of Sec. 3.1: a column

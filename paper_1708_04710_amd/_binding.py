@@ -30,7 +30,7 @@ STATUS_NAMES = {
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
-    "pms_reduce", "pms_reduce_batched", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
+    "pms_reduce", "pms_reduce_batched", "pms_round_stats_read", "pms_essential_estimate", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
     "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
@@ -46,8 +46,14 @@ class PmsOptions(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("compression", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("chain", ctypes.c_int32),
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("graph_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("graph_rounds", ctypes.c_int32), ("diagnostics", ctypes.c_int32),
                 ("arena_entries", ctypes.c_int64)]
+
+
+class PmsRoundStats(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("active", ctypes.c_int32), ("new_pivots", ctypes.c_int64),
+                ("additions", ctypes.c_int64), ("xor_entries", ctypes.c_int64), ("low_l1", ctypes.c_int64),
+                ("ess_estimate", ctypes.c_int64)]
 
 
 class PmsTuning(ctypes.Structure):
@@ -110,6 +116,11 @@ def load(path: str = LIB_PATH):
     lib.pms_reduce_batched.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                        ctypes.POINTER(PmsResult), P, P, P]
     lib.pms_reduce_batched.restype = ctypes.c_int
+    lib.pms_round_stats_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(PmsRoundStats),
+                                         ctypes.POINTER(ctypes.c_int32)]
+    lib.pms_round_stats_read.restype = ctypes.c_int
+    lib.pms_essential_estimate.argtypes = [P, ctypes.c_int64, P]
+    lib.pms_essential_estimate.restype = ctypes.c_int
     lib.pms_default_tuning.argtypes = []
     lib.pms_default_tuning.restype = PmsTuning
     lib.pms_set_tuning.argtypes = [P, ctypes.POINTER(PmsTuning)]

@@ -92,6 +92,10 @@ class ReduceResult:
     inst_pair_off: torch.Tensor | None = None
     inst_ess_off: torch.Tensor | None = None
     pair_inst: torch.Tensor | None = None
+    # diagnostics=True only: one dict per recorded round (round_stats) and
+    # the essential estimate of the last one (bool [m], essential_estimate)
+    round_stats: list | None = None
+    essential_estimate: torch.Tensor | None = None
 
 
 class Filtration:
@@ -213,9 +217,9 @@ def _dptr(t):
 
 
 def _options(variant=0, compression=True, max_rounds=0, chain=True, tail_active=1024, validate=True,
-             arena_entries=0, graph_rounds=0):
+             arena_entries=0, graph_rounds=0, diagnostics=False):
     return B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
-                        int(bool(validate)), graph_rounds, 0, arena_entries)
+                        int(bool(validate)), graph_rounds, int(bool(diagnostics)), arena_entries)
 
 
 def _outputs(dev, m, outputs):
@@ -263,7 +267,54 @@ def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off
                                     pinst.data_ptr() if outputs else None)
         extra = dict(inst_pair_off=poff, inst_ess_off=eoff, pair_inst=pinst[:res.n_pairs] if outputs else None)
     B.check(ctx, st)
+    if kw.get("diagnostics"):
+        extra.update(round_stats=round_stats(dev), essential_estimate=essential_estimate(m, dev))
     return _result(res, t, **extra)
+
+
+def round_stats(device=None) -> list:
+    """The per-round records of the last reduction with ``diagnostics=True``
+    on the context of ``device`` (``pms_round_stats_read``), also after one
+    stopped by ``max_rounds``: dicts with round, active, new_pivots,
+    additions, xor_entries, low_l1 (sum of low + 1) and ess_estimate (|E|)."""
+    dev = _dev(device)
+    ctx = _ctx(dev)
+    lib = B.load()
+    n = ctypes.c_int32(0)
+    B.check(ctx, lib.pms_round_stats_read(ctx, 0, None, ctypes.byref(n)))
+    arr = (B.PmsRoundStats * max(n.value, 1))()
+    B.check(ctx, lib.pms_round_stats_read(ctx, n.value, arr, ctypes.byref(n)))
+    return [{f: getattr(arr[i], f) for f, _ in B.PmsRoundStats._fields_} for i in range(n.value)]
+
+
+def essential_estimate(m: int, device=None) -> torch.Tensor:
+    """E of the last recorded round as a bool mask [m] (``pms_essential_estimate``)."""
+    dev = _dev(device)
+    ctx = _ctx(dev)
+    words = torch.zeros(max((m + 31) // 32, 1), dtype=torch.int32, device=dev)
+    B.check(ctx, B.load().pms_essential_estimate(ctx, m, words.data_ptr() if m else None))
+    bits = torch.arange(32, device=dev, dtype=torch.int32)
+    mask = ((words[:, None] >> bits[None, :]) & 1).reshape(-1)[:m]
+    return mask.to(torch.bool)
+
+
+def multiscale(stats: list, m: int, n_essential: int | None = None) -> list:
+    """The paper's per-iteration measures from ``round_stats`` of a
+    converged reduction: relative l1-error of low (eq. "rel_error", using
+    ||low*||_1 = the last entry's low_l1), proportion of unreduced columns,
+    and the precision |Ess| / |E| of the essential estimate."""
+    if not stats:
+        return []
+    final = stats[-1]["low_l1"]
+    ess = stats[-1]["ess_estimate"] if n_essential is None else n_essential
+    out = []
+    for s in stats:
+        out.append({"round": s["round"],
+                    "rel_error": (s["low_l1"] - final) / final if final else 0.0,
+                    "unreduced": s["active"] / m if m else 0.0,
+                    "ess_precision": ess / s["ess_estimate"] if s["ess_estimate"] else 1.0,
+                    "additions": s["additions"]})
+    return out
 
 
 # ------------------------------------------------------------------ tuning

@@ -74,6 +74,9 @@ struct Counters {
     unsigned long long chain_bytes;  // algorithmic bytes moved by k_chain
     unsigned long long lane_bytes;   // algorithmic bytes moved by k_chain_lane
     unsigned long long wide_bytes;   // algorithmic bytes moved by k_chain_wide
+    unsigned long long diag_low_l1;  // diagnostics: sum_j (low(j) + 1)
+    unsigned long long diag_ess;     // diagnostics: |E|
+    unsigned long long diag_active;  // diagnostics: columns neither pivot nor zero
     int32_t error;       // 1 = not compatible
     int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
@@ -133,6 +136,7 @@ struct Dev {
     int64_t cq_slice;
     int32_t *wq;       // columns handed from the lane chain passes to the wavefront kernel
     int32_t *wq2;      // columns the first lane pass hands to the wide one (too long for its buffer)
+    uint32_t *ess;     // diagnostics: the essential estimate E as a bitmask (null when off)
 };
 
 constexpr int kStripe = 64;
@@ -1604,6 +1608,64 @@ __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, c
     }
 }
 
+// ---------------------------------------------------------------- diagnostics
+__global__ void k_diag_reset(Dev d)
+{
+    d.cnt->diag_low_l1 = 0;
+    d.cnt->diag_ess = 0;
+    d.cnt->diag_active = 0;
+}
+
+// low^l of every column (-1 for zero and cleared columns; an active column's
+// low with known-negative rows trimmed, as k_low will), summed as
+// low^l(j) + 1; E loses the columns known negative (pivots, beta_j defined)
+// and every low^l(j): the paired rows of the pivots and the lows of the
+// columns still active (eq. "essential_iteration").
+__global__ void __launch_bounds__(kBlock) k_diag_update(Dev d, int compression)
+{
+    int64_t l1 = 0, act = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t st = d.state[j];
+        int32_t lo = -1;
+        if (st == ST_PIVOT) {
+            lo = d.low[j];
+        } else if (st == ST_ACTIVE) {
+            int32_t n = d.len[j];
+            const int32_t *c = col_base(d, d.off[j]);
+            if (compression)
+                while (n > 0 && is_neg(d.neg, c[n - 1])) n--;
+            lo = n > 0 ? c[n - 1] : -1;
+            act += lo >= 0 ? 1 : 0;
+        }
+        l1 += (int64_t)lo + 1;
+        if (st == ST_PIVOT || d.beta[j] >= 0) atomicAnd(&d.ess[j >> 5], ~(1u << (j & 31)));
+        if (lo >= 0) atomicAnd(&d.ess[lo >> 5], ~(1u << (lo & 31)));
+    }
+    const int64_t bl1 = block_sum64(l1), bact = block_sum64(act);
+    if (threadIdx.x == 0) {
+        atomicAdd(&d.cnt->diag_low_l1, (unsigned long long)bl1);
+        atomicAdd(&d.cnt->diag_active, (unsigned long long)bact);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_diag_count(Dev d, int64_t nwords)
+{
+    int64_t n = 0;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwords; w += (int64_t)gridDim.x * blockDim.x)
+        n += __popc(d.ess[w]);
+    const int64_t bn = block_sum64(n);
+    if (threadIdx.x == 0) atomicAdd(&d.cnt->diag_ess, (unsigned long long)bn);
+}
+
+// E^0 = [m]: every bit of the first m set
+__global__ void k_diag_init(uint32_t *ess, int64_t m, int64_t nwords)
+{
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwords; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rest = m - w * 32;
+        ess[w] = rest >= 32 ? ~0u : ((1u << rest) - 1u);
+    }
+}
+
 __global__ void k_round_init(Dev d, int32_t m)
 {
     d.cnt->n_cur = m;
@@ -1833,7 +1895,16 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     res->rounds = 0;
     res->phase0_pivots = 0;
     res->additions = res->xor_entries = 0;
-    if (m == 0) return PMS_OK;
+    c->diag.clear();
+    c->diag_m = -1;
+    const bool diag = opt->diagnostics != 0;
+    if (m == 0) {
+        if (diag) {
+            c->diag.push_back(pms_round_stats{0, 0, 0, 0, 0, 0, 0});
+            c->diag_m = 0;
+        }
+        return PMS_OK;
+    }
 
     // nnz (host needs it only to size the arena)
     int64_t nnz = 0;
@@ -1962,16 +2033,50 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
         // act, state, act_next
         PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an);
-        if (c->prof_on || trace) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+        if (c->prof_on || trace || diag) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
         PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, 1, d);
         return PMS_OK;
     };
+    // diagnostics after Phase 0 and after each round: low^l's l1 norm, the
+    // unreduced columns and the essential estimate, read with the round's counters
+    auto launch_diag = [&]() -> pms_status {
+        PMS_LAUNCH(c, K_FILL, 0, k_diag_reset, 1, 1, d);
+        PMS_LAUNCH(c, K_FILL, 13.0 * dm, k_diag_update, gm, kBlock, d, opt->compression);
+        PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_diag_count, grid_for(nwords, kBlock, 65536), kBlock, d, nwords);
+        return PMS_OK;
+    };
+    unsigned long long diag_adds = 0, diag_xe = 0, diag_np = 0;
+    auto record_diag = [&](int32_t r) {
+        pms_round_stats e;
+        e.round = r;
+        e.active = (int32_t)h->diag_active;
+        e.new_pivots = (int64_t)((unsigned long long)h->new_pivots - diag_np);
+        e.additions = (int64_t)(h->additions - diag_adds);
+        e.xor_entries = (int64_t)(h->xor_entries - diag_xe);
+        e.low_l1 = (int64_t)h->diag_low_l1;
+        e.ess_estimate = (int64_t)h->diag_ess;
+        diag_np = (unsigned long long)h->new_pivots;
+        diag_adds = h->additions;
+        diag_xe = h->xor_entries;
+        c->diag.push_back(e);
+    };
+    if (diag) {
+        d.ess = (uint32_t *)scratch(c, B_ESS, (size_t)nwords * 4);
+        if (!d.ess) return set_err(c, PMS_ERR_OOM, "diagnostics scratch");
+        PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_diag_init, grid_for(nwords, kBlock, 65536), kBlock, d.ess, m, nwords);
+        pms_status sd = launch_diag();
+        if (sd != PMS_OK) return sd;
+        PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        PMS_HIP(hipStreamSynchronize(st));
+        record_diag(0);
+        c->diag_m = m;
+    }
 
     // Graph mode: `graph_rounds` rounds (rounded up to even, so the active
     // list ends where it started) captured once into a HIP graph and
     // replayed, one host synchronisation per replay; rounds after
     // convergence find no active column and return at once.
-    const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && opt->max_rounds == 0)
+    const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && !diag && opt->max_rounds == 0)
                             ? (opt->graph_rounds + 1) & ~1 : 0;
     if (graph_k > 0) {
         // fixed grids: enough blocks to fill the device, looping over tiles
@@ -2061,10 +2166,15 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         const int64_t tiles = (nA + kBlock - 1) / kBlock;
         pms_status sr = launch_round(act, act_next, tiles, (double)nA);
         if (sr != PMS_OK) return sr;
+        if (diag) {
+            sr = launch_diag();
+            if (sr != PMS_OK) return sr;
+        }
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
         PMS_HIP(hipStreamSynchronize(st));
         round++;
+        if (diag) record_diag((int32_t)round);
         if (c->prof_on) {
             c->pend[xor_slot].bytes = (double)(h->xor_bytes - xor_bytes_prev);
             xor_bytes_prev = h->xor_bytes;
@@ -2204,7 +2314,7 @@ pms_options pms_default_options(void)
     o.tail_active = 1024;
     o.validate = 1;
     o.graph_rounds = 0;
-    o.reserved = 0;
+    o.diagnostics = 0;
     o.arena_entries = 0;
     return o;
 }
@@ -2312,7 +2422,7 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "null col_ptr / rows / low_star");
     pms_options o = opt ? *opt : pms_default_options();
     if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0 || o.graph_rounds < 0 ||
-        o.graph_rounds > 1024)
+        o.graph_rounds > 1024 || o.diagnostics < 0 || o.diagnostics > 1)
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
     pms_status s = pms::reduce_impl(c, bnd, &o, res);
@@ -2320,6 +2430,33 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         res->n_pairs = res->n_essential = 0;
     }
     return s;
+}
+
+pms_status pms_round_stats_read(pms_ctx *c, int32_t cap, pms_round_stats *out, int32_t *count)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!count || cap < 0 || (cap > 0 && !out))
+        return pms::set_err(c, PMS_ERR_INVALID_ARG, "null count, negative cap, or null out with cap > 0");
+    *count = (int32_t)c->diag.size();
+    const int32_t n = cap < *count ? cap : *count;
+    for (int32_t i = 0; i < n; i++) out[i] = c->diag[(size_t)i];
+    return PMS_OK;
+}
+
+pms_status pms_essential_estimate(pms_ctx *c, int64_t m, uint32_t *bits)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (c->diag_m < 0) return pms::set_err(c, PMS_ERR_INVALID_ARG, "no reduction with diagnostics on this context");
+    if (m != c->diag_m) return pms::set_err(c, PMS_ERR_INVALID_ARG, "m is not that of the last reduction with diagnostics");
+    if (m == 0) return PMS_OK;
+    if (!bits) return pms::set_err(c, PMS_ERR_INVALID_ARG, "null bits");
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    const size_t bytes = (size_t)((m + 31) / 32) * 4;
+    PMS_HIP(hipMemcpyAsync(bits, c->b[pms::B_ESS].p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    PMS_HIP(hipStreamSynchronize(c->stream));
+    return PMS_OK;
 }
 
 pms_tuning pms_default_tuning(void) { return pms::default_tuning(); }

@@ -45,3 +45,6 @@ def test_options_layout_and_defaults():
     # no context: the error text is static, and a null handle is rejected
     assert lib.pms_last_error(None) == b"no context"
     assert lib.pms_reduce(None, None, None, None) == _binding.PMS_ERR_INVALID_ARG
+    assert o.diagnostics == 0 and ctypes.sizeof(_binding.PmsRoundStats) == 48
+    assert lib.pms_round_stats_read(None, 0, None, None) == _binding.PMS_ERR_INVALID_ARG
+    assert lib.pms_essential_estimate(None, 0, None) == _binding.PMS_ERR_INVALID_ARG
