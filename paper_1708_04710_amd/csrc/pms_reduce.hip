@@ -761,9 +761,10 @@ constexpr int kLaneP = 16;
 // move on early (they are the critical path, tn.lane_steps_few).
 constexpr int kLaneChunk = 1024;   // arena entries a wave claims at a time for its write-backs
 
-template <int kCap, int kThreads, bool kWide>
-__device__ __forceinline__ void lane_chain(const Dev &d, int compression, int trace, const pms_tuning &tn)
+template <int kCap, int kThreads, bool kWide, bool kTrace>
+__device__ __forceinline__ void lane_chain(const Dev &d, int compression, const pms_tuning &tn)
 {
+    constexpr bool trace = kTrace;  // the trace counters exist only in the traced instantiation
     __shared__ int32_t sL[kCap * kThreads];
     __shared__ int32_t s_pre[kPart];
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -785,7 +786,10 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
     // LDS room (tn.lane_cap), handing longer columns to the wide pass
     const int32_t cap = kWide ? kCap : min(kCap, tn.lane_cap);
     const unsigned gwave = blockIdx.x * (kThreads / kWave) + (unsigned)bcast_first(tid / kWave);
-    int64_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0, tsl = 0, tg16 = 0, tg32 = 0;
+    // per-lane counts (32 bits: a lane makes a few thousand steps per launch;
+    // the wave sums below are 64-bit)
+    uint32_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0;
+    int64_t tsl = 0, tg16 = 0, tg32 = 0;
     // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
     // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ... (shared
     // by the whole grid: chain lengths vary, and fixed parts would idle at the end)
@@ -940,7 +944,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
                     d.low[j] = -1;
                     d.state[j] = ST_ZERO;  // column j is positive
                 }
-                by += 4 * (int64_t)w + 16;
+                by += 4u * (uint32_t)w + 16u;
             }
             if (room) cb += wtot;
             // hand the bailing columns over to the wavefront kernel, or (first
@@ -1007,7 +1011,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
             const bool fresh = ((finm >> lane) & 1ull) && !fin;
             if (fresh) {
                 const int32_t L = d.len[j];
-                by += 16 + 4 * (int64_t)L;
+                by += 16u + 4u * (uint32_t)L;
                 np = 0;
 #pragma unroll
                 for (int u = 0; u < kLaneP; u++) p[u] = -1;
@@ -1073,7 +1077,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
             if (go) {
                 steps++;
                 adds++;
-                xe += (int64_t)LB + np + kk + 1;
+                xe += (uint32_t)(LB + np + kk + 1);
                 by += 32;
                 if (trace) {
                     tsl += LB + np;
@@ -1111,10 +1115,10 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
     }
 #undef LW
     // counters: lane sums -> one atomic per wave
-    const int64_t wadds = wave_incl_sum64(adds), wxe = wave_incl_sum64(xe), wby = wave_incl_sum64(by),
-                  wb = wave_incl_sum64(bails);
+    const int64_t wadds = wave_incl_sum64((int64_t)adds), wxe = wave_incl_sum64((int64_t)xe),
+                  wby = wave_incl_sum64((int64_t)by), wb = wave_incl_sum64((int64_t)bails);
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
-                  wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64(towide) : 0;
+                  wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64((int64_t)towide) : 0;
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, gwave);
@@ -1136,14 +1140,16 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, int tr
     }
 }
 
-__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, int trace, pms_tuning tn)
+template <bool kTrace>
+__global__ void __launch_bounds__(kLaneThreads) k_chain_lane(Dev d, int compression, pms_tuning tn)
 {
-    lane_chain<kLaneCap, kLaneThreads, false>(d, compression, trace, tn);
+    lane_chain<kLaneCap, kLaneThreads, false, kTrace>(d, compression, tn);
 }
 
-__global__ void __launch_bounds__(kWideThreads) k_chain_wide(Dev d, int compression, int trace, pms_tuning tn)
+template <bool kTrace>
+__global__ void __launch_bounds__(kWideThreads) k_chain_wide(Dev d, int compression, pms_tuning tn)
 {
-    lane_chain<kWideCap, kWideThreads, true>(d, compression, trace, tn);
+    lane_chain<kWideCap, kWideThreads, true, kTrace>(d, compression, tn);
 }
 
 // Wavefront chaining, for the columns the lane kernel hands over (long
@@ -2018,11 +2024,19 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, gT, kBlock, d, a, opt->variant, opt->compression, opt->chain,
                    opt->tail_active);
         xor_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane, (unsigned)tn.lane_blocks, kLaneThreads, d, opt->compression,
-                   trace, tn);
+        if (trace)
+            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<true>, (unsigned)tn.lane_blocks, kLaneThreads, d,
+                       opt->compression, tn);
+        else
+            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<false>, (unsigned)tn.lane_blocks, kLaneThreads, d,
+                       opt->compression, tn);
         lane_slot = c->pend.size() - 1;
-        PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide, (unsigned)tn.wide_blocks, kWideThreads, d, opt->compression,
-                   trace, tn);
+        if (trace)
+            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<true>, (unsigned)tn.wide_blocks, kWideThreads, d,
+                       opt->compression, tn);
+        else
+            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<false>, (unsigned)tn.wide_blocks, kWideThreads, d,
+                       opt->compression, tn);
         wide_slot = c->pend.size() - 1;
         if (trace)
             PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
