@@ -157,6 +157,24 @@ __device__ inline int64_t arena_alloc(const Dev &d, unsigned p, int64_t n)
     return o + (unsigned long long)n <= end ? (int64_t)o : -1;
 }
 
+// Marks column j known negative (bit j of neg) where f holds; every lane of
+// the wave calls it.  When the active lanes hold 64 consecutive columns from
+// a 64-aligned base (one column per lane in index order), their bits are
+// combined per 32-bit word, one atomic per word instead of one per lane.
+__device__ inline void mark_neg(uint32_t *neg, int64_t j, bool f)
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int64_t jb = j - lane;
+    const int64_t jb0 = bcast_first64(jb);
+    if (__ballot(jb != jb0) == 0 && jb0 >= 0 && (jb0 & (kWave - 1)) == 0) {
+        const uint64_t bits = __ballot(f);
+        const uint32_t half = lane < 32 ? (uint32_t)bits : (uint32_t)(bits >> 32);
+        if (f && (lane & 31) == __ffs(half) - 1) atomicOr(&neg[(jb0 >> 5) + (lane >> 5)], half);
+    } else if (f) {
+        atomicOr(&neg[j >> 5], 1u << (j & 31));
+    }
+}
+
 __device__ inline bool is_neg(const uint32_t *neg, int32_t r)
 {
     return (neg[r >> 5] >> (r & 31)) & 1u;
@@ -257,10 +275,8 @@ __global__ void k_beta(Dev d, int compression)
             if (d.left[r] == (int32_t)j) { b = r; break; }  // rows ascending: first hit from the end is the max
         }
         d.beta[j] = b;
-        if (compression && b >= 0) {
-            atomicOr(&d.neg[j >> 5], 1u << (j & 31));
-            d.prec[j].k = -1;  // a negative row never gets a pivot record
-        }
+        if (compression && b >= 0) d.prec[j].k = -1;  // a negative row never gets a pivot record
+        if (compression) mark_neg(d.neg, j, b >= 0);
     }
 }
 
@@ -433,15 +449,13 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
             d.prec[i] = r;
             d.state[j] = ST_PIVOT;
             d.low_star[j] = i;
-            if (compression) {
-                atomicOr(&d.neg[j >> 5], 1u << (j & 31));
-                d.prec[j].k = -1;
-            }
+            if (compression) d.prec[j].k = -1;
             if (d.state[i] == ST_ACTIVE) d.state[i] = ST_CLEARED;  // clearing: sigma_i is positive
             np = 1;
             nb = by_beta ? 1 : 0;
         }
     }
+    if (compression) mark_neg(d.neg, j, np != 0);
     int32_t tnp;
     block_excl_sum32(np, &tnp);
     if (count_beta) {
