@@ -62,7 +62,7 @@ enum StatId {
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
     S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
-    S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY,
+    S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY, S_T_LLONG,
     S_NUM
 };
 
@@ -77,6 +77,7 @@ struct Counters {
     unsigned long long diag_low_l1;  // diagnostics: sum_j (low(j) + 1)
     unsigned long long diag_ess;     // diagnostics: |E|
     unsigned long long diag_active;  // diagnostics: columns neither pivot nor zero
+    unsigned long long arena_free;   // arena entries still free at the end of the round
     int32_t error;       // 1 = not compatible
     int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
@@ -148,13 +149,22 @@ __device__ inline void stat_add(const Dev &d, int id, unsigned long long v, unsi
 }
 
 // Bump allocation of n entries in partition p; -1 when the partition is full.
+// n entries from partition p, or, when p is full, from the next partition
+// with room (skipped by a plain read when full, so exhausted partitions take
+// no further atomics); -1 when every partition is full
 __device__ inline int64_t arena_alloc(const Dev &d, unsigned p, int64_t n)
 {
-    p &= kPart - 1;
-    const unsigned long long end =
-        p == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(p + 1) * d.part_size;
-    const unsigned long long o = atomicAdd(&d.part[p * 16], (unsigned long long)n);
-    return o + (unsigned long long)n <= end ? (int64_t)o : -1;
+    for (unsigned t = 0; t < (unsigned)kPart; t++) {
+        const unsigned q = (p + t) & (kPart - 1);
+        const unsigned long long end =
+            q == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(q + 1) * d.part_size;
+        if (t > 0 &&
+            __hip_atomic_load(&d.part[q * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (unsigned long long)n > end)
+            continue;
+        const unsigned long long o = atomicAdd(&d.part[q * 16], (unsigned long long)n);
+        if (o + (unsigned long long)n <= end) return (int64_t)o;
+    }
+    return -1;
 }
 
 // Marks column j known negative (bit j of neg) where f holds; every lane of
@@ -644,10 +654,8 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     if (threadIdx.x == 0) s_base = btot ? arena_alloc(d, (unsigned)tile, btot) : 0;
     __syncthreads();
     const int64_t bbase = s_base;
-    if (target && bbase < 0) {
-        atomicExch(&d.cnt->overflow, 1);
-        target = false;  // the column stays as it is this round
-    }
+    if (threadIdx.x == 0 && bbase < 0) atomicExch(&d.cnt->overflow, 1);  // once per block: one flag for all
+    if (target && bbase < 0) target = false;  // the column stays as it is this round
     int64_t adds = 0, xe = 0, by = q < nA ? 6 : 0;  // act, state, coll
     bool push = false;
     if (target) {
@@ -755,8 +763,10 @@ __device__ inline uint32_t wave_or32(uint32_t x)
 // iteration every busy lane takes one step, and a lane whose chain ends
 // writes its column back merged into the arena (from a chunk its wave
 // claimed) and takes the wave's next queued column, so short and long chains
-// share a wave without idling it.  Columns that meet a longer pivot or chain
-// longer than the step cap go on to the wavefront kernel.  The kernel runs in
+// share a wave without idling it.  A pivot with more entries than its record
+// holds is merged from its stored column into B in the merge phase, when B
+// has room for the result.  Columns that chain longer than the step cap go on
+// to the wavefront kernel.  The kernel runs in
 // two passes: the first (k_chain_lane, kLaneCap = 39 entries per lane, two waves per
 // block) takes the round's queued columns and hands those that outgrow its
 // buffer to the second (k_chain_wide, 80 entries per lane, one wave per
@@ -900,7 +910,9 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
     bool fin = true, bail = false;  // fin: no column in progress (finished, or never given one)
     bool roomb = false;             // the bail is for want of buffer room (first pass: to the wide one)
     bool wantf = false;             // P is full: this lane waits for a merge phase
+    bool wantl = false;             // a long pivot: merged from its column in the merge phase
     int64_t titer = 0, trefill = 0, tflush = 0, tbusy = 0;  // trace: wave iterations, phases, busy lanes
+    int64_t tlong = 0;                                       // trace: long-pivot steps
     for (;;) {
         if (trace) titer++;
         // finished lanes are written back and refilled together, once at
@@ -929,7 +941,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                 }
             }
             const bool room = wtot == 0 || ce - cb >= wtot;
-            if (wr && !room) atomicExch(&d.cnt->overflow, 1);  // progress dropped; the stored column stays valid
+            // progress dropped; the stored columns stay valid (one flag per wave)
+            if (!room && lane == 0) atomicExch(&d.cnt->overflow, 1);
             if (wr && room) {
                 const long long o = cb + incl - need;
                 int32_t *out = d.arena + o;
@@ -1031,6 +1044,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                 for (int u = 0; u < kLaneP; u++) p[u] = -1;
                 dirty = false;
                 wantf = false;
+                wantl = false;
                 steps = 0;
                 if (L > cap) {
                     bail = true;  // too long for a lane: straight to the next pass
@@ -1057,13 +1071,76 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
         // wait (the merge loop's trip count varies from lane to lane)
         {
             const uint64_t busy = __ballot(!fin);
-            const uint64_t nf = __ballot(!fin && wantf);
+            const uint64_t nf = __ballot(!fin && (wantf || wantl));
             if (trace) tbusy += __popcll(busy);
             if (nf && (__popcll(nf) >= tn.lane_flush || nf == busy)) {
                 if (trace) tflush++;
                 if (wantf) {
                     flush();
                     wantf = false;
+                }
+                if (wantl) {
+                    // a long pivot: W = B now, its top is the low.  Remove it
+                    // and merge the pivot's entries below its low (read from
+                    // the stored column) into B, from the top down
+                    wantl = false;
+                    if (LB <= 0 || LW(LB - 1) != i) {
+                        atomicExch(&d.cnt->bad_source, 2);
+                        dirty = false;
+                        fin = true;
+                    } else {
+                        LB--;
+                        const int32_t kk = lk.k - 1;
+                        const int32_t *g = col_base(d, d.off[lk.s]);
+                        int32_t r = LB - 1, w = LB + kk - 1, c = 0;
+                        for (int32_t q0 = kk - 1; q0 >= 0; q0 -= 8) {
+                            int32_t v[8];
+#pragma unroll
+                            for (int u = 0; u < 8; u++) v[u] = g[max(q0 - u, 0)];
+#pragma unroll
+                            for (int u = 0; u < 8; u++) {
+                                if (q0 - u >= 0) {
+                                    const int32_t x = v[u];
+                                    int32_t y = r >= 0 ? LW(r) : -1;
+                                    while (y > x) {
+                                        LW(w) = y;
+                                        w--;
+                                        r--;
+                                        y = r >= 0 ? LW(r) : -1;
+                                    }
+                                    if (y == x) {  // 1 + 1 = 0
+                                        r--;
+                                        c++;
+                                    } else {
+                                        LW(w) = x;
+                                        w--;
+                                    }
+                                }
+                            }
+                        }
+                        const int32_t topi = LB + kk - 1;
+                        if (c)
+                            for (int32_t e = w + 1; e <= topi; e++) LW(e - 2 * c) = LW(e);
+                        steps++;
+                        adds++;
+                        xe += (uint32_t)(LB + kk + 2);
+                        by += 44u + 4u * (uint32_t)lk.k;
+                        if (trace) {
+                            tsl += LB + 1;
+                            tlong++;
+                        }
+                        LB = LB + kk - 2 * c;
+                        dirty = true;
+                        const int32_t ni = top();
+                        if (ni >= i) {  // the low must drop; stop rather than spin
+                            atomicExch(&d.cnt->bad_source, 2);
+                            dirty = false;
+                            fin = true;
+                        } else {
+                            i = ni;
+                            if (i >= 0) lk = look_up(d, i);
+                        }
+                    }
                 }
             }
         }
@@ -1072,21 +1149,30 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
         // them cost more in exec-mask handling and register copies than the
         // selects themselves); only the search for the next low branches.
         {
-            const bool act = !fin && !wantf;
+            const bool act = !fin && !wantf && !wantl;
             const int32_t kk = lk.k - 1;
             const bool has = act && i >= 0;
             const bool piv = has && lk.s >= 0;
             const bool del = has && lk.s < 0 && compression && lk.k < 0;  // a known-negative row: delete it
             // W is zero, or no pivot owns its low: the chain ends here
             if (act && !piv && !del) fin = true;
-            const bool over = piv && (kk > kRecInline || steps >= step_cap || (np + kk > kLaneP && LB + np > cap));
+            // a longer pivot than its record holds is merged from its stored
+            // column in the wave's next merge phase (after P's merge), when B
+            // has room for the result
+            const bool lng = piv && kk > kRecInline;
+            const bool capx = piv && steps >= step_cap;
+            const bool roomx = piv && !capx && (lng ? LB + np + kk - 1 > cap : (np + kk > kLaneP && LB + np > cap));
+            const bool over = capx || roomx;
             if (over) {
                 bail = true;
-                roomb = !kWide && kk <= kRecInline && steps < step_cap;  // only room is lacking
+                roomb = !kWide && roomx;  // only room is lacking
                 fin = true;
             }
-            const bool full = piv && !over && np + kk > kLaneP;
-            if (full) wantf = true;  // P is full: wait for the wave's next merge phase
+            const bool full = piv && !over && (lng || np + kk > kLaneP);
+            if (full) {  // wait for the wave's next merge phase
+                wantf = np > 0 || !lng;
+                wantl = lng;
+            }
             const bool go = piv && !over && !full;
             if (go) {
                 steps++;
@@ -1132,7 +1218,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
     const int64_t wadds = wave_incl_sum64((int64_t)adds), wxe = wave_incl_sum64((int64_t)xe),
                   wby = wave_incl_sum64((int64_t)by), wb = wave_incl_sum64((int64_t)bails);
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
-                  wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64((int64_t)towide) : 0;
+                  wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64((int64_t)towide) : 0,
+                  wlg = trace ? wave_incl_sum64(tlong) : 0;
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, gwave);
@@ -1150,6 +1237,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
             stat_add(d, S_T_LSUML, (unsigned long long)wsl, gwave);
             stat_add(d, S_T_LGT16, (unsigned long long)wg16, gwave);
             stat_add(d, S_T_LGT32, (unsigned long long)wg32, gwave);
+            stat_add(d, S_T_LLONG, (unsigned long long)wlg, gwave);
         }
     }
 }
@@ -1698,6 +1786,14 @@ __global__ void k_round_end(Dev d)
 {
     if (d.cnt->n_cur > 0) d.cnt->round = d.cnt->round + 1;
     d.cnt->n_cur = d.cnt->n_next;
+    unsigned long long fr = 0;  // a partition past its end is full
+    for (int p = 0; p < kPart; p++) {
+        const unsigned long long end =
+            p == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(p + 1) * d.part_size;
+        const unsigned long long cur = d.part[p * 16];
+        fr += cur < end ? end - cur : 0;
+    }
+    d.cnt->arena_free = fr;
 }
 
 // Arena regrowth: copy every live arena column into a new arena.
@@ -2100,6 +2196,17 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         c->diag_m = m;
     }
 
+    // The arena grows (live columns copied into one twice as large) when a
+    // round runs it out, which drops that round's remaining progress, and
+    // before that happens: when the free part left after a round (or a graph
+    // replay of rounds) is less than twice what it took.
+    unsigned long long free_prev = d.arena_cap - d.part_base;
+    auto grow_early = [&](int32_t n_left) {
+        const unsigned long long took = free_prev > h->arena_free ? free_prev - h->arena_free : 0;
+        free_prev = h->arena_free;
+        return n_left > 0 && h->arena_free < 2 * took;
+    };
+
     // Graph mode: `graph_rounds` rounds (rounded up to even, so the active
     // list ends where it started) captured once into a HIP graph and
     // replayed, one host synchronisation per replay; rounds after
@@ -2172,9 +2279,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             if (e != hipSuccess) return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
             round = h->round;
             if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
-            if (h->overflow) {  // the arena moves: grow it (on the caller's stream) and capture again
+            if (h->overflow || grow_early(h->n_cur)) {  // the arena moves: grow it (on the caller's stream) and capture again
                 pms_status s = grow_arena(c, d, h);
                 if (s != PMS_OK) return s;
+                free_prev = d.arena_cap - d.part_base;
                 PMS_HIP(hipEventRecord(c->graph_ev, st));
                 PMS_HIP(hipStreamWaitEvent(gs, c->graph_ev, 0));
                 s = capture();
@@ -2223,14 +2331,14 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "pass %llu, wide steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
-                    "mean L %.1f, L>16 %llu, L>32 %llu; first lane pass: wave iterations %llu, refill phases %llu, "
+                    "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu; first lane pass: wave iterations %llu, refill phases %llu, "
                     "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
                     dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st,
-                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32],
+                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32], dl[S_T_LLONG],
                     dl[S_T_LITER], dl[S_T_LREFILL], dl[S_T_LFLUSH],
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
                     (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1));
@@ -2238,9 +2346,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
                                                                 : "internal: a chained addition did not lower the low");
-        if (h->overflow) {
+        if (h->overflow || grow_early(h->n_next)) {
             pms_status s = grow_arena(c, d, h);
             if (s != PMS_OK) return s;
+            free_prev = d.arena_cap - d.part_base;
         }
         nA_prev = h->n_next;
         nA = h->n_next;
