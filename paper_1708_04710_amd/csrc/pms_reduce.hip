@@ -62,7 +62,7 @@ enum StatId {
     // length, shader cycles per phase of a short-pivot step, flushes, lows from P
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
     S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
-    S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY, S_T_LLONG,
+    S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY, S_T_LLONG, S_T_LTOG, S_T_LTROUND,
     S_NUM
 };
 
@@ -737,6 +737,12 @@ __device__ inline Look look_up(const Dev &d, int32_t i)
     return r;
 }
 
+// median of three (selected to v_med3_i32 from this min/max form)
+__device__ __forceinline__ int32_t med3_i32(int32_t a, int32_t b, int32_t c)
+{
+    return max(min(a, b), min(max(a, b), c));
+}
+
 __device__ inline int32_t wave_sum32(int32_t x)
 {
 #pragma unroll
@@ -829,16 +835,11 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
     for (int u = 0; u < kLaneP; u++) p[u] = -1;
     bool dirty = false;
     Look lk{};
-    // P's top leaves it
-    auto shift_p = [&]() {
-#pragma unroll
-        for (int u = 0; u < kLaneP - 1; u++) p[u] = p[u + 1];
-        p[kLaneP - 1] = -1;
-        np--;
-    };
     // the low of W: an equal pair on top of P cancels (1 + 1 = 0), and so do
-    // equal tops of B and P
+    // equal tops of B and P.  Not unrolled: peeled copies of this loop turn
+    // into chains of register copies of P on the common path.
     auto top = [&]() -> int32_t {
+#pragma clang loop unroll(disable)
         for (;;) {
             if (p[0] >= 0 && p[0] == p[1]) {
 #pragma unroll
@@ -850,23 +851,25 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
             const int32_t bt = LB > 0 ? LW(LB - 1) : -1;
             if (p[0] != bt) return p[0] > bt ? p[0] : bt;
             if (bt < 0) return -1;
-            shift_p();
+#pragma unroll
+            for (int u = 0; u < kLaneP - 1; u++) p[u] = p[u + 1];
+            p[kLaneP - 1] = -1;
+            np--;
             LB--;
         }
     };
     // P := P + {x}: x is inserted in order even when P holds it already, the
     // equal entries then sit side by side and cancel when they reach the top
-    // of P or are merged (P is W's toggles counted mod 2).  One max and one
-    // min per entry; x = -2 (above the -1 padding, below every row) leaves P
-    // as it is, so lanes with fewer toggles run the same instructions.
+    // of P or are merged (P is W's toggles counted mod 2).  Slot u of the
+    // result is the median of x and the old slots u and u-1 (x clamped into
+    // [P[u], P[u-1]]): one v_med3 per slot, updated from the bottom up so P
+    // stays in the same registers.  x = -2 (above the -1 padding, below
+    // every row) leaves P as it is, so lanes with fewer toggles run the same
+    // instructions.
     auto toggle = [&](int32_t x) {
-        int32_t c = x;
 #pragma unroll
-        for (int u = 0; u < kLaneP; u++) {
-            const int32_t hi = max(p[u], c);
-            c = min(p[u], c);
-            p[u] = hi;
-        }
+        for (int u = kLaneP - 1; u >= 1; u--) p[u] = med3_i32(p[u], x, p[u - 1]);
+        p[0] = max(p[0], x);
         np += x < 0 ? 0 : 1;
     };
     // B := B xor P in place, from the top down (needs LB + np <= cap);
@@ -913,6 +916,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
     bool wantl = false;             // a long pivot: merged from its column in the merge phase
     int64_t titer = 0, trefill = 0, tflush = 0, tbusy = 0;  // trace: wave iterations, phases, busy lanes
     int64_t tlong = 0;                                       // trace: long-pivot steps
+    int64_t ttog = 0, ttround = 0;                           // trace: toggles (per lane), toggle rounds (per wave)
     for (;;) {
         if (trace) titer++;
         // finished lanes are written back and refilled together, once at
@@ -1197,6 +1201,10 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
 #pragma unroll
             for (int q = 0; q < kRecInline; q++) {
                 if (__ballot(go && q < kk) == 0) break;
+                if (trace) {
+                    ttog += go && q < kk ? 1 : 0;
+                    ttround++;
+                }
                 toggle(go && q < kk ? lk.e[q] : -2);
             }
             if (rm) {
@@ -1219,7 +1227,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                   wby = wave_incl_sum64((int64_t)by), wb = wave_incl_sum64((int64_t)bails);
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
                   wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64((int64_t)towide) : 0,
-                  wlg = trace ? wave_incl_sum64(tlong) : 0;
+                  wlg = trace ? wave_incl_sum64(tlong) : 0, wtg = trace ? wave_incl_sum64(ttog) : 0;
     if (lane == kWave - 1) {
         stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, gwave);
@@ -1238,6 +1246,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
             stat_add(d, S_T_LGT16, (unsigned long long)wg16, gwave);
             stat_add(d, S_T_LGT32, (unsigned long long)wg32, gwave);
             stat_add(d, S_T_LLONG, (unsigned long long)wlg, gwave);
+            stat_add(d, S_T_LTOG, (unsigned long long)wtg, gwave);
+            if (!kWide) stat_add(d, S_T_LTROUND, (unsigned long long)ttround, gwave);
         }
     }
 }
@@ -2331,14 +2341,14 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "pass %llu, wide steps %llu, handed to waves "
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
-                    "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu; first lane pass: wave iterations %llu, refill phases %llu, "
+                    "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu, toggles %llu; first lane pass: toggle rounds %llu, wave iterations %llu, refill phases %llu, "
                     "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
                     (double)dl[S_T_SUML] / (double)((dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) ? (dl[S_T_SHORT] + dl[S_T_LONG] + dl[S_T_GLOBAL]) : 1),
                     dl[S_T_FROMP], dl[S_T_FLUSHES], dl[S_T_DEL], h->max_chain, dl[S_T_CTOG] / st, dl[S_T_CNEXT] / st, dl[S_T_CFLUSH] / st,
-                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32], dl[S_T_LLONG],
+                    (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32], dl[S_T_LLONG], dl[S_T_LTOG], dl[S_T_LTROUND],
                     dl[S_T_LITER], dl[S_T_LREFILL], dl[S_T_LFLUSH],
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
                     (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1));
