@@ -180,6 +180,54 @@ def test_vr_full_closed_form_counts():
     assert f.nnz == 2 * math.comb(50, 2) + 3 * math.comb(50, 3)
 
 
+def test_vr_dim3_counts_values_order():
+    """Tetrahedra (maxdim 3): every 4-clique of the threshold graph, its value
+    the largest squared distance among its vertices, compatible order, and
+    each column the four triangle faces (eq. 'def:boundary_matrix')."""
+    pts = synth.vr_grid_cloud(seed=8, n=12, side=64)
+    thr = synth.percentile_threshold_sqd(pts, 0.6)
+    f = oracle.build_vr_i32(pts, thr, 3)
+    x = pts.astype(np.int64)
+    sq = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    n = len(pts)
+    cliques = [[t for t in itertools.combinations(range(n), k)
+                if all(sq[p, q] <= thr for p, q in itertools.combinations(t, 2))] for k in (2, 3, 4)]
+    assert len(cliques[2]) > 0
+    assert np.bincount(f.dim, minlength=4).tolist() == [n] + [len(c) for c in cliques]
+    for j in range(f.m):
+        s = [int(v) for v in f.verts[j] if v >= 0]
+        assert f.value[j] == max((sq[p, q] for p, q in itertools.combinations(s, 2)), default=0)
+    _check_order(f)
+    _check_boundary_by_definition(f)
+
+
+def test_vr_dim3_full_skeleton_homology():
+    """The full complex on n points to dimension 3 is the 3-skeleton of the
+    (n-1)-simplex: reduced homology only in degree 3, of rank C(n-1, 4), so
+    the essential simplices are one vertex and C(n-1, 4) tetrahedra."""
+    n = 9
+    f = oracle.build_vr_i32(synth.vr_grid_cloud(seed=9, n=n), -1, 3)
+    assert np.bincount(f.dim).tolist() == [n, math.comb(n, 2), math.comb(n, 3), math.comb(n, 4)]
+    assert f.nnz == 2 * math.comb(n, 2) + 3 * math.comb(n, 3) + 4 * math.comb(n, 4)
+    low = oracle.reduce_standard(f.col_ptr, f.rows)
+    ess = oracle.essential(low)
+    assert np.bincount(f.dim[ess], minlength=4).tolist() == [1, 0, 0, math.comb(n - 1, 4)]
+
+
+def test_vr_octahedron_sphere():
+    """The six points +-e_i: at squared scale 2 the complex is the octahedral
+    2-sphere (no 4-clique avoids an antipodal pair), and at 4 the antipodal
+    edges and the tetrahedra fill it, so the one H2 class with non-zero
+    persistence is born at 2 and dies at 4."""
+    pts = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.int32)
+    f = oracle.build_vr_i32(pts, -1, 3)
+    assert np.bincount(f.dim).tolist() == [6, 15, 20, 15]
+    low = oracle.reduce_standard(f.col_ptr, f.rows)
+    pairs = [(int(f.dim[low[j]]), int(f.value[low[j]]), int(f.value[j])) for j in range(f.m) if low[j] >= 0]
+    assert sorted(p for p in pairs if p[1] != p[2]) == [(0, 0, 2)] * 5 + [(2, 2, 4)]
+    assert [int(f.dim[i]) for i in oracle.essential(low)] == [0] + [3] * 5
+
+
 def test_vr_f32_values_stepwise():
     x = synth.circle_batch(seed=9, clouds=1, n=12)[0]
     f = oracle.build_vr_f32(x, -1.0, 2)
