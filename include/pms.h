@@ -286,7 +286,7 @@ typedef struct {
  * NaN -> PMS_ERR_INVALID_ARG.  Grids of 2^26 vertices or more are rejected. */
 pms_status pms_build_lowerstar(pms_ctx *ctx, const float *grid, int32_t nx, int32_t ny, int32_t nz,
                                pms_filtration **f);
-/* Vietoris-Rips filtrations to dimension maxdim (0..2) of `count` point
+/* Vietoris-Rips filtrations to dimension maxdim (0..3) of `count` point
  * clouds at once (Sec. 2.2: a simplex enters when its diameter is at most
  * 2r, i.e. the value of a simplex is its squared diameter).  Cloud b has
  * n[b] points of D[b] coordinates stored row-major at pts + pt_off[b]
@@ -302,7 +302,12 @@ pms_status pms_build_lowerstar(pms_ctx *ctx, const float *grid, int32_t nx, int3
  *         n[b] <= 511;
  *   _f32: FP32 coordinates; the squared distance is rounded step by step
  *         in coordinate order (d = x_a - x_b; s = s + d*d, no fused
- *         multiply-add); n[b] <= 1023. */
+ *         multiply-add); n[b] <= 1023.
+ * Order within a cloud: (value, dimension, lexicographic vertex tuple).  A
+ * tetrahedron's value is the largest squared distance among its four
+ * vertices, its critical edge (`crit`) the latest of its six edges in the
+ * filtration.  More than 32 bits of simplices in total, or a cloud outside
+ * the size limits, gives PMS_ERR_INVALID_ARG. */
 pms_status pms_build_vr_i32(pms_ctx *ctx, const int32_t *pts, int32_t count, const int32_t *n, const int32_t *D,
                             const int64_t *pt_off, const int64_t *thr_sqd, int32_t maxdim, pms_filtration **f,
                             int64_t *inst_col_off);

@@ -105,7 +105,7 @@ enum BufId {
     B_OFF = 0, B_LEN, B_LOW, B_STATE, B_BETA, B_LEFT, B_PIV, B_T, B_NEG, B_ACT0, B_ACT1,
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
-    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_STATS, B_PART, B_CQN, B_PREC, B_WQ, B_WQ2, B_ESS,
+    B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_BUILD14, B_STATS, B_PART, B_CQN, B_PREC, B_WQ, B_WQ2, B_ESS,
     B_NUM
 };
 static_assert(B_NUM <= 40, "Ctx::b holds 40 buffers");

@@ -90,7 +90,8 @@ def _check_vr_segment(got, off, b, pbase, ref):
         assert np.array_equal(gv, ref.value)
     verts = got["verts"][lo:hi]
     assert np.array_equal(np.where(verts >= 0, verts - pbase, -1), ref.verts)
-    # critical edge: the facet edge latest in the filtration (edges: themselves)
+    # critical edge: the edge of the simplex latest in the filtration (edges:
+    # themselves; triangles: their last facet)
     crit = got["crit"][lo:hi]
     want = np.full((ref.m, 2), -1, np.int64)
     e = ref.dim == 1
@@ -99,6 +100,15 @@ def _check_vr_segment(got, off, b, pbase, ref):
     if t.size:
         last = ref.rows[ref.col_ptr[t + 1] - 1]
         want[t] = ref.verts[last][:, :2]
+    q = np.nonzero(ref.dim == 3)[0]
+    if q.size:  # tetrahedra: the latest of their six edges
+        n = int(ref.verts.max()) + 1
+        eid = np.full((n, n), -1, np.int64)
+        ei = np.nonzero(e)[0]
+        eid[ref.verts[ei, 0], ref.verts[ei, 1]] = ei
+        V = ref.verts[q]
+        best = np.stack([eid[V[:, u], V[:, w]] for u in range(4) for w in range(u + 1, 4)], 1).max(1)
+        want[q] = ref.verts[best][:, :2]
     assert np.array_equal(np.where(crit >= 0, crit - pbase, -1), want)
 
 
@@ -126,7 +136,7 @@ def test_vr_builder_f32_circle(gpu):
     _compare_vr([synth.circle_batch(clouds=1)[0]], [-1.0], 2, gpu)
 
 
-@pytest.mark.parametrize("maxdim", [0, 1, 2])
+@pytest.mark.parametrize("maxdim", [0, 1, 2, 3])
 def test_vr_builder_batch_mixed(gpu, maxdim):
     inst = synth.vr_batch(seed=31, count=6, n_range=(3, 40))
     clouds = [p for p, _ in inst] + [np.zeros((0, 3), np.int32), np.array([[5, 5, 5]], np.int32),
@@ -139,6 +149,56 @@ def test_vr_builder_ties(gpu):
     # many equal distances: the (value, dim, lex) tie-break decides the order
     g = np.array([[x, y] for x in range(5) for y in range(4)], np.int32)
     _compare_vr([g, g[:7]], [4, -1], 2, gpu)
+
+
+def test_vr_builder_dim3_small(gpu):
+    """Tetrahedra: a thresholded integer cloud, a full FP32 cloud, ties."""
+    pts, _ = synth.vr_torus(seed=12, n=60)
+    _compare_vr([pts], [synth.percentile_threshold_sqd(pts, 0.3)], 3, gpu)
+    _compare_vr([synth.circle_batch(seed=13, clouds=1, n=14)[0]], [-1.0], 3, gpu)
+    g = np.array([[x, y] for x in range(4) for y in range(4)], np.int32)
+    _compare_vr([g, g[:9]], [5, -1], 3, gpu)
+
+
+def test_vr_dim3_reduce_and_octahedron(gpu):
+    """Dimension-3 batches reduce to the oracle's low* cloud by cloud; the
+    octahedron's one persistent H2 class is born at 2 and dies at 4."""
+    octa = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.int32)
+    inst = synth.vr_batch(seed=33, count=5, n_range=(4, 30))
+    clouds = [octa] + [p for p, _ in inst]
+    thrs = [-1] + [t for _, t in inst]
+    f, off, refs = _compare_vr(clouds, thrs, 3, gpu)
+    res = api.reduce_filtration(f)
+    low = res.low_star.cpu().numpy()
+    for b, ref in enumerate(refs):
+        want = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+        seg = low[off[b]:off[b + 1]]
+        assert np.array_equal(np.where(seg >= 0, seg - off[b], -1), want), b
+    v = f.to_torch()
+    val, dm = v["value"].cpu().numpy(), v["dim"].cpu().numpy()
+    pb, pd = res.pair_birth.cpu().numpy(), res.pair_death.cpu().numpy()
+    octa_pairs = (pd < off[1]) & (dm[pb] == 2) & (val[pb] != val[pd])
+    assert [(int(val[i]), int(val[j])) for i, j in zip(pb[octa_pairs], pd[octa_pairs])] == [(2, 4)]
+
+
+def test_vr_torus400_dim3_full(gpu):
+    """The 400-point torus at its 20th-percentile threshold taken to dimension
+    3 (3.8e6 simplices, 3.5e6 tetrahedra): the built matrix and the reduced
+    low* equal the oracle's element by element."""
+    pts, thr = synth.vr_torus()
+    f, off, refs = _compare_vr([pts], [thr], 3, gpu)
+    assert int(np.sum(refs[0].dim == 3)) > 3_000_000
+    res = api.reduce_filtration(f)
+    want = oracle.reduce_twist(refs[0].col_ptr, refs[0].rows, refs[0].dim)
+    assert np.array_equal(res.low_star.cpu().numpy(), want)
+    b, d = oracle.pairs(want)
+    assert np.array_equal(res.pair_birth.cpu().numpy(), b) and np.array_equal(res.pair_death.cpu().numpy(), d)
+    assert np.array_equal(res.essential.cpu().numpy(), oracle.essential(want))
+
+
+def test_vr_builder_rejects_maxdim4(gpu):
+    with pytest.raises(_binding.PmsError):
+        api.build_vr([torch.zeros((5, 2), dtype=torch.int32, device=gpu)], [-1], 4)
 
 
 def test_vr_batch_reduce_f32_circles(gpu):
