@@ -14,7 +14,8 @@ whole device path on the grid already resident in HBM:
 The same run also times the batched Vietoris-Rips workloads against one call
 per cloud on the same GPU ("batched" field): 512 clouds of 32..256 points
 (reduction only) and 64 FP32 clouds of 128 points (reduction + backward of
-the sum of squared H1 persistences), each checked on the host for its size.
+the sum of squared H1 persistences), each checked on the host for its size;
+and ("vr_dim3") the 400-point torus taken to dimension 3 (3.8e6 simplices).
 
 Before the warm-up steps, the chaining kernels' launch shapes and the
 graph-mode round count are autotuned on each workload's own filtration
@@ -189,16 +190,41 @@ def batched_vs_plain(api, autograd, synth, torch, dev, tune):
     return out
 
 
+def vr_dim3(api, synth, torch, dev, tune):
+    """Vietoris-Rips to dimension 3 (H0-H2 plus the tetrahedra): the 400-point
+    torus at its 20th-percentile threshold, build + reduce on the device."""
+    pts, thr = synth.vr_torus()
+    cl = [torch.as_tensor(pts, device=dev)]
+    w = api.Filtration(dev)
+    f, _ = api.build_vr(cl, [thr], 3, out=w)
+    kw, rec = _tune(tune, f)
+    meta = {}
+
+    def run():
+        f, _ = api.build_vr(cl, [thr], 3, out=w)
+        r = api.reduce_filtration(f, **kw)
+        meta["m"], meta["rounds"], meta["adds"], meta["r"] = f.m, r.rounds, r.additions, r
+
+    t = _timed(run, torch)
+    dims = w.to_torch()["dim"]
+    ess = meta["r"].essential
+    return {"workload": "vr_torus400_p20_dim3", "m": meta["m"],
+            "simplices_by_dim": torch.bincount(dims.long(), minlength=4).tolist(),
+            "rounds": meta["rounds"], "additions": meta["adds"], "n_pairs": int(meta["r"].pair_birth.numel()),
+            "essential_by_dim": torch.bincount(dims[ess].long(), minlength=4).tolist(),
+            "build_reduce_s": round(t, 5), "simplices_per_s": meta["m"] / t, "tuning": rec}
+
+
 # the bench run autotunes and stores the shapes in <C>; the profiled runs
 # read them from there (no candidate timings in the traces)
 PROFILE_CMDS = [
     "python3 bench.py --steps 10 --warmup 2 --tune-cache <C>",
     "rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o ls64 -- python3 bench.py --steps 3 "
-    "--warmup 1 --no-cpu-baseline --no-batched --no-multiscale --calibrate-copy --tune-cache <C>",
+    "--warmup 1 --no-cpu-baseline --no-batched --no-dim3 --no-multiscale --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o f -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
+    "--no-cpu-baseline --no-batched --no-dim3 --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o w -- python3 bench.py --steps 1 --warmup 0 "
-    "--no-cpu-baseline --no-batched --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
+    "--no-cpu-baseline --no-batched --no-dim3 --no-profile --no-multiscale --calibrate-copy --tune-cache <C>",
 ]
 COPY_BYTES = 256 << 20
 
@@ -308,6 +334,7 @@ def main():
                     help="JSON file of autotuned shapes by size class (read, and written on a miss)")
     ap.add_argument("--no-autotune", action="store_true", help="run with the library's built-in shapes")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the reduction with per-round diagnostics")
+    ap.add_argument("--no-dim3", action="store_true", help="skip the Vietoris-Rips dimension-3 workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to scale rocprof's FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -479,6 +506,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(api, autograd, synth, torch, dev, tune)
+    if not args.no_dim3:
+        out["vr_dim3"] = vr_dim3(api, synth, torch, dev, tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid_np, m)
     print(json.dumps(out), flush=True)
