@@ -124,7 +124,8 @@ def _tune(tune, f, count=1):
         return {}, None
     from paper_1708_04710_amd import autotune
     rec = autotune.autotune(f, count=count, cache=tune, reps=3)
-    return {"graph_rounds": rec["graph_rounds"]}, {k: rec[k] for k in ("tuning", "graph_rounds", "ms", "cached")}
+    return ({"graph_rounds": rec["graph_rounds"], "variant": rec["variant"]},
+            {k: rec[k] for k in ("tuning", "graph_rounds", "variant", "ms", "cached")})
 
 
 def batched_vs_plain(api, autograd, synth, torch, dev, tune):

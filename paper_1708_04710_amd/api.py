@@ -362,7 +362,8 @@ def get_tuning(device=None) -> dict:
 def time_candidates(f: "Filtration", candidates, reps: int = 3, **kw):
     """Time reductions of filtration ``f`` under each candidate
     (``pms_autotune``).  A candidate is a dict of tuning fields plus, optionally,
-    ``graph_rounds``; ``kw`` are the other reduce options, common to all.
+    ``graph_rounds`` and the Phase II ``variant`` (both give the same low*);
+    ``kw`` are the other reduce options, common to all.
     Returns (median ms per candidate, index of the fastest, ReduceResult of
     one more run with it); the context keeps the fastest tuning."""
     n = len(candidates)
@@ -371,6 +372,7 @@ def time_candidates(f: "Filtration", candidates, reps: int = 3, **kw):
     kw = dict(kw)
     outputs = kw.pop("outputs", True)
     graph_rounds = kw.pop("graph_rounds", 0)
+    variant = kw.pop("variant", 0)
     lib = B.load()
     ctx = _ctx(f.device)
     v = f.view
@@ -380,7 +382,8 @@ def time_candidates(f: "Filtration", candidates, reps: int = 3, **kw):
     tunes = (B.PmsTuning * n)()
     for i, c in enumerate(candidates):
         c = dict(c)
-        opts[i] = _options(graph_rounds=int(c.pop("graph_rounds", graph_rounds)), **kw)
+        opts[i] = _options(graph_rounds=int(c.pop("graph_rounds", graph_rounds)),
+                           variant=int(c.pop("variant", variant)), **kw)
         tunes[i] = _tuning_struct(c)
     res, t = _outputs(f.device, m, outputs)
     ms = (ctypes.c_double * n)()

@@ -41,7 +41,11 @@ GRID = {
     "wide_blocks": (1024, 2048, 4096),
     "lane_cap": (24, 32, 39),
     "graph_rounds": (0, 8),
+    # Phase II source: 0 the leftmost column per low, 1 pivots only (Alg. 2);
+    # both reach the same low*, so the faster one is kept
+    "variant": (0, 1),
 }
+_OPTION_KEYS = ("graph_rounds", "variant")  # reduce options, not pms_tuning fields
 
 
 def size_class(m: int, nnz: int, count: int = 1) -> str:
@@ -126,7 +130,7 @@ def autotune(f: "api.Filtration", *, count: int = 1, cache: TuneCache | str | No
     in-memory cache; kw: the other reduce options (their ``graph_rounds``
     is the starting round count).  On a cache hit the stored setting is
     applied without timing.  Returns the record: ``tuning`` (now set on the
-    context), ``graph_rounds`` (pass it to the reductions), ``ms``,
+    context), ``graph_rounds`` and ``variant`` (pass them to the reductions), ``ms``,
     ``scored`` (candidates timed), ``key`` and ``cached``."""
     cache = _memory if cache is None else (TuneCache(cache) if isinstance(cache, str) else cache)
     v = f.view
@@ -135,17 +139,19 @@ def autotune(f: "api.Filtration", *, count: int = 1, cache: TuneCache | str | No
     rec = cache.get(key)
     if rec is not None:
         api.set_tuning(rec["tuning"], device=f.device)
-        return {**rec, "key": key, "cached": True}
+        return {"variant": 0, **rec, "key": key, "cached": True}
     grid = dict(GRID if grid is None else grid)
-    start = {**api.default_tuning(), "graph_rounds": int(kw.pop("graph_rounds", 0))}
+    start = {**api.default_tuning(), "graph_rounds": int(kw.pop("graph_rounds", 0)),
+             "variant": int(kw.pop("variant", 0))}
 
     def measure(cands):
         ms, _, _ = api.time_candidates(f, cands, reps=reps, **kw)
         return ms
 
     best, ms, scored = coordinate_search(measure, start, grid, passes)
-    tuning = {k: x for k, x in best.items() if k != "graph_rounds"}
+    tuning = {k: x for k, x in best.items() if k not in _OPTION_KEYS}
     api.set_tuning(tuning, device=f.device)
-    rec = {"tuning": tuning, "graph_rounds": int(best["graph_rounds"]), "ms": ms, "scored": scored}
+    rec = {"tuning": tuning, "graph_rounds": int(best["graph_rounds"]), "variant": int(best["variant"]), "ms": ms,
+           "scored": scored}
     cache.put(key, rec)
     return {**rec, "key": key, "cached": False}

@@ -158,3 +158,19 @@ def test_autotune_search_and_cache(gpu, builtin_after, tmp_path):
     assert again["cached"] and again["tuning"] == rec["tuning"]
     assert api.get_tuning(device=gpu) == rec["tuning"]
     _check(api.reduce_filtration(f, graph_rounds=again["graph_rounds"]), low_ref)
+
+
+def test_autotune_picks_the_phase2_variant(gpu, builtin_after):
+    """The Phase II source (leftmost column per low, or pivots only as in
+    Alg. 2) is a tuned option like graph_rounds: both reach the oracle's
+    low*, and the record names the faster one without putting it among the
+    kernel shapes."""
+    f, low_ref = _lowerstar(gpu)
+    ms, best, res = api.time_candidates(f, [dict(variant=0), dict(variant=1, lane_steps=32)], reps=1)
+    assert len(ms) == 2 and best in (0, 1)
+    _check(res, low_ref)
+    assert api.get_tuning(device=gpu)["lane_steps"] == (32 if best == 1 else api.default_tuning()["lane_steps"])
+    rec = autotune.autotune(f, cache=autotune.TuneCache(), reps=1, grid={"variant": (0, 1)})
+    assert rec["variant"] in (0, 1) and "variant" not in rec["tuning"]
+    _check(api.reduce_filtration(f, variant=rec["variant"]), low_ref)
+    _check(api.reduce_filtration(f, variant=1 - rec["variant"]), low_ref)
