@@ -233,6 +233,29 @@ def test_vr_batch512_sampled(gpu):
         assert np.array_equal(np.where(seg >= 0, seg - off[b], -1), want), b
 
 
+@pytest.mark.parametrize("maxdim", [2, 3])
+def test_vr_builder_largest_clouds(gpu, maxdim):
+    """The largest clouds accepted (511 integer points, 1023 FP32 points), two
+    per batch: the lex field at its widest (n^3, or n^4 to dimension 3), the
+    integer key a full 64 bits (sorted by key, then by cloud) and the FP32 key
+    with its cloud bit exactly 64 (one pass); built and reduced as the oracle."""
+    rng = np.random.default_rng(5)
+    ints = [rng.integers(0, 1 << 16, (511, 3)).astype(np.int32) for _ in range(2)]
+    flts = [rng.normal(0.0, 1.0, (1023, 2)).astype(np.float32) for _ in range(2)]
+    thr_i = [synth.percentile_threshold_sqd(p, 0.01) for p in ints]
+    thr_f = []
+    for x in flts:
+        d = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+        thr_f.append(float(np.quantile(d[np.triu_indices(len(x), 1)], 0.005)))
+    for clouds, thrs in ((ints, thr_i), (flts, thr_f)):
+        f, off, refs = _compare_vr(clouds, thrs, maxdim, gpu)
+        low = api.reduce_filtration(f).low_star.cpu().numpy()
+        for b, ref in enumerate(refs):
+            want = oracle.reduce_twist(ref.col_ptr, ref.rows, ref.dim)
+            seg = low[off[b]:off[b + 1]]
+            assert np.array_equal(np.where(seg >= 0, seg - off[b], -1), want), b
+
+
 def test_vr_builder_rejects_large_cloud(gpu):
     with pytest.raises(_binding.PmsError):
         api.build_vr([torch.zeros((600, 2), dtype=torch.int32, device=gpu)], [-1], 2)
