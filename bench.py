@@ -68,13 +68,13 @@ def cpu_baseline(grid_np, m_gpu):
     import oracle
     t0 = time.perf_counter()
     f = oracle.build_lowerstar(grid_np)
-    low = oracle.reduce_standard(f.col_ptr, f.rows)
+    low, st = oracle.reduce_standard(f.col_ptr, f.rows, with_stats=True)
     t = time.perf_counter() - t0
     assert f.m == m_gpu
     return {"value": f.m / t, "unit": "simplices/s", "cores": 1, "kind": "oracle",
             "sample": "full 64^3 workload: oracle lower-star build + standard reduction, one thread",
             "seconds": round(t, 3), "cpu": _cpu_model(), "host_threads": os.cpu_count(),
-            "n_pairs": int((low >= 0).sum())}
+            "n_pairs": int((low >= 0).sum()), "standard_additions": st["additions"]}
 
 
 def _source_hash():

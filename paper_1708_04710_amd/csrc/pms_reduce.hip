@@ -1987,11 +1987,12 @@ static void set_partitions(Dev &d, unsigned long long used)
     d.part_size = (d.arena_cap - used) / kPart;
 }
 
-// Arena regrowth: copy the live columns into an arena twice as large, then
-// split the free space into fresh partitions.
-static pms_status grow_arena(Ctx *c, Dev &d, Counters *h)
+// Arena regrowth: copy the live columns into an arena at least twice as
+// large (and at least min_cap entries), then split the free space into
+// fresh partitions.
+static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, unsigned long long min_cap = 0)
 {
-    unsigned long long new_cap = c->arena_cap * 2;
+    unsigned long long new_cap = std::max<unsigned long long>(c->arena_cap * 2, min_cap);
     int32_t *na = nullptr;
     PMS_HIP(hipMalloc(&na, new_cap * sizeof(int32_t)));
     unsigned long long *top = (unsigned long long *)scratch(c, B_TMP1, 64);
@@ -2210,10 +2211,14 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // round runs it out, which drops that round's remaining progress, and
     // before that happens: when the free part left after a round (or a graph
     // replay of rounds) is less than twice what it took.
-    unsigned long long free_prev = d.arena_cap - d.part_base;
+    // Grown early, it takes at least what is in use plus four times the last
+    // round's take, so the rounds after it (and later calls, which start from
+    // the kept arena) do not grow it again.
+    unsigned long long free_prev = d.arena_cap - d.part_base, want_cap = 0;
     auto grow_early = [&](int32_t n_left) {
         const unsigned long long took = free_prev > h->arena_free ? free_prev - h->arena_free : 0;
         free_prev = h->arena_free;
+        want_cap = (d.arena_cap - h->arena_free) + 4 * took;
         return n_left > 0 && h->arena_free < 2 * took;
     };
 
@@ -2290,7 +2295,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             round = h->round;
             if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
             if (h->overflow || grow_early(h->n_cur)) {  // the arena moves: grow it (on the caller's stream) and capture again
-                pms_status s = grow_arena(c, d, h);
+                pms_status s = grow_arena(c, d, h, h->overflow ? 0 : want_cap);
                 if (s != PMS_OK) return s;
                 free_prev = d.arena_cap - d.part_base;
                 PMS_HIP(hipEventRecord(c->graph_ev, st));
@@ -2357,7 +2362,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
                                                                 : "internal: a chained addition did not lower the low");
         if (h->overflow || grow_early(h->n_next)) {
-            pms_status s = grow_arena(c, d, h);
+            pms_status s = grow_arena(c, d, h, h->overflow ? 0 : want_cap);
             if (s != PMS_OK) return s;
             free_prev = d.arena_cap - d.part_base;
         }
@@ -2449,7 +2454,7 @@ __global__ void k_pair_inst(int32_t count, const int64_t *col_off, const int32_t
 
 extern "C" {
 
-const char *pms_version(void) { return "pms-gfx950 0.1"; }
+const char *pms_version(void) { return "pms-gfx950 0.2"; }
 
 pms_options pms_default_options(void)
 {

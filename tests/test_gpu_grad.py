@@ -190,3 +190,59 @@ def test_vr_grad_batch64_sampled(gpu):
         _, ref, _ = _vr_loss_grad64(x[c])
         err = np.linalg.norm(got[c] - ref) / np.linalg.norm(ref)
         assert err <= TOL, (c, err)
+
+
+def _crit_edge(f, j, eid):
+    """The edge of simplex j latest in the filtration (its value's source)."""
+    v = [int(t) for t in f.verts[j] if t >= 0]
+    if len(v) == 2:
+        return j
+    return max(int(eid[v[a], v[b]]) for a in range(len(v)) for b in range(a + 1, len(v)))
+
+
+def _vr_h2_loss_grad64(x32):
+    """FP64 loss and gradient of sum over H2 pairs of (death - birth)^2 on
+    the pairing of the FP32 filtration to dimension 3: a triangle's and a
+    tetrahedron's values are the squared lengths of their critical edges."""
+    f = oracle.build_vr_f32(x32, -1.0, 3)
+    low = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+    b, d = oracle.pairs(low)
+    h2 = f.dim[b] == 2
+    n = len(x32)
+    eid = np.full((n, n), -1, np.int64)
+    e = np.nonzero(f.dim == 1)[0]
+    eid[f.verts[e, 0], f.verts[e, 1]] = e
+    x = x32.astype(np.float64)
+    loss, grad = 0.0, np.zeros_like(x)
+    for bi, di in zip(b[h2], d[h2]):
+        ba, bb = f.verts[_crit_edge(f, bi, eid)][:2]
+        da, db = f.verts[_crit_edge(f, di, eid)][:2]
+        pers = _sqd64(x, da, db) - _sqd64(x, ba, bb)
+        loss += pers * pers
+        w = 2.0 * pers
+        grad[da] += w * 2.0 * (x[da] - x[db])
+        grad[db] -= w * 2.0 * (x[da] - x[db])
+        grad[ba] -= w * 2.0 * (x[ba] - x[bb])
+        grad[bb] += w * 2.0 * (x[ba] - x[bb])
+    return loss, grad
+
+
+def test_vr_h2_grad_dim3(gpu):
+    """Noisy 2-spheres to dimension 3: the H2 classes die at tetrahedra, whose
+    critical edge (the latest of six) carries the death's gradient; FP32
+    gradients of all clouds in one pass against the FP64 gradient."""
+    rng = np.random.default_rng(71)
+    x = rng.normal(size=(3, 24, 3))
+    x /= np.linalg.norm(x, axis=2, keepdims=True)
+    x = (x + rng.normal(0.0, 0.05, x.shape)).astype(np.float32)
+    pts = torch.as_tensor(x, device=gpu).requires_grad_(True)
+    bv, dv, dims, cloud = autograd.persistence_vr(pts, maxdim=3)
+    h2 = dims == 2
+    assert int(h2.sum()) > 0
+    ((dv[h2] - bv[h2]) ** 2).sum().backward()
+    got = pts.grad.detach().cpu().numpy()
+    for c in range(x.shape[0]):
+        loss, ref = _vr_h2_loss_grad64(x[c])
+        assert loss > 0
+        err = np.linalg.norm(got[c] - ref) / np.linalg.norm(ref)
+        assert err <= TOL, (c, err)
