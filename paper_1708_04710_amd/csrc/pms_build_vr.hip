@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_vr_rows(const VrInst *inst, const in
                         cb = (int32_t)(I.pbase + x[w]);
                     }
                 }
-            int32_t r[4];
+            int32_t r[4] = {-1, -1, -1, -1};
             if (dm == 2) {
                 r[0] = eidx[g + (int64_t)x[1] * I.n + x[2]];
                 r[1] = eidx[g + (int64_t)x[0] * I.n + x[2]];
@@ -398,6 +398,8 @@ __global__ void __launch_bounds__(kBlock) k_vr_rows(const VrInst *inst, const in
                     r[k] = find_triangle<F32>(keys, hi, lo, end, chi | (fv << 2) | 2ull, flex);
                     if (r[k] < 0) atomicExch(err, 3);
                 }
+            } else {  // one-word keys never hold a tetrahedron
+                atomicExch(err, 3);
             }
             for (int u = 1; u <= dm; u++) {
                 const int32_t y = r[u];
