@@ -216,6 +216,50 @@ def vr_dim3(api, synth, torch, dev, tune):
             "build_reduce_s": round(t, 5), "simplices_per_s": meta["m"] / t, "tuning": rec}
 
 
+def workload_only(args, api, autograd, synth, torch, dev):
+    """``--workload circles64`` or ``vr512``: that batch alone, K timed steps
+    after W warm-up steps (the kernels of the batched workloads, for
+    profiling them without the 64^3 step around)."""
+    tune = False if args.no_autotune else args.tune_cache
+    w = api.Filtration(dev)
+    if args.workload == "circles64":
+        x = torch.as_tensor(synth.circle_batch(), device=dev)
+        f, _ = api.build_vr(list(x.unbind(0)), None, 2, out=w)
+        kw, rec = _tune(tune, f, x.shape[0])
+        desc = "64 FP32 circles x 128 points, full 2-skeleton: build + reduce + backward of the sum of squared H1 persistences"
+
+        def step():
+            pts = x.clone().requires_grad_(True)
+            bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=w, **kw)
+            torch.where(dims == 1, (dv - bv) ** 2, torch.zeros_like(dv)).sum().backward()
+    else:
+        inst = synth.vr_batch()
+        clouds = [torch.as_tensor(p, device=dev) for p, _ in inst]
+        thrs = [t for _, t in inst]
+        f, _ = api.build_vr(clouds, thrs, 2, out=w)
+        kw, rec = _tune(tune, f, len(clouds))
+        desc = "512 integer clouds of 32..256 points, own 30th-percentile thresholds: build + reduce"
+
+        def step():
+            fb, off = api.build_vr(clouds, thrs, 2, out=w)
+            api.reduce_batched(fb, off, **kw)
+
+    m = f.m
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    out = {"metric": "simplices/s", "value": m / (ms / 1000.0), "unit": "simplices/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+           "config": {"workload": args.workload, "m": m, "step": desc, "tuning": rec}}
+    print(json.dumps(out), flush=True)
+
+
 # the bench run autotunes and stores the shapes in <C>; the profiled runs
 # read them from there (no candidate timings in the traces)
 PROFILE_CMDS = [
@@ -336,6 +380,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="run with the library's built-in shapes")
     ap.add_argument("--no-multiscale", action="store_true", help="skip the reduction with per-round diagnostics")
     ap.add_argument("--no-dim3", action="store_true", help="skip the Vietoris-Rips dimension-3 workload")
+    ap.add_argument("--workload", default="lowerstar64", choices=("lowerstar64", "circles64", "vr512"),
+                    help="lowerstar64 (default): the full bench line; circles64 / vr512: that batch alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to scale rocprof's FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -350,6 +396,9 @@ def main():
     from paper_1708_04710_amd import api, autograd, synth
 
     dev = torch.device("cuda:0")
+    if args.workload != "lowerstar64":
+        workload_only(args, api, autograd, synth, torch, dev)
+        return
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
         dst = torch.empty_like(src)
