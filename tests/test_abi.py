@@ -48,3 +48,14 @@ def test_options_layout_and_defaults():
     assert o.diagnostics == 0 and ctypes.sizeof(_binding.PmsRoundStats) == 48
     assert lib.pms_round_stats_read(None, 0, None, None) == _binding.PMS_ERR_INVALID_ARG
     assert lib.pms_essential_estimate(None, 0, None) == _binding.PMS_ERR_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with status 2 and says
+    so, before it touches torch or the device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
