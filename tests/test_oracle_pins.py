@@ -228,9 +228,11 @@ def test_vr_octahedron_sphere():
     assert [int(f.dim[i]) for i in oracle.essential(low)] == [0] + [3] * 5
 
 
-def test_vr_f32_values_stepwise():
+@pytest.mark.parametrize("maxdim", [2, 3])
+def test_vr_f32_values_stepwise(maxdim):
     x = synth.circle_batch(seed=9, clouds=1, n=12)[0]
-    f = oracle.build_vr_f32(x, -1.0, 2)
+    f = oracle.build_vr_f32(x, -1.0, maxdim)
+    assert np.bincount(f.dim).tolist() == [12] + [math.comb(12, k) for k in range(2, maxdim + 2)]
     for j in range(f.m):
         s = [int(v) for v in f.verts[j] if v >= 0]
         best = np.float32(0)
