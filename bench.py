@@ -63,18 +63,77 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(grid_np, m_gpu):
-    """The oracle as it stands, single-threaded, on the full grid."""
+def _host_threads():
+    """Threads for the per-cloud oracle baselines: the host cores this
+    process may run on (the GPU machine's share is 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(grid_np, m_gpu, batches=True):
+    """The oracle as it stands on the host cores.  The headline value: the
+    full 64^3 grid, oracle build + standard reduction (Alg. "Standard
+    reduction"), one thread; beside it the same build + the twist reduction
+    (Alg. "Standard reduction with a twist"), one thread, and the two
+    batches cloud by cloud (build + twist per cloud) over a thread pool of
+    host cores (the oracle is C behind ctypes, which drops the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
     import oracle
+    from paper_1708_04710_amd import synth
     t0 = time.perf_counter()
     f = oracle.build_lowerstar(grid_np)
+    tb = time.perf_counter() - t0
     low, st = oracle.reduce_standard(f.col_ptr, f.rows, with_stats=True)
     t = time.perf_counter() - t0
     assert f.m == m_gpu
-    return {"value": f.m / t, "unit": "simplices/s", "cores": 1, "kind": "oracle",
-            "sample": "full 64^3 workload: oracle lower-star build + standard reduction, one thread",
-            "seconds": round(t, 3), "cpu": _cpu_model(), "host_threads": os.cpu_count(),
-            "n_pairs": int((low >= 0).sum()), "standard_additions": st["additions"]}
+    t1 = time.perf_counter()
+    lowt, stt = oracle.reduce_twist(f.col_ptr, f.rows, f.dim, with_stats=True)
+    tt = tb + time.perf_counter() - t1
+    assert np.array_equal(low, lowt)
+    out = {"value": f.m / t, "unit": "simplices/s", "cores": 1, "kind": "oracle",
+           "sample": "full 64^3 workload: oracle lower-star build + standard reduction, one thread",
+           "seconds": round(t, 3), "cpu": _cpu_model(), "host_threads": os.cpu_count(),
+           "n_pairs": int((low >= 0).sum()), "standard_additions": st["additions"],
+           "twist": {"value": f.m / tt, "unit": "simplices/s", "cores": 1, "seconds": round(tt, 3),
+                     "sample": "full 64^3 workload: oracle lower-star build + twist reduction, one thread",
+                     "twist_additions": stt["additions"]}}
+    if not batches:
+        return out
+    nt = _host_threads()
+    oracle._load()
+
+    def pool(jobs, fn):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(nt) as ex:
+            ms = list(ex.map(fn, jobs))
+        return sum(ms), time.perf_counter() - t0
+
+    def vr_i32(job):
+        p, thr = job
+        g = oracle.build_vr_i32(p, thr, 2)
+        oracle.reduce_twist(g.col_ptr, g.rows, g.dim)
+        return g.m
+
+    def vr_f32(x):
+        g = oracle.build_vr_f32(x, -1.0, 2)
+        oracle.reduce_twist(g.col_ptr, g.rows, g.dim)
+        return g.m
+
+    m3, t3 = pool(synth.vr_batch(), vr_i32)
+    m4, t4 = pool(list(synth.circle_batch()), vr_f32)
+    out["batches"] = {
+        "vr512": {"value": m3 / t3, "unit": "simplices/s", "cores": nt, "seconds": round(t3, 3),
+                  "sample": "all 512 clouds: oracle build + twist reduction per cloud, thread pool"},
+        "circles64": {"value": m4 / t4, "unit": "simplices/s", "cores": nt, "seconds": round(t4, 3),
+                      "sample": "all 64 circles: oracle build + twist reduction per cloud (no gradient), "
+                                "thread pool"}}
+    return out
 
 
 def _source_hash():
@@ -126,6 +185,36 @@ def _tune(tune, f, count=1):
     rec = autotune.autotune(f, count=count, cache=tune, reps=3)
     return ({"graph_rounds": rec["graph_rounds"], "variant": rec["variant"]},
             {k: rec[k] for k in ("tuning", "graph_rounds", "variant", "ms", "cached")})
+
+
+def grad_error_fp64(x, bv, dv, dims, torch):
+    """Norm-wise relative error, per cloud, of the FP32 gradient of
+    sum over H1 pairs of (death - birth)^2 (already in x.grad) against the
+    FP64 gradient on the same pairing: each pair's birth and death values are
+    the squared lengths of their critical edges, recomputed here from the
+    coordinates in float64 on the host."""
+    f, res = bv.grad_fn.f, bv.grad_fn.result
+    crit = f.to_torch()["crit"].cpu().long()
+    h1 = (dims == 1).cpu()
+    pb = res.pair_birth.cpu().long()[h1]
+    pd = res.pair_death.cpu().long()[h1]
+    X = x.detach().cpu().double().reshape(-1, x.shape[-1])
+    eb, ed = crit[pb], crit[pd]
+    vb = X[eb[:, 0]] - X[eb[:, 1]]
+    vd = X[ed[:, 0]] - X[ed[:, 1]]
+    pers = (vd * vd).sum(1) - (vb * vb).sum(1)
+    w = (4.0 * pers)[:, None]
+    g = torch.zeros_like(X)
+    g.index_add_(0, ed[:, 0], w * vd)
+    g.index_add_(0, ed[:, 1], -w * vd)
+    g.index_add_(0, eb[:, 0], -w * vb)
+    g.index_add_(0, eb[:, 1], w * vb)
+    g = g.reshape(x.shape)
+    g32 = x.grad.detach().cpu().double()
+    errs = ((g32 - g).flatten(1).norm(dim=1) / g.flatten(1).norm(dim=1)).numpy()
+    return {"clouds": int(x.shape[0]), "max_rel_err": float(errs.max()), "median_rel_err": float(
+        sorted(errs)[len(errs) // 2]), "tolerance": 1e-5,
+        "reference": "FP64 gradient on the same pairing (critical edges' squared lengths in float64)"}
 
 
 def batched_vs_plain(api, autograd, synth, torch, dev, tune):
@@ -182,11 +271,16 @@ def batched_vs_plain(api, autograd, synth, torch, dev, tune):
 
     _tune(tune, f, x.shape[0])
     tb = _timed(batch4, torch)
+    # the gradient of the last batched step against the FP64 gradient
+    pts = x.clone().requires_grad_(True)
+    bv, dv, dims, cloud = autograd.persistence_vr(pts, workspace=wb, **kw_b)
+    torch.where(dims == 1, (dv - bv) ** 2, torch.zeros_like(dv)).sum().backward()
+    grad = grad_error_fp64(pts, bv, dv, dims, torch)
     _tune(tune, f1)
     tp = _timed(plain4, torch)
     out["circles64"] = {"clouds": int(x.shape[0]), "m": meta["m4"], "batched_with_backward_s": round(tb, 5),
                         "plain_reduce_only_s": round(tp, 5), "speedup": round(tp / tb, 3),
-                        "batched_simplices_per_s": meta["m4"] / tb, "tuning_batched": rec_b,
+                        "batched_simplices_per_s": meta["m4"] / tb, "grad": grad, "tuning_batched": rec_b,
                         "tuning_plain": rec_p}
     return out
 
@@ -446,7 +540,7 @@ def main():
             step()
         torch.cuda.synchronize()
         prof_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-        prof = api.profile_read(dev)
+        prof = api.profile_read(dev, addition_bytes=True)
         api.profile_enable(False, dev)
     bv, dv, dims = state["fn"]
     res = bv.grad_fn.result if hasattr(bv.grad_fn, "result") else None
@@ -479,42 +573,69 @@ def main():
               "reduce_only_simplices_per_s": m / (reduce_ms / 1000.0)}
 
     # the paper's per-iteration measures (Sec. 4) on this filtration: one more
-    # reduction with diagnostics, outside every timed region
-    multiscale = None
-    if not args.no_multiscale:
-        dres = api.reduce_filtration(f, diagnostics=True, **rkw)
+    # reduction with diagnostics, outside every timed region; once with the
+    # bench's schedule (pivot chaining), once with the paper's own (Alg.
+    # "Parallel multi-scale reduction" as printed: Phase II adds known pivots
+    # only, one addition per column per round)
+    def multiscale_block(kw, keep_rows):
+        dres = api.reduce_filtration(f, diagnostics=True, **kw)
         ms_rows = api.multiscale(dres.round_stats, m, int(dres.essential.numel()))
 
         def first_round(pred):
             return next((r["round"] for r in ms_rows if pred(r)), None)
 
-        multiscale = {
-            "rounds": dres.rounds,
+        def fmt(r):
+            return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+
+        keep = ms_rows if keep_rows is None else [r for r in ms_rows if r["round"] in keep_rows or r is ms_rows[-1]]
+        return {
+            "rounds": dres.rounds, "additions": dres.additions,
             "rounds_to_rel_l1_error": {f"1e-{k}": first_round(lambda r, k=k: r["rel_error"] <= 10.0 ** -k)
-                                       for k in (1, 2, 3, 4)},
-            "rounds_to_unreduced": {str(p): first_round(lambda r, p=p: r["unreduced"] <= p) for p in (0.5, 0.1, 0.01)},
-            "per_round": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for r in ms_rows],
+                                       for k in (1, 2, 3, 4)} | {"0": first_round(lambda r: r["rel_error"] == 0.0)},
+            "rounds_to_unreduced": {str(p): first_round(lambda r, p=p: r["unreduced"] <= p)
+                                    for p in (0.9, 0.5, 0.1, 0.05, 0.01)},
+            "rounds_to_ess_precision": {str(p): first_round(lambda r, p=p: r["ess_precision"] >= p)
+                                        for p in (0.1, 0.5, 0.9, 0.95, 1.0)},
+            "per_round": [fmt(r) for r in keep],
         }
 
-    roof = None
+    multiscale = multiscale_paper = None
+    if not args.no_multiscale:
+        multiscale = multiscale_block(rkw, None)
+        paper_kw = dict(variant=1, chain=False)
+        multiscale_paper = multiscale_block(paper_kw, {0, 1, 2, 3, 5, 10, 20, 50, 100, 200, 500, 1000, 2000})
+        multiscale_paper["schedule"] = ("Phase II adds known pivots only, one addition per column per round "
+                                        "(no chaining): variant=1, chain=False")
+
+    roof = roof_s8d = None
     kernels = {}
     if prof:
-        for name, (tot_ms, n, by) in prof.items():
+        for name, (tot_ms, n, by, ab) in prof.items():
             kernels[name] = {"ms_total": round(tot_ms, 4), "launches": n,
                              "avg_us": round(1000.0 * tot_ms / n, 3),
                              "alg_bytes_per_launch": by / n}
+            if ab > 0:
+                kernels[name]["addition_bytes_per_launch"] = ab / n
         dom = max(prof, key=lambda k: prof[k][0])
-        tot_ms, n, by = prof[dom]
+        tot_ms, n, by, ab = prof[dom]
         avg_s = tot_ms / n / 1000.0
         ach = (by / n) / avg_s / 1e9 if avg_s > 0 else 0.0
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
-                "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": by / n}
+                "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": by / n,
+                "bytes_model": "the bytes the kernel's own design must move (one record per chained step)"}
+        # the same kernel priced by the unit cost of a column addition: each
+        # addition t <- t + s reads t and s and writes t + s, 4 bytes an entry
+        ach2 = (ab / n) / avg_s / 1e9 if avg_s > 0 else 0.0
+        roof_s8d = {"kernel": dom, "bound": "hbm", "achieved": round(ach2, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach2 / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
+                    "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": ab / n,
+                    "bytes_model": "4 (len t + len s + len t+s) per column addition"}
         # the whole step's HBM traffic (rocprof FETCH+WRITE per kernel launch,
         # when the counters match these kernels) and algorithmic bytes
         alg = sum(v[2] for v in prof.values()) / args.steps
         meas, missing = 0.0, []
-        for name, (_, nl, _) in prof.items():
+        for name, (_, nl, _, _) in prof.items():
             b = measured_traffic(name)
             if b is None:
                 missing.append(name)
@@ -527,6 +648,19 @@ def main():
             phases["step_measured_frac_of_hbm_peak"] = round(meas / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)
         else:
             phases["step_measured_hbm_bytes"] = None  # kernels changed since the counters were taken
+    # the reduction's bytes by the unit costs of the method: the CSC read
+    # once (4 nnz + 8 m), 40 bytes per active column per round (low read and
+    # written, leftmost table update and read, compaction, header), every
+    # column addition at 4 (len t + len s + len t+s), and the finalisation
+    # (4 m + 8 per pair + 4 per essential simplex), over the reduction's time
+    if res is not None:
+        s8d = (4.0 * f.nnz + 8.0 * m + 40.0 * res.active_sum + res.addition_bytes + 4.0 * m
+               + 8.0 * n_pairs + 4.0 * int(res.essential.numel()))
+        phases["reduce_unit_cost_bytes"] = s8d
+        phases["reduce_unit_cost_parts"] = {"load": 4.0 * f.nnz + 8.0 * m, "rounds": 40.0 * res.active_sum,
+                                            "additions": float(res.addition_bytes),
+                                            "finalize": 4.0 * m + 8.0 * n_pairs + 4.0 * int(res.essential.numel())}
+        phases["reduce_unit_cost_frac_of_hbm_peak"] = round(s8d / (reduce_ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)
 
     out = {
         "metric": METRIC,
@@ -549,8 +683,10 @@ def main():
                    "n_pairs": n_pairs, "n_essential": int(res.essential.numel()) if res else None,
                    "tuning": tune_rec},
         "roofline": roof,
+        "roofline_s8d": roof_s8d,
         "phases": phases,
         "multiscale": multiscale,
+        "multiscale_paper": multiscale_paper,
         "kernels": kernels,
         "cpu_baseline": None,
     }
@@ -559,7 +695,7 @@ def main():
     if not args.no_dim3:
         out["vr_dim3"] = vr_dim3(api, synth, torch, dev, tune)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(grid_np, m)
+        out["cpu_baseline"] = cpu_baseline(grid_np, m, batches=not args.no_batched)
     print(json.dumps(out), flush=True)
 
 

@@ -46,7 +46,9 @@ typedef enum {
     PMS_ERR_OOM = -3,            /* device allocation failed */
     PMS_ERR_HIP = -4,            /* a HIP runtime call failed */
     PMS_ERR_NOT_CONVERGED = -5,  /* max_rounds reached before low was injective */
-    PMS_ERR_CAPACITY = -6        /* output buffers too small; counts hold the sizes */
+    PMS_ERR_CAPACITY = -6,       /* output buffers too small; counts hold the sizes */
+    PMS_ERR_INVARIANT = -7       /* debug_invariants: a property the theory guarantees
+                                    did not hold (a library bug); the message names it */
 } pms_status;
 
 typedef struct pms_ctx pms_ctx;
@@ -62,7 +64,8 @@ const char *pms_last_error(const pms_ctx *ctx);
 /* Library version string (static). */
 const char *pms_version(void);
 /* Checks the device's wave-level primitives (DPP reductions) against
- * reference shuffles on ctx's device; PMS_OK when they agree. */
+ * reference shuffles on ctx's device, and the debug_invariants detectors on
+ * fabricated states that each break one property; PMS_OK when all agree. */
 pms_status pms_selftest(pms_ctx *ctx);
 
 /* Boundary matrix d of a filtration in filtration order, CSC:
@@ -116,6 +119,24 @@ typedef struct {
      * A non-zero value reallocates the arena to exactly this size (the
      * arena still grows when fill-in exceeds it). */
     int64_t arena_entries;
+    /* 1 = check, on the device after Phase 0, after every kernel that writes
+     * columns and after every round, the properties the theory guarantees,
+     * and fail with PMS_ERR_INVARIANT naming the first one broken:
+     *   - lows never increase (Sec. 3.1, "Convergence": additions only
+     *     remove the low; compression only deletes rows);
+     *   - beta_j <= low(j), and a column with beta_j defined is never zero
+     *     (Thm. "Properties of beta_j" P.5 and P.3);
+     *   - a pivot column never changes again, and piv / low_star name it;
+     *   - no column is written twice by one kernel launch (no two threads
+     *     own one column);
+     *   - no essential simplex ever leaves the estimate E^l (Lemma
+     *     "Essential estimation": Ess is a subset of every E^l), checked
+     *     against the final Ess;
+     *   - at the end low*(j) is the last low seen and beta_j <= low*(j).
+     * Runs one round at a time (no graph) with several extra passes over the
+     * columns per round; for testing, not production.  0 = off. */
+    int32_t debug_invariants;
+    int32_t reserved; /* 0 */
 } pms_options;
 
 pms_options pms_default_options(void);
@@ -142,6 +163,14 @@ typedef struct {
     int32_t phase0_pivots;  /* pivots known from beta before any addition (Phase 0) */
     int64_t additions;      /* column additions performed (the paper's cost unit) */
     int64_t xor_entries;    /* entries read by those additions */
+    int64_t active_sum;     /* sum over rounds of the round's active columns (the columns
+                               the per-round kernels pass over) */
+    int64_t addition_bytes; /* sum over the additions t <- t + s of 4 (len t + len s +
+                               len(t + s)): the bytes a column addition reads and writes
+                               by itself.  Exact for a column's first addition in a round;
+                               for the chained additions after it, len t counts the
+                               column's pending toggles, and len(t + s) = len t + len s - 2
+                               (only the low is known to cancel) */
 } pms_result;
 
 /* Reduce one boundary matrix (Alg. "Parallel multi-scale reduction":
@@ -361,6 +390,10 @@ pms_status pms_profile_enable(pms_ctx *ctx, int enable);
 int pms_profile_kernels(void);
 const char *pms_profile_kernel_name(int k); /* static, NULL when out of range */
 pms_status pms_profile_read(pms_ctx *ctx, int k, double *total_ms, int64_t *launches, double *bytes);
+/* For the kernels that add columns (0 for the others): the summed bytes of
+ * their additions at 4 (len t + len s + len(t + s)) each, as in
+ * pms_result.addition_bytes, since pms_profile_enable. */
+pms_status pms_profile_read_addition_bytes(pms_ctx *ctx, int k, double *bytes);
 
 #ifdef __cplusplus
 }

@@ -19,12 +19,13 @@ PMS_ERR_OOM = -3
 PMS_ERR_HIP = -4
 PMS_ERR_NOT_CONVERGED = -5
 PMS_ERR_CAPACITY = -6
+PMS_ERR_INVARIANT = -7
 
 STATUS_NAMES = {
     PMS_OK: "PMS_OK", PMS_ERR_INVALID_ARG: "PMS_ERR_INVALID_ARG",
     PMS_ERR_NOT_COMPATIBLE: "PMS_ERR_NOT_COMPATIBLE", PMS_ERR_OOM: "PMS_ERR_OOM",
     PMS_ERR_HIP: "PMS_ERR_HIP", PMS_ERR_NOT_CONVERGED: "PMS_ERR_NOT_CONVERGED",
-    PMS_ERR_CAPACITY: "PMS_ERR_CAPACITY",
+    PMS_ERR_CAPACITY: "PMS_ERR_CAPACITY", PMS_ERR_INVARIANT: "PMS_ERR_INVARIANT",
 }
 
 # every symbol include/pms.h declares (checked by the CPU test suite)
@@ -32,7 +33,7 @@ EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
     "pms_reduce", "pms_reduce_batched", "pms_round_stats_read", "pms_essential_estimate", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
     "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
-    "pms_profile_read", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
+    "pms_profile_read", "pms_profile_read_addition_bytes", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
 ]
 
@@ -47,7 +48,8 @@ class PmsOptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("chain", ctypes.c_int32),
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph_rounds", ctypes.c_int32), ("diagnostics", ctypes.c_int32),
-                ("arena_entries", ctypes.c_int64)]
+                ("arena_entries", ctypes.c_int64), ("debug_invariants", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PmsRoundStats(ctypes.Structure):
@@ -76,7 +78,8 @@ class PmsResult(ctypes.Structure):
                 ("essential", ctypes.c_void_p), ("cap_essential", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_essential", ctypes.c_int64),
                 ("rounds", ctypes.c_int32), ("phase0_pivots", ctypes.c_int32),
-                ("additions", ctypes.c_int64), ("xor_entries", ctypes.c_int64)]
+                ("additions", ctypes.c_int64), ("xor_entries", ctypes.c_int64),
+                ("active_sum", ctypes.c_int64), ("addition_bytes", ctypes.c_int64)]
 
 
 class PmsError(RuntimeError):
@@ -140,6 +143,8 @@ def load(path: str = LIB_PATH):
     lib.pms_profile_read.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     lib.pms_profile_read.restype = ctypes.c_int
+    lib.pms_profile_read_addition_bytes.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.pms_profile_read_addition_bytes.restype = ctypes.c_int
     lib.pms_build_lowerstar.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(P)]
     lib.pms_build_lowerstar.restype = ctypes.c_int

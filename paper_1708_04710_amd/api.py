@@ -58,8 +58,11 @@ def profile_enable(enable: bool = True, device=None):
     B.check(ctx, B.load().pms_profile_enable(ctx, int(bool(enable))))
 
 
-def profile_read(device=None) -> dict:
-    """{kernel name: (total ms, launches, algorithmic bytes)} since profile_enable."""
+def profile_read(device=None, addition_bytes=False) -> dict:
+    """{kernel name: (total ms, launches, algorithmic bytes)} since
+    profile_enable; with ``addition_bytes`` a fourth entry: the bytes of the
+    kernel's column additions at 4 (len t + len s + len t+s) each (0 for the
+    kernels that add no columns)."""
     lib = B.load()
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     ctx = _ctx(dev)
@@ -68,7 +71,12 @@ def profile_read(device=None) -> dict:
         ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         B.check(ctx, lib.pms_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
         if n.value:
-            out[lib.pms_profile_kernel_name(k).decode()] = (ms.value, n.value, by.value)
+            rec = (ms.value, n.value, by.value)
+            if addition_bytes:
+                ab = ctypes.c_double()
+                B.check(ctx, lib.pms_profile_read_addition_bytes(ctx, k, ctypes.byref(ab)))
+                rec = rec + (ab.value,)
+            out[lib.pms_profile_kernel_name(k).decode()] = rec
     return out
 
 
@@ -87,6 +95,8 @@ class ReduceResult:
     phase0_pivots: int
     additions: int
     xor_entries: int
+    active_sum: int = 0      # sum over rounds of the round's active columns
+    addition_bytes: int = 0  # sum over additions of 4 (len t + len s + len t+s)
     # batched reductions only (reduce_batched): per-instance starts in the
     # pair / essential lists ([count+1] int64) and the instance of each pair
     inst_pair_off: torch.Tensor | None = None
@@ -217,9 +227,10 @@ def _dptr(t):
 
 
 def _options(variant=0, compression=True, max_rounds=0, chain=True, tail_active=1024, validate=True,
-             arena_entries=0, graph_rounds=0, diagnostics=False):
+             arena_entries=0, graph_rounds=0, diagnostics=False, debug_invariants=False):
     return B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
-                        int(bool(validate)), graph_rounds, int(bool(diagnostics)), arena_entries)
+                        int(bool(validate)), graph_rounds, int(bool(diagnostics)), arena_entries,
+                        int(bool(debug_invariants)), 0)
 
 
 def _outputs(dev, m, outputs):
@@ -245,7 +256,8 @@ def _result(res, t, **extra) -> ReduceResult:
     return ReduceResult(low_star=t["low_star"], pair_birth=t["birth"][:res.n_pairs],
                         pair_death=t["death"][:res.n_pairs], essential=t["ess"][:res.n_essential],
                         rounds=res.rounds, phase0_pivots=res.phase0_pivots, additions=res.additions,
-                        xor_entries=res.xor_entries, **extra)
+                        xor_entries=res.xor_entries, active_sum=res.active_sum,
+                        addition_bytes=res.addition_bytes, **extra)
 
 
 def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off=None, **kw) -> ReduceResult:
@@ -400,7 +412,8 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     col_ptr: int64 [m+1]; rows: int32 [nnz] ascending per column; dim: int8 [m]
     or None.  All on the same device.  Keyword options as in ``pms_options``:
     variant, compression, max_rounds, chain, tail_active, validate,
-    graph_rounds, arena_entries; ``outputs=False`` skips the pair / essential lists."""
+    graph_rounds, arena_entries, diagnostics, debug_invariants; ``outputs=False``
+    skips the pair / essential lists."""
     if not col_ptr.is_cuda or not rows.is_cuda or (dim is not None and not dim.is_cuda):
         raise ValueError("col_ptr, rows and dim must be device tensors")
     if col_ptr.dtype != torch.int64 or rows.dtype != torch.int32 or (dim is not None and dim.dtype != torch.int8):

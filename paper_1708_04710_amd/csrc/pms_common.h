@@ -34,7 +34,8 @@ enum KernelId {
 struct PendingEv {
     int kid;
     hipEvent_t e0, e1;
-    double bytes;  // algorithmic bytes of this launch (< 0: filled in later)
+    double bytes;   // algorithmic bytes of this launch (< 0: filled in later)
+    double abytes;  // addition kernels: 4 (len t + len s + len t+s) over its additions (filled in later)
 };
 
 // Entries of the first lane chaining pass's per-lane LDS buffer: 39 x 128
@@ -79,9 +80,10 @@ struct Ctx {
     std::vector<hipEvent_t> ev_pool;
     double prof_ms[K_NUM] = {};
     double prof_bytes[K_NUM] = {};
+    double prof_abytes[K_NUM] = {};
     int64_t prof_launches[K_NUM] = {};
     // named scratch buffers, grown on demand
-    Buf b[40];
+    Buf b[48];
     int32_t *arena = nullptr;
     uint64_t arena_cap = 0;  // entries
     void *host_pinned = nullptr;
@@ -106,9 +108,10 @@ enum BufId {
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
     B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_BUILD14, B_STATS, B_PART, B_CQN, B_PREC, B_WQ, B_WQ2, B_ESS,
+    B_DBG_LOW, B_DBG_OFF, B_DBG_LEN, B_DBG_STATE, B_DBG_W, B_DBG_EREM,
     B_NUM
 };
-static_assert(B_NUM <= 40, "Ctx::b holds 40 buffers");
+static_assert(B_NUM <= 48, "Ctx::b holds 48 buffers");
 
 // Grow-only scratch: returns the buffer, reallocating (contents dropped) when
 // it is smaller than `bytes`.
@@ -133,7 +136,7 @@ void prof_flush(Ctx *c);
         if ((c)->prof_on) {                                                                     \
             hipEvent_t e1_ = ::pms::prof_event(c);                                              \
             (void)hipEventRecord(e1_, (c)->stream);                                             \
-            (c)->pend.push_back({(kid), e0_, e1_, (double)(bytes)});                            \
+            (c)->pend.push_back({(kid), e0_, e1_, (double)(bytes), 0.0});                       \
         }                                                                                       \
     } while (0)
 

@@ -63,6 +63,9 @@ enum StatId {
     S_T_SHORT, S_T_LONG, S_T_GLOBAL, S_T_SUML, S_T_CTOG, S_T_CNEXT, S_T_CFLUSH, S_T_FLUSHES, S_T_QUEUED,
     S_T_LANE, S_T_BAIL, S_LBYTES, S_T_FROMP, S_T_DEL, S_T_LSUML, S_T_LGT16, S_T_LGT32,
     S_WBYTES, S_T_WIDE, S_T_TOWIDE, S_T_LITER, S_T_LREFILL, S_T_LFLUSH, S_T_LBUSY, S_T_LLONG, S_T_LTOG, S_T_LTROUND,
+    // bytes of the additions by the unit cost of one column addition,
+    // 4 (len t + len s + len t+s), per kernel
+    S_ABYTES_XOR, S_ABYTES_LANE, S_ABYTES_WIDE, S_ABYTES_CHAIN,
     S_NUM
 };
 
@@ -74,6 +77,10 @@ struct Counters {
     unsigned long long chain_bytes;  // algorithmic bytes moved by k_chain
     unsigned long long lane_bytes;   // algorithmic bytes moved by k_chain_lane
     unsigned long long wide_bytes;   // algorithmic bytes moved by k_chain_wide
+    // 4 (len t + len s + len t+s) summed over the additions of k_xor, the two
+    // lane passes and k_chain (the bytes of a column addition by itself)
+    unsigned long long abytes_xor, abytes_lane, abytes_wide, abytes_chain;
+    unsigned long long active_sum;   // sum over rounds of the round's active columns
     unsigned long long diag_low_l1;  // diagnostics: sum_j (low(j) + 1)
     unsigned long long diag_ess;     // diagnostics: |E|
     unsigned long long diag_active;  // diagnostics: columns neither pivot nor zero
@@ -90,7 +97,21 @@ struct Counters {
     int32_t max_chain;   // trace: most additions one column made in k_chain this round
     int32_t n_cur;       // active columns of the current round (read by the round kernels)
     uint32_t round;      // rounds that did work so far
+    int32_t dbg_flags;   // debug_invariants: the invariants found broken (DbgBit)
+    int32_t dbg_col;     // a column or row that broke one
     unsigned long long trace[S_NUM];  // folded stripes (trace output)
+};
+
+// debug_invariants: one bit per property checked
+enum DbgBit : int32_t {
+    DBG_LOW_ROSE = 1,        // a column's low increased
+    DBG_BETA_ABOVE = 2,      // beta_j > low(j) (P.5)
+    DBG_BETA_ZERO = 4,       // beta_j defined but column j zero (P.3)
+    DBG_PIVOT_CHANGED = 8,   // a pivot column changed, or stopped being one
+    DBG_PIVOT_TABLE = 16,    // piv / low_star do not name a pivot
+    DBG_DOUBLE_WRITE = 32,   // a column written twice by one kernel launch
+    DBG_ESS_REMOVED = 64,    // an essential simplex left the estimate E
+    DBG_FINAL = 128          // low* is not the last low seen, or beta_j > low*(j)
 };
 
 // Everything a chained addition needs about row i, in one 32-byte record
@@ -138,7 +159,27 @@ struct Dev {
     int32_t *wq;       // columns handed from the lane chain passes to the wavefront kernel
     int32_t *wq2;      // columns the first lane pass hands to the wide one (too long for its buffer)
     uint32_t *ess;     // diagnostics: the essential estimate E as a bitmask (null when off)
+    // debug_invariants (null when off): the last round's low, header and
+    // state of every column, writes per column in the current kernel, and
+    // the round at which each index left the essential estimate
+    int32_t *dbg_low;
+    int64_t *dbg_off;
+    int32_t *dbg_len;
+    uint8_t *dbg_state;
+    int32_t *dbg_w;
+    int32_t *dbg_erem;
 };
+
+// debug_invariants: one more write of column j by the current kernel
+__device__ inline void dbg_write(const Dev &d, int64_t j)
+{
+    if (d.dbg_w) atomicAdd(&d.dbg_w[j], 1);
+}
+
+__device__ inline void dbg_fail(const Dev &d, int32_t bit, int64_t j)
+{
+    if (atomicOr(&d.cnt->dbg_flags, bit) == 0) d.cnt->dbg_col = (int32_t)j;
+}
 
 constexpr int kStripe = 64;
 constexpr int kPart = 64;
@@ -300,6 +341,7 @@ __global__ void k_low(Dev d, const int32_t *act)
         const int64_t q = t * blockDim.x + threadIdx.x;
         if (q >= nA) continue;
         const int32_t j = act[q];
+        dbg_write(d, j);
         int32_t n = d.len[j];
         const int32_t *c = col_base(d, d.off[j]);
         // rows of known-negative simplices at the bottom of the column are
@@ -458,9 +500,13 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
             }
             d.prec[i] = r;
             d.state[j] = ST_PIVOT;
+            dbg_write(d, j);
             d.low_star[j] = i;
             if (compression) d.prec[j].k = -1;
-            if (d.state[i] == ST_ACTIVE) d.state[i] = ST_CLEARED;  // clearing: sigma_i is positive
+            if (d.state[i] == ST_ACTIVE) {
+                d.state[i] = ST_CLEARED;  // clearing: sigma_i is positive
+                dbg_write(d, i);
+            }
             np = 1;
             nb = by_beta ? 1 : 0;
         }
@@ -656,7 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     const int64_t bbase = s_base;
     if (threadIdx.x == 0 && bbase < 0) atomicExch(&d.cnt->overflow, 1);  // once per block: one flag for all
     if (target && bbase < 0) target = false;  // the column stays as it is this round
-    int64_t adds = 0, xe = 0, by = q < nA ? 6 : 0;  // act, state, coll
+    int64_t adds = 0, xe = 0, by = q < nA ? 6 : 0, ab = 0;  // act, state, coll
     bool push = false;
     if (target) {
         const int64_t dst = bbase + excl;
@@ -665,6 +711,8 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
         adds = 1;
         xe = (int64_t)tlen + slen;
         by += 42 + 4 * ((int64_t)tlen + slen + k) + 16;  // headers, low, piv/T, beta, dim; data in and out
+        ab = 4 * ((int64_t)tlen + slen + k);
+        dbg_write(d, j);
         d.off[j] = dst | (int64_t)kArenaBit;
         d.len[j] = k;
         if (k == 0) {
@@ -688,8 +736,10 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     const int64_t badds = block_sum64(adds);
     const int64_t bxe = block_sum64(xe);
     const int64_t bby = block_sum64(by);
+    const int64_t bab = block_sum64(ab);
     if (threadIdx.x == 0) {
         stat_add(d, S_XBYTES, (unsigned long long)bby, (unsigned)tile);
+        stat_add(d, S_ABYTES_XOR, (unsigned long long)bab, (unsigned)tile);
         stat_add(d, S_ADDS, (unsigned long long)badds, (unsigned)tile);
         stat_add(d, S_XE, (unsigned long long)bxe, (unsigned)tile);
     }
@@ -818,7 +868,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
     const unsigned gwave = blockIdx.x * (kThreads / kWave) + (unsigned)bcast_first(tid / kWave);
     // per-lane counts (32 bits: a lane makes a few thousand steps per launch;
     // the wave sums below are 64-bit)
-    uint32_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0;
+    uint32_t adds = 0, xe = 0, by = 0, bails = 0, towide = 0, ab = 0;
     int64_t tsl = 0, tg16 = 0, tg32 = 0;
     // wave state (uniform): unassigned tasks [tb, te) and the arena chunk [cb, ce);
     // the wave's tasks are the 64-task chunks gwave, gwave + nwaves, ... (shared
@@ -948,6 +998,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
             // progress dropped; the stored columns stay valid (one flag per wave)
             if (!room && lane == 0) atomicExch(&d.cnt->overflow, 1);
             if (wr && room) {
+                dbg_write(d, j);
                 const long long o = cb + incl - need;
                 int32_t *out = d.arena + o;
                 int32_t w = 0, r = 0;
@@ -1129,6 +1180,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                         adds++;
                         xe += (uint32_t)(LB + kk + 2);
                         by += 44u + 4u * (uint32_t)lk.k;
+                        ab += 4u * (uint32_t)((LB + 1) + lk.k + (LB + kk - 2 * c));
                         if (trace) {
                             tsl += LB + 1;
                             tlong++;
@@ -1183,6 +1235,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                 adds++;
                 xe += (uint32_t)(LB + np + kk + 1);
                 by += 32;
+                ab += 4u * (uint32_t)(2 * (LB + np + kk + 1) - 2);
                 if (trace) {
                     tsl += LB + np;
                     tg16 += LB + np > 16 ? 1 : 0;
@@ -1224,7 +1277,8 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
 #undef LW
     // counters: lane sums -> one atomic per wave
     const int64_t wadds = wave_incl_sum64((int64_t)adds), wxe = wave_incl_sum64((int64_t)xe),
-                  wby = wave_incl_sum64((int64_t)by), wb = wave_incl_sum64((int64_t)bails);
+                  wby = wave_incl_sum64((int64_t)by), wb = wave_incl_sum64((int64_t)bails),
+                  wab = wave_incl_sum64((int64_t)ab);
     const int64_t wsl = trace ? wave_incl_sum64(tsl) : 0, wg16 = trace ? wave_incl_sum64(tg16) : 0,
                   wg32 = trace ? wave_incl_sum64(tg32) : 0, wtw = trace ? wave_incl_sum64((int64_t)towide) : 0,
                   wlg = trace ? wave_incl_sum64(tlong) : 0, wtg = trace ? wave_incl_sum64(ttog) : 0;
@@ -1232,6 +1286,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
         stat_add(d, S_ADDS, (unsigned long long)wadds, gwave);
         stat_add(d, S_XE, (unsigned long long)wxe, gwave);
         stat_add(d, kWide ? S_WBYTES : S_LBYTES, (unsigned long long)wby, gwave);
+        stat_add(d, kWide ? S_ABYTES_WIDE : S_ABYTES_LANE, (unsigned long long)wab, gwave);
         if (trace) {
             stat_add(d, kWide ? S_T_WIDE : S_T_LANE, (unsigned long long)wadds, gwave);
             stat_add(d, S_T_TOWIDE, (unsigned long long)wtw, gwave);
@@ -1307,7 +1362,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
     int4 *RPa = sRP[w][0], *RPb = sRP[w][1], *RWa = sRW[w][0], *RWb = sRW[w][1];
     const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
-    int64_t adds = 0, xe = 0, by = 0;
+    int64_t adds = 0, xe = 0, by = 0, ab = 0;
     // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P, deletions
     unsigned long long tr[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (kTrace && gw == 0) tr[8] = (unsigned long long)total;
@@ -1334,6 +1389,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         int4 lea, leb;            // and entries (e[0], e[1] in lea.z, lea.w; e[2..5] in leb)
         bool dirty = false, failed = false;
         int32_t cadds = 0, cxe = 0, cby = 0;  // this column's counters (32-bit: cheap in the loop)
+        int64_t cab = 0;
 
         auto Bp = [&]() -> const int32_t * { return in_lds ? (const int32_t *)sW[w][cur] : Bg; };
         auto refill = [&]() {
@@ -1535,6 +1591,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                     from_p = false;  // W is unchanged: its low is now the top of B
                 }
                 cby += 32;  // the record of the low
+                cab += 4 * (2 * (int64_t)(LB + __popcll(valid) + lk) - 2);
                 if (kTrace) {
                     tr[0]++;
                     tr[3] += LB + __popcll(valid);
@@ -1590,6 +1647,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                         if (!(qq < L && W[qq] == x)) Wn[b + qq - 2 * sE[w][b]] = x;
                     }
                     LB = L + k - 2 * carry;
+                    cab += 4 * ((int64_t)L + k + LB);
                     wave_sync();
                     cur ^= 1;
                 } else {
@@ -1612,6 +1670,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
                     Bg = out;
                     in_lds = false;
                     LB = nL;
+                    cab += 4 * ((int64_t)L + k + nL);
                 }
                 dirty = true;
                 refill();
@@ -1628,11 +1687,13 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         adds += cadds;
         xe += cxe;
         by += cby;
+        ab += cab;
         if (kTrace && lane == 0) atomicMax(&d.cnt->max_chain, cadds);
         if (failed || !dirty) continue;
         // write the result back
         if (LB == 0) {
             if (lane == 0) {
+                dbg_write(d, j);
                 d.len[j] = 0;
                 d.low[j] = -1;
                 d.state[j] = ST_ZERO;  // column j is positive
@@ -1654,6 +1715,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         } else {
             if (Bg == g) {  // only deletions at the top: the stored column, shortened
                 if (lane == 0) {
+                    dbg_write(d, j);
                     d.len[j] = LB;
                     d.low[j] = Bg[LB - 1];
                 }
@@ -1663,6 +1725,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         }
         by += 4 * (int64_t)LB + 16;  // column and header out
         if (lane == 0) {
+            dbg_write(d, j);
             d.off[j] = dst | (int64_t)kArenaBit;
             d.len[j] = LB;
             d.low[j] = in_lds ? sW[w][cur][LB - 1] : Bg[LB - 1];
@@ -1674,6 +1737,7 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
         stat_add(d, S_ADDS, (unsigned long long)adds, gw);
         stat_add(d, S_XE, (unsigned long long)xe, gw);
         stat_add(d, S_CBYTES, (unsigned long long)by, gw);
+        stat_add(d, S_ABYTES_CHAIN, (unsigned long long)ab, gw);
         if (kTrace) {
             for (int q = 0; q < 9; q++) stat_add(d, S_T_SHORT + q, tr[q], gw);
             stat_add(d, S_T_FROMP, tr[9], gw);
@@ -1713,6 +1777,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, c
         j = act[q];
         const uint8_t st = d.state[j];
         if (st == ST_CLEARED) {
+            dbg_write(d, j);
             d.state[j] = ST_ZERO;
             d.len[j] = 0;
             d.low[j] = -1;
@@ -1784,6 +1849,72 @@ __global__ void k_diag_init(uint32_t *ess, int64_t m, int64_t nwords)
     }
 }
 
+// ---------------------------------------------------------------- debug_invariants
+// The current low of column j as the round kernels see it: a pivot's low, an
+// active column's last row that is not known negative, -1 otherwise.
+__device__ inline int32_t dbg_cur_low(const Dev &d, int64_t j, uint8_t st, int compression)
+{
+    if (st == ST_PIVOT) return d.low[j];
+    if (st != ST_ACTIVE) return -1;
+    int32_t n = d.len[j];
+    const int32_t *c = col_base(d, d.off[j]);
+    if (compression)
+        while (n > 0 && is_neg(d.neg, c[n - 1])) n--;
+    return n > 0 ? c[n - 1] : -1;
+}
+
+// After Phase 0 (first = 1: records the starting state) and after every
+// round: lows never rise (Sec. 3.1), beta_j <= low(j) and beta_j defined =>
+// column j not zero (Thm. "Properties of beta_j" P.5, P.3), a pivot column is
+// frozen and named by piv and low_star; and the indices that leave the
+// essential estimate this round (known negative columns and every current
+// low, eq. "essential_iteration") get the round as their stamp.
+__global__ void __launch_bounds__(kBlock) k_dbg_round(Dev d, int compression, int first, int32_t round)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t st = d.state[j];
+        const int32_t lo = dbg_cur_low(d, j, st, compression);
+        const int32_t b = d.beta[j];
+        if (!first) {
+            if (lo > d.dbg_low[j]) dbg_fail(d, DBG_LOW_ROSE, j);
+            if (d.dbg_state[j] == ST_PIVOT &&
+                (st != ST_PIVOT || d.off[j] != d.dbg_off[j] || d.len[j] != d.dbg_len[j] || lo != d.dbg_low[j]))
+                dbg_fail(d, DBG_PIVOT_CHANGED, j);
+        }
+        if (b >= 0 && (st == ST_ZERO || st == ST_CLEARED)) dbg_fail(d, DBG_BETA_ZERO, j);
+        if (b >= 0 && lo >= 0 && b > lo) dbg_fail(d, DBG_BETA_ABOVE, j);
+        if (st == ST_PIVOT && (lo < 0 || d.piv[lo] != (int32_t)j || d.low_star[j] != lo))
+            dbg_fail(d, DBG_PIVOT_TABLE, j);
+        d.dbg_low[j] = lo;
+        d.dbg_state[j] = st;
+        d.dbg_off[j] = d.off[j];
+        d.dbg_len[j] = d.len[j];
+        if (st == ST_PIVOT || b >= 0) atomicMin(&d.dbg_erem[j], round);
+        if (lo >= 0) atomicMin(&d.dbg_erem[lo], round);
+    }
+}
+
+// After each kernel that writes columns: no column was written twice.
+__global__ void __launch_bounds__(kBlock) k_dbg_writes(Dev d)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+        if (d.dbg_w[j] > 1) dbg_fail(d, DBG_DOUBLE_WRITE, j);
+        d.dbg_w[j] = 0;
+    }
+}
+
+// After finalisation: low*(j) is the last low seen, beta_j <= low*(j), and no
+// essential simplex (low*(i) = -1 and no column's low*) ever left E.
+__global__ void __launch_bounds__(kBlock) k_dbg_final(Dev d)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.m; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t ls = d.low_star[j];
+        if (ls != d.dbg_low[j] || (d.beta[j] >= 0 && d.beta[j] > ls)) dbg_fail(d, DBG_FINAL, j);
+        if (ls >= 0 && d.piv[ls] != (int32_t)j) dbg_fail(d, DBG_PIVOT_TABLE, j);
+        if (ls < 0 && d.piv[j] < 0 && d.dbg_erem[j] != 0x7FFFFFFF) dbg_fail(d, DBG_ESS_REMOVED, j);
+    }
+}
+
 __global__ void k_round_init(Dev d, int32_t m)
 {
     d.cnt->n_cur = m;
@@ -1794,6 +1925,7 @@ __global__ void k_round_init(Dev d, int32_t m)
 // work advances the round number (the T table's stamp).
 __global__ void k_round_end(Dev d)
 {
+    d.cnt->active_sum += (unsigned long long)d.cnt->n_cur;
     if (d.cnt->n_cur > 0) d.cnt->round = d.cnt->round + 1;
     d.cnt->n_cur = d.cnt->n_next;
     unsigned long long fr = 0;  // a partition past its end is full
@@ -1894,6 +2026,10 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->chain_bytes = s_sum[S_CBYTES];
         d.cnt->lane_bytes = s_sum[S_LBYTES];
         d.cnt->wide_bytes = s_sum[S_WBYTES];
+        d.cnt->abytes_xor = s_sum[S_ABYTES_XOR];
+        d.cnt->abytes_lane = s_sum[S_ABYTES_LANE];
+        d.cnt->abytes_wide = s_sum[S_ABYTES_WIDE];
+        d.cnt->abytes_chain = s_sum[S_ABYTES_CHAIN];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
         for (int q = 0; q < S_NUM; q++) d.cnt->trace[q] = s_sum[q];
@@ -1974,6 +2110,7 @@ void prof_flush(Ctx *c)
             c->prof_ms[p.kid] += ms;
             c->prof_launches[p.kid] += 1;
             if (p.bytes > 0) c->prof_bytes[p.kid] += p.bytes;
+            c->prof_abytes[p.kid] += p.abytes;
         }
         if (p.e0) c->ev_pool.push_back(p.e0);
         if (p.e1) c->ev_pool.push_back(p.e1);
@@ -2022,9 +2159,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     res->rounds = 0;
     res->phase0_pivots = 0;
     res->additions = res->xor_entries = 0;
+    res->active_sum = res->addition_bytes = 0;
     c->diag.clear();
     c->diag_m = -1;
     const bool diag = opt->diagnostics != 0;
+    const bool dbg = opt->debug_invariants != 0;
     if (m == 0) {
         if (diag) {
             c->diag.push_back(pms_round_stats{0, 0, 0, 0, 0, 0, 0});
@@ -2075,6 +2214,16 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec || !d.wq ||
         !d.wq2)
         return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
+    if (dbg) {
+        d.dbg_low = (int32_t *)scratch(c, B_DBG_LOW, m * 4);
+        d.dbg_off = (int64_t *)scratch(c, B_DBG_OFF, m * 8);
+        d.dbg_len = (int32_t *)scratch(c, B_DBG_LEN, m * 4);
+        d.dbg_state = (uint8_t *)scratch(c, B_DBG_STATE, m);
+        d.dbg_w = (int32_t *)scratch(c, B_DBG_W, m * 4);
+        d.dbg_erem = (int32_t *)scratch(c, B_DBG_EREM, m * 4);
+        if (!d.dbg_low || !d.dbg_off || !d.dbg_len || !d.dbg_state || !d.dbg_w || !d.dbg_erem)
+            return set_err(c, PMS_ERR_OOM, "debug scratch allocation failed");
+    }
 
     // arena: sized for the first rounds' fill-in, grown on demand
     unsigned long long want = (unsigned long long)(4 * nnz) + (1ull << 22);
@@ -2109,6 +2258,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
     PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act0, m);
     PMS_LAUNCH(c, K_FILL, 0, k_round_init, 1, 1, d, (int32_t)m);
+    if (dbg) {
+        PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, gm, kBlock, d.dbg_w, m, 0);
+        PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, gm, kBlock, d.dbg_erem, m, 0x7FFFFFFF);
+        PMS_LAUNCH(c, K_FILL, 0, k_dbg_round, gm, kBlock, d, opt->compression, 1, 0);
+    }
     PMS_HIP(hipGetLastError());
 
     Counters *h = (Counters *)c->host_pinned;
@@ -2116,10 +2270,34 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     PMS_HIP(hipStreamSynchronize(st));
     if (h->error) return set_err(c, PMS_ERR_NOT_COMPATIBLE, "boundary matrix is not that of a compatible filtration "
                                                             "(rows must ascend, lie above the diagonal and be facets)");
+    // debug_invariants: the first broken property, by name
+    auto dbg_check = [&](const char *where, int32_t r) -> pms_status {
+        if (!h->dbg_flags) return PMS_OK;
+        static const char *const names[] = {
+            "a column's low increased (lows only decrease, Sec. 3.1)",
+            "beta_j > low(j) (Thm. \"Properties of beta_j\" P.5)",
+            "a column with beta_j defined became zero (Thm. \"Properties of beta_j\" P.3)",
+            "a pivot column changed after it was found",
+            "piv / low_star do not name a pivot column",
+            "a column was written twice by one kernel launch",
+            "an essential simplex left the essential estimate (Lemma \"Essential estimation\")",
+            "low* differs from the last low, or beta_j > low*(j)"};
+        int bit = 0;
+        while (!((h->dbg_flags >> bit) & 1)) bit++;
+        return set_err(c, PMS_ERR_INVARIANT,
+                       std::string("invariant broken ") + where + " " + std::to_string(r) + ": " + names[bit] +
+                           " (column or row " + std::to_string(h->dbg_col) + ", flags " +
+                           std::to_string(h->dbg_flags) + ")");
+    };
+    {
+        const pms_status sdb = dbg_check("after Phase 0, round", 0);
+        if (sdb != PMS_OK) return sdb;
+    }
 
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
     unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0, wide_bytes_prev = 0;
+    unsigned long long ab_prev[4] = {0, 0, 0, 0};
     const char *tr_env = getenv("PMS_TRACE");
     const int trace = tr_env && tr_env[0] == '1';
     unsigned long long tprev[S_NUM] = {};
@@ -2137,14 +2315,17 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         const double dt = (double)grid_tiles;
         // act, len, off, last row, low out, T atomic
         PMS_LAUNCH(c, K_LOW, 32 * dA, k_low, gA, kBlock, d, a);
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         // act, state, low, T, piv, coll out, dim; block aggregates
         PMS_LAUNCH(c, K_COLLIDE, 23 * dA + 16 * dt, k_collide, gT, kBlock, d, a, agg);
         PMS_LAUNCH(c, K_SCAN, 32 * dt, k_scan_max4, 1, kScanThreads, agg, &d.cnt->n_cur);
         // act, state, low, coll, dim, beta; aggregates
         PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, gT, kBlock, d, a, agg, opt->compression);
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, gT, kBlock, d, a, opt->variant, opt->compression, opt->chain,
                    opt->tail_active);
         xor_slot = c->pend.size() - 1;
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (trace)
             PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<true>, (unsigned)tn.lane_blocks, kLaneThreads, d,
                        opt->compression, tn);
@@ -2152,6 +2333,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<false>, (unsigned)tn.lane_blocks, kLaneThreads, d,
                        opt->compression, tn);
         lane_slot = c->pend.size() - 1;
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (trace)
             PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<true>, (unsigned)tn.wide_blocks, kWideThreads, d,
                        opt->compression, tn);
@@ -2159,15 +2341,18 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<false>, (unsigned)tn.wide_blocks, kWideThreads, d,
                        opt->compression, tn);
         wide_slot = c->pend.size() - 1;
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (trace)
             PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         else
             PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         chain_slot = c->pend.size() - 1;
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
         // act, state, act_next
         PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an);
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (c->prof_on || trace || diag) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
         PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, 1, d);
         return PMS_OK;
@@ -2226,7 +2411,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // list ends where it started) captured once into a HIP graph and
     // replayed, one host synchronisation per replay; rounds after
     // convergence find no active column and return at once.
-    const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && !diag && opt->max_rounds == 0)
+    const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && !diag && !dbg && opt->max_rounds == 0)
                             ? (opt->graph_rounds + 1) & ~1 : 0;
     if (graph_k > 0) {
         // fixed grids: enough blocks to fill the device, looping over tiles
@@ -2321,6 +2506,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             sr = launch_diag();
             if (sr != PMS_OK) return sr;
         }
+        if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_round, gm, kBlock, d, opt->compression, 0, (int32_t)round + 1);
         PMS_HIP(hipGetLastError());
         PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
         PMS_HIP(hipStreamSynchronize(st));
@@ -2335,6 +2521,12 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             lane_bytes_prev = h->lane_bytes;
             c->pend[wide_slot].bytes = (double)(h->wide_bytes - wide_bytes_prev);
             wide_bytes_prev = h->wide_bytes;
+            const unsigned long long abn[4] = {h->abytes_xor, h->abytes_lane, h->abytes_wide, h->abytes_chain};
+            const size_t slots[4] = {xor_slot, lane_slot, wide_slot, chain_slot};
+            for (int q = 0; q < 4; q++) {
+                c->pend[slots[q]].abytes = (double)(abn[q] - ab_prev[q]);
+                ab_prev[q] = abn[q];
+            }
             prof_flush(c);
         }
         if (trace) {
@@ -2361,6 +2553,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         if (h->bad_source)
             return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
                                                                 : "internal: a chained addition did not lower the low");
+        {
+            const pms_status sdb = dbg_check("in round", (int32_t)round);
+            if (sdb != PMS_OK) return sdb;
+        }
         if (h->overflow || grow_early(h->n_next)) {
             pms_status s = grow_arena(c, d, h, h->overflow ? 0 : want_cap);
             if (s != PMS_OK) return s;
@@ -2371,11 +2567,18 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         std::swap(act, act_next);
     }
     PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
+    if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_final, gm, kBlock, d);
     PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     PMS_HIP(hipStreamSynchronize(st));
+    {
+        const pms_status sdb = dbg_check("at the end, after round", (int32_t)round);
+        if (sdb != PMS_OK) return sdb;
+    }
     res->rounds = (int32_t)round;
     res->additions = (int64_t)h->additions;
     res->xor_entries = (int64_t)h->xor_entries;
+    res->active_sum = (int64_t)h->active_sum;
+    res->addition_bytes = (int64_t)(h->abytes_xor + h->abytes_lane + h->abytes_wide + h->abytes_chain);
     res->phase0_pivots = h->beta_pivots;
 
     // pairs and essential simplices, canonical order
@@ -2468,6 +2671,8 @@ pms_options pms_default_options(void)
     o.graph_rounds = 0;
     o.diagnostics = 0;
     o.arena_entries = 0;
+    o.debug_invariants = 0;
+    o.reserved = 0;
     return o;
 }
 
@@ -2520,6 +2725,7 @@ pms_status pms_profile_enable(pms_ctx *c, int enable)
     for (int k = 0; k < pms::K_NUM; k++) {
         c->prof_ms[k] = 0;
         c->prof_bytes[k] = 0;
+        c->prof_abytes[k] = 0;
         c->prof_launches[k] = 0;
     }
     c->prof_on = enable != 0;
@@ -2527,6 +2733,98 @@ pms_status pms_profile_enable(pms_ctx *c, int enable)
 }
 
 int pms_profile_kernels(void) { return pms::K_NUM; }
+
+// The debug_invariants detectors on fabricated states of an 8-column
+// matrix (column j >= 1 holds the single row j - 1): a consistent state
+// raises nothing, and each state that breaks one property raises exactly
+// that property's bit.
+static pms_status debug_selftest(pms::Ctx *c)
+{
+    using namespace pms;
+    constexpr int M = 8;
+    struct Host {
+        int64_t off[M], dbg_off[M];
+        int32_t rows[M], len[M], low[M], beta[M], piv[M], low_star[M], dbg_low[M], dbg_len[M], dbg_w[M],
+            dbg_erem[M];
+        uint32_t neg[1];
+        uint8_t state[M], dbg_state[M];
+    };
+    Host h0{};
+    for (int j = 0; j < M; j++) {
+        h0.rows[j] = j;  // column j >= 1 is rows[j-1 .. j) = {j - 1}
+        h0.off[j] = h0.dbg_off[j] = j > 0 ? j - 1 : 0;
+        h0.len[j] = h0.dbg_len[j] = j > 0 ? 1 : 0;
+        h0.low[j] = h0.dbg_low[j] = j - 1;
+        h0.state[j] = h0.dbg_state[j] = j > 0 ? ST_ACTIVE : ST_ZERO;
+        h0.beta[j] = h0.piv[j] = h0.low_star[j] = -1;
+        h0.dbg_w[j] = 0;
+        h0.dbg_erem[j] = 0x7FFFFFFF;
+    }
+    h0.neg[0] = 0;
+    Host *dv = (Host *)scratch(c, B_TMP0, sizeof(Host) + sizeof(Counters) + 256);
+    if (!dv) return set_err(c, PMS_ERR_OOM, "scratch");
+    Counters *cnt = (Counters *)((char *)dv + ((sizeof(Host) + 255) / 256) * 256);
+    Dev d{};
+    d.m = M;
+    d.rows = dv->rows;
+    d.off = dv->off;
+    d.len = dv->len;
+    d.low = dv->low;
+    d.state = dv->state;
+    d.beta = dv->beta;
+    d.piv = dv->piv;
+    d.low_star = dv->low_star;
+    d.neg = dv->neg;
+    d.cnt = cnt;
+    d.dbg_low = dv->dbg_low;
+    d.dbg_off = dv->dbg_off;
+    d.dbg_len = dv->dbg_len;
+    d.dbg_state = dv->dbg_state;
+    d.dbg_w = dv->dbg_w;
+    d.dbg_erem = dv->dbg_erem;
+    // kind 0: the round check, 1: the write check, 2: the final check
+    auto run = [&](const Host &h, int kind, int32_t want) -> pms_status {
+        PMS_HIP(hipMemcpyAsync(dv, &h, sizeof(Host), hipMemcpyHostToDevice, c->stream));
+        PMS_HIP(hipMemsetAsync(cnt, 0, sizeof(Counters), c->stream));
+        if (kind == 0) k_dbg_round<<<1, kBlock, 0, c->stream>>>(d, 1, 0, 1);
+        else if (kind == 1) k_dbg_writes<<<1, kBlock, 0, c->stream>>>(d);
+        else k_dbg_final<<<1, kBlock, 0, c->stream>>>(d);
+        PMS_HIP(hipGetLastError());
+        int32_t got = -1;
+        PMS_HIP(hipMemcpyAsync(&got, &cnt->dbg_flags, 4, hipMemcpyDeviceToHost, c->stream));
+        PMS_HIP(hipStreamSynchronize(c->stream));
+        if (got != want)
+            return set_err(c, PMS_ERR_HIP, "debug_invariants detector self-test: kind " + std::to_string(kind) +
+                                               " raised " + std::to_string(got) + ", expected " +
+                                               std::to_string(want));
+        return PMS_OK;
+    };
+    pms_status s;
+    Host h = h0;
+    if ((s = run(h, 0, 0)) != PMS_OK) return s;
+    h = h0; h.dbg_low[5] = 2;  // column 5's low is 4 now: it rose
+    if ((s = run(h, 0, DBG_LOW_ROSE)) != PMS_OK) return s;
+    h = h0; h.beta[5] = 5;     // above low(5) = 4
+    if ((s = run(h, 0, DBG_BETA_ABOVE)) != PMS_OK) return s;
+    h = h0; h.beta[0] = 0;     // column 0 is zero
+    if ((s = run(h, 0, DBG_BETA_ZERO)) != PMS_OK) return s;
+    h = h0; h.dbg_state[3] = ST_PIVOT;  // a pivot that is active again
+    if ((s = run(h, 0, DBG_PIVOT_CHANGED)) != PMS_OK) return s;
+    h = h0; h.state[3] = ST_PIVOT;      // a pivot no table names
+    if ((s = run(h, 0, DBG_PIVOT_TABLE)) != PMS_OK) return s;
+    h = h0;
+    if ((s = run(h, 1, 0)) != PMS_OK) return s;
+    h.dbg_w[6] = 2;
+    if ((s = run(h, 1, DBG_DOUBLE_WRITE)) != PMS_OK) return s;
+    Host f = h0;  // a finished reduction with every column zero
+    for (int j = 0; j < M; j++) f.dbg_low[j] = -1;
+    if ((s = run(f, 2, 0)) != PMS_OK) return s;
+    h = f; h.dbg_erem[7] = 1;  // simplex 7 is essential but left E in round 1
+    if ((s = run(h, 2, DBG_ESS_REMOVED)) != PMS_OK) return s;
+    h = f; h.low_star[3] = 2; h.piv[2] = 3; h.dbg_low[3] = 1;  // low* is not the last low
+    if ((s = run(h, 2, DBG_FINAL)) != PMS_OK) return s;
+    return PMS_OK;
+}
 
 pms_status pms_selftest(pms_ctx *c)
 {
@@ -2542,7 +2840,7 @@ pms_status pms_selftest(pms_ctx *c)
     PMS_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, c->stream));
     PMS_HIP(hipStreamSynchronize(c->stream));
     if (h != 0) return pms::set_err(c, PMS_ERR_HIP, "wave reduction self-test failed");
-    return PMS_OK;
+    return debug_selftest(c);
 }
 
 const char *pms_profile_kernel_name(int k) { return (k >= 0 && k < pms::K_NUM) ? kKernelNames[k] : nullptr; }
@@ -2555,6 +2853,15 @@ pms_status pms_profile_read(pms_ctx *c, int k, double *total_ms, int64_t *launch
     if (total_ms) *total_ms = c->prof_ms[k];
     if (launches) *launches = c->prof_launches[k];
     if (bytes) *bytes = c->prof_bytes[k];
+    return PMS_OK;
+}
+
+pms_status pms_profile_read_addition_bytes(pms_ctx *c, int k, double *bytes)
+{
+    if (!c || k < 0 || k >= pms::K_NUM || !bytes) return PMS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PMS_ERR_HIP;
+    pms::prof_flush(c);
+    *bytes = c->prof_abytes[k];
     return PMS_OK;
 }
 
@@ -2574,7 +2881,8 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "null col_ptr / rows / low_star");
     pms_options o = opt ? *opt : pms_default_options();
     if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0 || o.graph_rounds < 0 ||
-        o.graph_rounds > 1024 || o.diagnostics < 0 || o.diagnostics > 1)
+        o.graph_rounds > 1024 || o.diagnostics < 0 || o.diagnostics > 1 || o.debug_invariants < 0 ||
+        o.debug_invariants > 1 || o.reserved != 0)
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
     pms_status s = pms::reduce_impl(c, bnd, &o, res);

@@ -39,7 +39,8 @@ def test_options_layout_and_defaults():
     lib = _binding.load()
     o = lib.pms_default_options()
     assert (o.variant, o.compression, o.max_rounds, o.chain, o.validate, o.arena_entries) == (0, 1, 0, 1, 1, 0)
-    assert ctypes.sizeof(_binding.PmsOptions) == 40
+    assert ctypes.sizeof(_binding.PmsOptions) == 48
+    assert (o.debug_invariants, o.reserved) == (0, 0)
     assert ctypes.sizeof(_binding.PmsBoundary) == 32
     assert lib.pms_version().decode().startswith("pms-gfx950")
     # no context: the error text is static, and a null handle is rejected

@@ -174,9 +174,12 @@ def test_vr_grad_vs_fp64_and_fd(gpu):
             skipped += 1
             continue
         fd = (lp - lm) / (2 * h)
+        # the loss is a quartic polynomial where the pairs stay put: the
+        # central difference's truncation error at h = 1e-4 is ~h^2, so FD
+        # and the FP64 gradient agree to ~1e-7, FD and FP32 to the FP32 bound
         scale = max(1.0, np.abs(ref0).max())
-        assert abs(fd - ref0.reshape(-1)[k]) <= 1e-4 * scale, (k, fd, ref0.reshape(-1)[k])
-        assert abs(fd - got[0].reshape(-1)[k]) <= 1e-4 * scale, (k, fd, got[0].reshape(-1)[k])
+        assert abs(fd - ref0.reshape(-1)[k]) <= 1e-7 * scale, (k, fd, ref0.reshape(-1)[k])
+        assert abs(fd - got[0].reshape(-1)[k]) <= TOL * scale, (k, fd, got[0].reshape(-1)[k])
         checked += 1
     assert checked >= 6, (checked, skipped)
 

@@ -199,3 +199,47 @@ def test_graph_rounds_arena_regrowth(gpu):
     ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
     _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=1024, graph_rounds=4), ref)
     _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
+
+
+def _long_pivot_matrix(seed):
+    """A boundary matrix (no dimensions) whose chains need pivot columns far
+    longer than an LDS buffer: rows 0..7999 are empty columns; ten pivots
+    P_a hold 600..2000 random rows below 6000 plus the row 7990 - a as their
+    low; short pivots Q_r = {r-3, r-2, r-1, r} own the rows r in [6003, 7000);
+    sixty targets hold all ten lows of the P_a, a few rows in [6003, 7000) and
+    a few rows below 6000.  A target's first addition (P_0) leaves it with
+    P_1's low: its chain then merges the long P_a one after another, grows
+    past the LDS buffer, and walks down the short pivots from global memory."""
+    rng = np.random.default_rng(seed)
+    B = 8000
+    cols = [[] for _ in range(B)]
+    for a in range(10):
+        k = int(rng.integers(600, 2001))
+        cols.append(sorted(rng.choice(6000, k - 1, replace=False).tolist()) + [7990 - a])
+    for r in range(6003, 7000):
+        cols.append([r - 3, r - 2, r - 1, r])
+    for _ in range(60):
+        extra = set(rng.choice(np.arange(6003, 7000), 4, replace=False).tolist())
+        extra |= set(rng.choice(6000, 5, replace=False).tolist())
+        cols.append(sorted(extra) + [7990 - a for a in range(9, -1, -1)])
+    cp = np.zeros(len(cols) + 1, np.int64)
+    cp[1:] = np.cumsum([len(c) for c in cols])
+    rows = np.concatenate([np.asarray(c, np.int32) for c in cols if c])
+    return cp, rows
+
+
+def test_long_pivots_global_paths(gpu, capfd, monkeypatch):
+    """The wavefront chain kernel's paths for columns and pivots too long for
+    LDS (a long pivot merged in global memory, and the working column flushed
+    to the arena) give the oracle's low*; the kernel's trace counters show
+    that the global-memory merge ran."""
+    monkeypatch.setenv("PMS_TRACE", "1")
+    for seed in (1, 2):
+        cp, rows = _long_pivot_matrix(seed)
+        ref = oracle.reduce_standard(cp, rows)
+        for kw in (dict(), dict(compression=False), dict(variant=1)):
+            res = _reduce(cp, rows, None, gpu, validate=False, tail_active=1 << 30, **kw)
+            _check(res, ref)
+    err = capfd.readouterr().err
+    glob = [int(x) for x in __import__("re").findall(r"global (\d+)", err)]
+    assert glob and sum(glob) > 0, err[-2000:]
