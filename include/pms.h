@@ -47,8 +47,10 @@ typedef enum {
     PMS_ERR_HIP = -4,            /* a HIP runtime call failed */
     PMS_ERR_NOT_CONVERGED = -5,  /* max_rounds reached before low was injective */
     PMS_ERR_CAPACITY = -6,       /* output buffers too small; counts hold the sizes */
-    PMS_ERR_INVARIANT = -7       /* debug_invariants: a property the theory guarantees
+    PMS_ERR_INVARIANT = -7,      /* debug_invariants: a property the theory guarantees
                                     did not hold (a library bug); the message names it */
+    PMS_ERR_TOO_LARGE = -8       /* pms_reduce_noalloc: the problem does not fit the
+                                    fixed region (use pms_reduce) */
 } pms_status;
 
 typedef struct pms_ctx pms_ctx;
@@ -178,6 +180,30 @@ typedef struct {
  * (Alg. "Finding local injections", Thms. "Local injection I/II") and
  * Phase II simultaneous column additions, with clearing and compression). */
 pms_status pms_reduce(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *opt, pms_result *res);
+
+/* Allocation-free reduction, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * it).  The same reduction and outputs as pms_reduce, but every scratch
+ * buffer -- per-column state, tables, queues, counters and the column arena
+ * -- is carved from one fixed device region of PMS_NOALLOC_BYTES per device,
+ * reserved when the library is loaded and held until the process ends; the
+ * call makes no device or pinned allocation and frees nothing.
+ *   - Limits: the per-column state takes about 100 bytes per column (130
+ *     with debug_invariants) and the arena at least 4 nnz + 2^20 entries of
+ *     4 bytes; a matrix that does not fit, or whose fill-in outgrows the
+ *     arena during the reduction (the arena cannot grow), fails with
+ *     PMS_ERR_TOO_LARGE.  About 500 000 columns of a lower-star or
+ *     Vietoris-Rips filtration fit.
+ *   - Options: graph_rounds, diagnostics and arena_entries must be 0, and
+ *     the context's profiler off (PMS_ERR_INVALID_ARG otherwise).
+ *   - The region is shared by every context and call on a device and keeps
+ *     the last call's contents (each call clears what it needs): calls that
+ *     overlap in time on one device, from any context or stream, race and
+ *     give undefined results.  Serialise them.
+ * Everything else (ownership of inputs / outputs, statuses, synchronisation)
+ * is as for pms_reduce. */
+#define PMS_NOALLOC_BYTES (128ull << 20)
+pms_status pms_reduce_noalloc(pms_ctx *ctx, const pms_boundary *bnd, const pms_options *opt, pms_result *res);
 
 /* Reduce `count` filtrations concatenated block-diagonally (as built by
  * pms_build_vr_*: instance b owns the columns [inst_col_off[b],

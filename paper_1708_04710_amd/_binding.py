@@ -20,18 +20,21 @@ PMS_ERR_HIP = -4
 PMS_ERR_NOT_CONVERGED = -5
 PMS_ERR_CAPACITY = -6
 PMS_ERR_INVARIANT = -7
+PMS_ERR_TOO_LARGE = -8
+PMS_NOALLOC_BYTES = 128 << 20
 
 STATUS_NAMES = {
     PMS_OK: "PMS_OK", PMS_ERR_INVALID_ARG: "PMS_ERR_INVALID_ARG",
     PMS_ERR_NOT_COMPATIBLE: "PMS_ERR_NOT_COMPATIBLE", PMS_ERR_OOM: "PMS_ERR_OOM",
     PMS_ERR_HIP: "PMS_ERR_HIP", PMS_ERR_NOT_CONVERGED: "PMS_ERR_NOT_CONVERGED",
     PMS_ERR_CAPACITY: "PMS_ERR_CAPACITY", PMS_ERR_INVARIANT: "PMS_ERR_INVARIANT",
+    PMS_ERR_TOO_LARGE: "PMS_ERR_TOO_LARGE",
 }
 
 # every symbol include/pms.h declares (checked by the CPU test suite)
 EXPORTED = [
     "pms_create", "pms_destroy", "pms_last_error", "pms_version", "pms_selftest", "pms_default_options",
-    "pms_reduce", "pms_reduce_batched", "pms_round_stats_read", "pms_essential_estimate", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
+    "pms_reduce", "pms_reduce_noalloc", "pms_reduce_batched", "pms_round_stats_read", "pms_essential_estimate", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
     "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_profile_read_addition_bytes", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
     "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
@@ -116,6 +119,9 @@ def load(path: str = LIB_PATH):
     lib.pms_reduce.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                ctypes.POINTER(PmsResult)]
     lib.pms_reduce.restype = ctypes.c_int
+    lib.pms_reduce_noalloc.argtypes = [P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
+                                       ctypes.POINTER(PmsResult)]
+    lib.pms_reduce_noalloc.restype = ctypes.c_int
     lib.pms_reduce_batched.argtypes = [P, ctypes.c_int32, P, ctypes.POINTER(PmsBoundary), ctypes.POINTER(PmsOptions),
                                        ctypes.POINTER(PmsResult), P, P, P]
     lib.pms_reduce_batched.restype = ctypes.c_int

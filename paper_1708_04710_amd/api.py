@@ -260,14 +260,19 @@ def _result(res, t, **extra) -> ReduceResult:
                         addition_bytes=res.addition_bytes, **extra)
 
 
-def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off=None, **kw) -> ReduceResult:
+def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off=None, noalloc=False,
+                 **kw) -> ReduceResult:
     lib = B.load()
     ctx = _ctx(dev)
     bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
     opt = _options(**kw)
     res, t = _outputs(dev, m, outputs)
     extra = {}
-    if inst_col_off is None:
+    if noalloc:
+        if inst_col_off is not None:
+            raise ValueError("the allocation-free entry point reduces one matrix")
+        st = lib.pms_reduce_noalloc(ctx, ctypes.byref(bnd), ctypes.byref(opt), ctypes.byref(res))
+    elif inst_col_off is None:
         st = lib.pms_reduce(ctx, ctypes.byref(bnd), ctypes.byref(opt), ctypes.byref(res))
     else:
         nb = inst_col_off.numel() - 1
@@ -413,7 +418,9 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     or None.  All on the same device.  Keyword options as in ``pms_options``:
     variant, compression, max_rounds, chain, tail_active, validate,
     graph_rounds, arena_entries, diagnostics, debug_invariants; ``outputs=False``
-    skips the pair / essential lists."""
+    skips the pair / essential lists; ``noalloc=True`` calls the
+    allocation-free entry point (``pms_reduce_noalloc``; the output tensors
+    are still allocated here, by the caller of the library)."""
     if not col_ptr.is_cuda or not rows.is_cuda or (dim is not None and not dim.is_cuda):
         raise ValueError("col_ptr, rows and dim must be device tensors")
     if col_ptr.dtype != torch.int64 or rows.dtype != torch.int32 or (dim is not None and dim.dtype != torch.int8):

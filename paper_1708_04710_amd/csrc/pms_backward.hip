@@ -109,7 +109,7 @@ pms_status pms_gather(pms_ctx *ctx, const pms_filtration *fh, int64_t n, const i
     pms_status s = bw_prologue(ctx, fh, &c, &f);
     if (s != PMS_OK) return s;
     if (n < 0 || (n > 0 && !simplex)) return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad gather arguments");
-    int32_t *err = (int32_t *)pms::scratch(c, pms::B_TMP1, 64);
+    int32_t *err = (int32_t *)pms::grow_scratch(c, pms::B_TMP1, 64);
     if (!err) return pms::set_err(c, PMS_ERR_OOM, "scratch");
     PMS_HIP(hipMemsetAsync(err, 0, 4, c->stream));
     if (n > 0)
@@ -127,7 +127,7 @@ pms_status pms_backward_lowerstar(pms_ctx *ctx, const pms_filtration *fh, int64_
     if (s != PMS_OK) return s;
     if (n < 0 || (n > 0 && (!simplex || !grad || !grad_grid)))
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad backward arguments");
-    int32_t *err = (int32_t *)pms::scratch(c, pms::B_TMP1, 64);
+    int32_t *err = (int32_t *)pms::grow_scratch(c, pms::B_TMP1, 64);
     if (!err) return pms::set_err(c, PMS_ERR_OOM, "scratch");
     PMS_HIP(hipMemsetAsync(err, 0, 4, c->stream));
     if (n > 0)
@@ -145,7 +145,7 @@ pms_status pms_backward_vr_f32(pms_ctx *ctx, const pms_filtration *fh, int64_t n
     if (s != PMS_OK) return s;
     if (n < 0 || D < 1 || (n > 0 && (!simplex || !grad || !pts || !grad_pts)))
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad backward arguments");
-    int32_t *err = (int32_t *)pms::scratch(c, pms::B_TMP1, 64);
+    int32_t *err = (int32_t *)pms::grow_scratch(c, pms::B_TMP1, 64);
     if (!err) return pms::set_err(c, PMS_ERR_OOM, "scratch");
     PMS_HIP(hipMemsetAsync(err, 0, 4, c->stream));
     if (n > 0)

@@ -269,16 +269,16 @@ pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, in
     f->value_is_f32 = 1;
     hipStream_t s = c->stream;
     const int64_t nk = nv * kShapes;
-    unsigned long long *keys = (unsigned long long *)scratch(c, B_BUILD0, nk * 8);
-    unsigned long long *keys2 = (unsigned long long *)scratch(c, B_BUILD1, nk * 8);
-    int32_t *idx = (int32_t *)scratch(c, B_BUILD2, nk * 4);
+    unsigned long long *keys = (unsigned long long *)grow_scratch(c, B_BUILD0, nk * 8);
+    unsigned long long *keys2 = (unsigned long long *)grow_scratch(c, B_BUILD1, nk * 8);
+    int32_t *idx = (int32_t *)grow_scratch(c, B_BUILD2, nk * 4);
     const int64_t tiles = (m + kBlock - 1) / kBlock;
-    int64_t *tsum = (int64_t *)scratch(c, B_BUILD3, (tiles + 1) * 8);
-    int32_t *err = (int32_t *)scratch(c, B_BUILD4, 64);
+    int64_t *tsum = (int64_t *)grow_scratch(c, B_BUILD3, (tiles + 1) * 8);
+    int32_t *err = (int32_t *)grow_scratch(c, B_BUILD4, 64);
     if (!keys || !keys2 || !idx || !tsum || !err) return set_err(c, PMS_ERR_OOM, "builder scratch");
     size_t tmp_bytes = 0;
     PMS_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys2, (size_t)nk, 0, 64, s));
-    void *tmp = scratch(c, B_BUILD5, tmp_bytes);
+    void *tmp = grow_scratch(c, B_BUILD5, tmp_bytes);
     if (!tmp) return set_err(c, PMS_ERR_OOM, "sort scratch");
     PMS_HIP(hipMemsetAsync(err, 0, 4, s));
     // grid reads are cache resident; the key write is the stream

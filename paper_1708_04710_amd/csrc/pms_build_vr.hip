@@ -470,14 +470,14 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
     if (pbase >= 0x7FFFFFFF) return set_err(c, PMS_ERR_INVALID_ARG, "too many points");
     hipStream_t s = c->stream;
     const int64_t S = slots > 0 ? slots : 1;
-    VrInst *dinst = (VrInst *)scratch(c, B_BUILD6, (size_t)B * sizeof(VrInst));
-    unsigned long long *val = (unsigned long long *)scratch(c, B_BUILD7, S * 8);
-    unsigned long long *adj = (unsigned long long *)scratch(c, B_BUILD8, (adjw > 0 ? adjw : 1) * 8);
-    int64_t *ecnt = (int64_t *)scratch(c, B_BUILD9, (S + 1) * 8);
-    int64_t *tcnt = (int64_t *)scratch(c, B_BUILD10, (S + 1) * 8);
-    int64_t *tmp = (int64_t *)scratch(c, B_BUILD11, ((S + kBlock - 1) / kBlock + 2) * 8);
-    int32_t *err = (int32_t *)scratch(c, B_BUILD4, 64);
-    int64_t *qcnt = wide ? (int64_t *)scratch(c, B_BUILD14, (S + 1) * 8) : nullptr;
+    VrInst *dinst = (VrInst *)grow_scratch(c, B_BUILD6, (size_t)B * sizeof(VrInst));
+    unsigned long long *val = (unsigned long long *)grow_scratch(c, B_BUILD7, S * 8);
+    unsigned long long *adj = (unsigned long long *)grow_scratch(c, B_BUILD8, (adjw > 0 ? adjw : 1) * 8);
+    int64_t *ecnt = (int64_t *)grow_scratch(c, B_BUILD9, (S + 1) * 8);
+    int64_t *tcnt = (int64_t *)grow_scratch(c, B_BUILD10, (S + 1) * 8);
+    int64_t *tmp = (int64_t *)grow_scratch(c, B_BUILD11, ((S + kBlock - 1) / kBlock + 2) * 8);
+    int32_t *err = (int32_t *)grow_scratch(c, B_BUILD4, 64);
+    int64_t *qcnt = wide ? (int64_t *)grow_scratch(c, B_BUILD14, (S + 1) * 8) : nullptr;
     if (!dinst || !val || !adj || !ecnt || !tcnt || !tmp || !err || (wide && !qcnt))
         return set_err(c, PMS_ERR_OOM, "builder scratch");
     PMS_HIP(hipMemcpyAsync(dinst, h.data(), (size_t)B * sizeof(VrInst), hipMemcpyHostToDevice, s));
@@ -521,14 +521,14 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
     f->nnz = nnz;
     f->value_is_f32 = f32 ? 1 : 0;
     const int64_t M = m > 0 ? m : 1;
-    unsigned long long *keys = (unsigned long long *)scratch(c, B_BUILD0, M * 8);
-    unsigned long long *keys2 = (unsigned long long *)scratch(c, B_BUILD1, M * 8);
-    int32_t *vidx = (int32_t *)scratch(c, B_BUILD2, (pbase > 0 ? pbase : 1) * 4);
-    int32_t *eidx = (int32_t *)scratch(c, B_BUILD3, S * 4);
-    int64_t *colb = (int64_t *)scratch(c, B_TMP0, (size_t)(B + 1) * 8);
-    int32_t *seg = (int32_t *)scratch(c, B_TMP1, (size_t)(2 * B + 2) * 4);
+    unsigned long long *keys = (unsigned long long *)grow_scratch(c, B_BUILD0, M * 8);
+    unsigned long long *keys2 = (unsigned long long *)grow_scratch(c, B_BUILD1, M * 8);
+    int32_t *vidx = (int32_t *)grow_scratch(c, B_BUILD2, (pbase > 0 ? pbase : 1) * 4);
+    int32_t *eidx = (int32_t *)grow_scratch(c, B_BUILD3, S * 4);
+    int64_t *colb = (int64_t *)grow_scratch(c, B_TMP0, (size_t)(B + 1) * 8);
+    int32_t *seg = (int32_t *)grow_scratch(c, B_TMP1, (size_t)(2 * B + 2) * 4);
     const int64_t tiles = (m + kBlock - 1) / kBlock;
-    int64_t *tsum = (int64_t *)scratch(c, B_BUILD5, (tiles + 1) * 8);
+    int64_t *tsum = (int64_t *)grow_scratch(c, B_BUILD5, (tiles + 1) * 8);
     if (!keys || !keys2 || !vidx || !eidx || !colb || !seg || !tsum) return set_err(c, PMS_ERR_OOM, "builder scratch");
     PMS_HIP(hipMemcpyAsync(dinst, h.data(), (size_t)B * sizeof(VrInst), hipMemcpyHostToDevice, s));
     if (m == 0) {
@@ -549,8 +549,8 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         // two words, two stable radix passes: by lex, then by (cloud, value, dim)
         while (lexb < 63 && (1ll << lexb) < n_hi * n_hi * n_hi * n_hi) lexb++;
         const int hibits = (f32 ? kValueBitsF : kValueBitsI) + 2 + (B > 1 ? cbits : 0);
-        unsigned long long *hw = (unsigned long long *)scratch(c, B_BUILD12, M * 8);
-        unsigned long long *hw2 = (unsigned long long *)scratch(c, B_BUILD13, M * 8);
+        unsigned long long *hw = (unsigned long long *)grow_scratch(c, B_BUILD12, M * 8);
+        unsigned long long *hw2 = (unsigned long long *)grow_scratch(c, B_BUILD13, M * 8);
         if (!hw || !hw2) return set_err(c, PMS_ERR_OOM, "builder scratch");
         if (f32)
             PMS_LAUNCH(c, K_VR_TRI, 16.0 * m, (k_vr_emit<true, true>), g3, kBlock, dinst, val, adj, ecnt, tcnt, qcnt,
@@ -563,7 +563,7 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         size_t tb = 0, tb2 = 0;
         PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, hw, hw2, (size_t)m, 0, lexb, s));
         PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, hw2, hw, keys2, keys, (size_t)m, 0, hibits, s));
-        void *tmps = scratch(c, B_AGG, tb > tb2 ? tb : tb2);
+        void *tmps = grow_scratch(c, B_AGG, tb > tb2 ? tb : tb2);
         if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
         PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, hw, hw2, (size_t)m, 0, lexb, s));
         PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, hw2, hw, keys2, keys, (size_t)m, 0, hibits, s));
@@ -587,8 +587,8 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         const bool by_cloud = B > 1 && !one_pass && B <= 65536;
         uint16_t *cl = nullptr, *cl2 = nullptr;
         if (by_cloud) {
-            cl = (uint16_t *)scratch(c, B_BUILD12, M * 2);
-            cl2 = (uint16_t *)scratch(c, B_BUILD13, M * 2);
+            cl = (uint16_t *)grow_scratch(c, B_BUILD12, M * 2);
+            cl2 = (uint16_t *)grow_scratch(c, B_BUILD13, M * 2);
             if (!cl || !cl2) return set_err(c, PMS_ERR_OOM, "builder scratch");
         }
         if (f32)
@@ -603,14 +603,14 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         if (B == 1 || one_pass) {
             const int bits = keybits + (one_pass ? cbits : 0);
             PMS_HIP(rocprim::radix_sort_keys(nullptr, tb, keys, keys2, (size_t)m, 0, bits, s));
-            void *tmps = scratch(c, B_AGG, tb);
+            void *tmps = grow_scratch(c, B_AGG, tb);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
             PMS_HIP(rocprim::radix_sort_keys(tmps, tb, keys, keys2, (size_t)m, 0, bits, s));
         } else if (by_cloud) {
             size_t tb2 = 0;
             PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
             PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
-            void *tmps = scratch(c, B_AGG, tb > tb2 ? tb : tb2);
+            void *tmps = grow_scratch(c, B_AGG, tb > tb2 ? tb : tb2);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
             PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
             PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
@@ -618,7 +618,7 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         } else {
             PMS_HIP(rocprim::segmented_radix_sort_keys(nullptr, tb, keys, keys2, (unsigned)m, (unsigned)B, seg,
                                                        seg + B, 0, keybits, s));
-            void *tmps = scratch(c, B_AGG, tb);
+            void *tmps = grow_scratch(c, B_AGG, tb);
             if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
             PMS_HIP(rocprim::segmented_radix_sort_keys(tmps, tb, keys, keys2, (unsigned)m, (unsigned)B, seg, seg + B,
                                                        0, keybits, s));

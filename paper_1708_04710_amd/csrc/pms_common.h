@@ -115,7 +115,7 @@ static_assert(B_NUM <= 48, "Ctx::b holds 48 buffers");
 
 // Grow-only scratch: returns the buffer, reallocating (contents dropped) when
 // it is smaller than `bytes`.
-void *scratch(Ctx *c, int id, size_t bytes);
+void *grow_scratch(Ctx *c, int id, size_t bytes);
 
 pms_status set_err(Ctx *c, pms_status s, const std::string &msg);
 

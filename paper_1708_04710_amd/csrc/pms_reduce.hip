@@ -42,6 +42,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,6 +102,8 @@ struct Counters {
     int32_t dbg_col;     // a column or row that broke one
     unsigned long long trace[S_NUM];  // folded stripes (trace output)
 };
+
+static_assert(sizeof(Counters) % 8 == 0, "Counters is cleared as 64-bit words");
 
 // debug_invariants: one bit per property checked
 enum DbgBit : int32_t {
@@ -2064,7 +2067,7 @@ __global__ void k_selftest(int32_t *bad)
 }
 
 // ---------------------------------------------------------------- host
-void *scratch(Ctx *c, int id, size_t bytes)
+void *grow_scratch(Ctx *c, int id, size_t bytes)
 {
     Buf &b = c->b[id];
     if (b.bytes >= bytes && b.p) return b.p;
@@ -2127,14 +2130,36 @@ static void set_partitions(Dev &d, unsigned long long used)
 // Arena regrowth: copy the live columns into an arena at least twice as
 // large (and at least min_cap entries), then split the free space into
 // fresh partitions.
-static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, unsigned long long min_cap = 0)
+// Where a reduction's scratch comes from: the context's grow-only buffers
+// (allocated on growth), or one fixed device region carved front to back,
+// with the column arena taking what is left (the allocation-free entry
+// point; then nothing is allocated and the arena cannot grow).
+struct ScratchSource {
+    Ctx *c = nullptr;
+    char *base = nullptr;  // the fixed region, or null for the context's buffers
+    size_t cap = 0, used = 0;
+    void *get(int id, size_t bytes)
+    {
+        if (!base) return grow_scratch(c, id, bytes);
+        const size_t a = (used + 255) & ~(size_t)255;
+        if (a > cap || bytes > cap - a) return nullptr;
+        used = a + bytes;
+        return base + a;
+    }
+};
+
+static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, const ScratchSource &S, unsigned long long min_cap = 0)
 {
+    if (S.base)
+        return set_err(c, PMS_ERR_TOO_LARGE,
+                       "the column arena of the allocation-free region is full (its fill-in outgrew it); "
+                       "use pms_reduce, whose arena grows");
     unsigned long long new_cap = std::max<unsigned long long>(c->arena_cap * 2, min_cap);
     int32_t *na = nullptr;
     PMS_HIP(hipMalloc(&na, new_cap * sizeof(int32_t)));
-    unsigned long long *top = (unsigned long long *)scratch(c, B_TMP1, 64);
+    unsigned long long *top = (unsigned long long *)grow_scratch(c, B_TMP1, 64);
     if (!top) { (void)hipFree(na); return set_err(c, PMS_ERR_OOM, "scratch alloc"); }
-    PMS_HIP(hipMemsetAsync(top, 0, sizeof(unsigned long long), c->stream));
+    PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, 1, kBlock, top, 1, 0ull);
     PMS_LAUNCH(c, K_DEFRAG, 0, k_defrag, grid_for(d.m, kBlock, 65536), kBlock, d, na, top);
     PMS_HIP(hipGetLastError());
     unsigned long long ntop = 0;
@@ -2148,11 +2173,12 @@ static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, unsigned long long min
     set_partitions(d, ntop);
     PMS_LAUNCH(c, K_FILL, 0, k_part_init, 1, kPart, d);
     h->overflow = 0;
-    PMS_HIP(hipMemsetAsync(&d.cnt->overflow, 0, sizeof(int32_t), c->stream));
+    PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, 1, kBlock, &d.cnt->overflow, 1, 0);
     return PMS_OK;
 }
 
-static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options *opt, pms_result *res)
+static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options *opt, pms_result *res,
+                              ScratchSource &S)
 {
     const int64_t m = bnd->m;
     res->n_pairs = res->n_essential = 0;
@@ -2185,63 +2211,79 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     d.col_ptr = bnd->col_ptr;
     d.rows = bnd->rows;
     d.dim = bnd->dim;
-    d.off = (int64_t *)scratch(c, B_OFF, m * 8);
-    d.len = (int32_t *)scratch(c, B_LEN, m * 4);
-    d.low = (int32_t *)scratch(c, B_LOW, m * 4);
-    d.state = (uint8_t *)scratch(c, B_STATE, m);
-    d.beta = (int32_t *)scratch(c, B_BETA, m * 4);
-    d.left = (int32_t *)scratch(c, B_LEFT, m * 4);
-    d.piv = (int32_t *)scratch(c, B_PIV, m * 4);
-    d.T = (unsigned long long *)scratch(c, B_T, m * 8);
-    d.neg = (uint32_t *)scratch(c, B_NEG, nwords * 4);
-    d.coll = (int8_t *)scratch(c, B_COLL, m);
-    d.cnt = (Counters *)scratch(c, B_CNT, sizeof(Counters));
+    d.off = (int64_t *)S.get(B_OFF, m * 8);
+    d.len = (int32_t *)S.get(B_LEN, m * 4);
+    d.low = (int32_t *)S.get(B_LOW, m * 4);
+    d.state = (uint8_t *)S.get(B_STATE, m);
+    d.beta = (int32_t *)S.get(B_BETA, m * 4);
+    d.left = (int32_t *)S.get(B_LEFT, m * 4);
+    d.piv = (int32_t *)S.get(B_PIV, m * 4);
+    d.T = (unsigned long long *)S.get(B_T, m * 8);
+    d.neg = (uint32_t *)S.get(B_NEG, nwords * 4);
+    d.coll = (int8_t *)S.get(B_COLL, m);
+    d.cnt = (Counters *)S.get(B_CNT, sizeof(Counters));
     d.low_star = res->low_star;
-    int32_t *act0 = (int32_t *)scratch(c, B_ACT0, m * 4);
-    int32_t *act1 = (int32_t *)scratch(c, B_ACT1, m * 4);
-    I4 *agg = (I4 *)scratch(c, B_AGG, nblk * sizeof(I4));
-    int32_t *keep = (int32_t *)scratch(c, B_AGG2, (nblk + 1) * 4);
-    int32_t *keep2 = (int32_t *)scratch(c, B_FLAGS, (nblk + 1) * 4);
+    int32_t *act0 = (int32_t *)S.get(B_ACT0, m * 4);
+    int32_t *act1 = (int32_t *)S.get(B_ACT1, m * 4);
+    I4 *agg = (I4 *)S.get(B_AGG, nblk * sizeof(I4));
+    int32_t *keep = (int32_t *)S.get(B_AGG2, (nblk + 1) * 4);
+    int32_t *keep2 = (int32_t *)S.get(B_FLAGS, (nblk + 1) * 4);
     d.cq_slice = (nblk + kPart - 1) / kPart * kBlock;  // a slice takes every kPart-th tile
-    d.cq = (int32_t *)scratch(c, B_TMP0, (size_t)kPart * d.cq_slice * 4);
-    d.cq_n = (int32_t *)scratch(c, B_CQN, (kPart + 2) * 32 * 4);
-    d.wq = (int32_t *)scratch(c, B_WQ, (size_t)m * 4);
-    d.wq2 = (int32_t *)scratch(c, B_WQ2, (size_t)m * 4);
-    d.stats = (unsigned long long *)scratch(c, B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
-    d.part = (unsigned long long *)scratch(c, B_PART, kPart * 16 * 8);
-    d.prec = (PivRec *)scratch(c, B_PREC, (size_t)m * sizeof(PivRec));
+    d.cq = (int32_t *)S.get(B_TMP0, (size_t)kPart * d.cq_slice * 4);
+    d.cq_n = (int32_t *)S.get(B_CQN, (kPart + 2) * 32 * 4);
+    d.wq = (int32_t *)S.get(B_WQ, (size_t)m * 4);
+    d.wq2 = (int32_t *)S.get(B_WQ2, (size_t)m * 4);
+    d.stats = (unsigned long long *)S.get(B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
+    d.part = (unsigned long long *)S.get(B_PART, kPart * 16 * 8);
+    d.prec = (PivRec *)S.get(B_PREC, (size_t)m * sizeof(PivRec));
     if (!d.off || !d.len || !d.low || !d.state || !d.beta || !d.left || !d.piv || !d.T || !d.neg || !d.coll ||
         !d.cnt || !act0 || !act1 || !agg || !keep || !keep2 || !d.cq || !d.cq_n || !d.stats || !d.part || !d.prec || !d.wq ||
         !d.wq2)
-        return set_err(c, PMS_ERR_OOM, "scratch allocation failed");
+        return S.base ? set_err(c, PMS_ERR_TOO_LARGE, "the matrix does not fit the allocation-free region; use pms_reduce")
+                      : set_err(c, PMS_ERR_OOM, "scratch allocation failed");
     if (dbg) {
-        d.dbg_low = (int32_t *)scratch(c, B_DBG_LOW, m * 4);
-        d.dbg_off = (int64_t *)scratch(c, B_DBG_OFF, m * 8);
-        d.dbg_len = (int32_t *)scratch(c, B_DBG_LEN, m * 4);
-        d.dbg_state = (uint8_t *)scratch(c, B_DBG_STATE, m);
-        d.dbg_w = (int32_t *)scratch(c, B_DBG_W, m * 4);
-        d.dbg_erem = (int32_t *)scratch(c, B_DBG_EREM, m * 4);
+        d.dbg_low = (int32_t *)S.get(B_DBG_LOW, m * 4);
+        d.dbg_off = (int64_t *)S.get(B_DBG_OFF, m * 8);
+        d.dbg_len = (int32_t *)S.get(B_DBG_LEN, m * 4);
+        d.dbg_state = (uint8_t *)S.get(B_DBG_STATE, m);
+        d.dbg_w = (int32_t *)S.get(B_DBG_W, m * 4);
+        d.dbg_erem = (int32_t *)S.get(B_DBG_EREM, m * 4);
         if (!d.dbg_low || !d.dbg_off || !d.dbg_len || !d.dbg_state || !d.dbg_w || !d.dbg_erem)
-            return set_err(c, PMS_ERR_OOM, "debug scratch allocation failed");
+            return set_err(c, S.base ? PMS_ERR_TOO_LARGE : PMS_ERR_OOM, "debug scratch allocation failed");
     }
 
-    // arena: sized for the first rounds' fill-in, grown on demand
-    unsigned long long want = (unsigned long long)(4 * nnz) + (1ull << 22);
-    if (opt->arena_entries > 0) want = (unsigned long long)opt->arena_entries;
-    if (c->arena_cap < want || (opt->arena_entries > 0 && c->arena_cap != want)) {
-        if (c->arena) PMS_HIP(hipFree(c->arena));
-        c->arena = nullptr;
-        c->arena_cap = 0;
-        PMS_HIP(hipMalloc(&c->arena, want * sizeof(int32_t)));
-        c->arena_cap = want;
+    // arena: sized for the first rounds' fill-in, grown on demand; in a
+    // fixed region, everything the other buffers left
+    if (S.base) {
+        const size_t a = (S.used + 255) & ~(size_t)255;
+        const unsigned long long avail = a < S.cap ? (S.cap - a) / sizeof(int32_t) : 0;
+        const unsigned long long need = (unsigned long long)(4 * nnz) + (1ull << 20);
+        if (avail < need)
+            return set_err(c, PMS_ERR_TOO_LARGE,
+                           "the matrix does not fit the allocation-free region (its per-column state and an "
+                           "arena of 4 nnz + 2^20 entries); use pms_reduce");
+        d.arena = (int32_t *)(S.base + a);
+        d.arena_cap = avail;
+        S.used = S.cap;
+    } else {
+        unsigned long long want = (unsigned long long)(4 * nnz) + (1ull << 22);
+        if (opt->arena_entries > 0) want = (unsigned long long)opt->arena_entries;
+        if (c->arena_cap < want || (opt->arena_entries > 0 && c->arena_cap != want)) {
+            if (c->arena) PMS_HIP(hipFree(c->arena));
+            c->arena = nullptr;
+            c->arena_cap = 0;
+            PMS_HIP(hipMalloc(&c->arena, want * sizeof(int32_t)));
+            c->arena_cap = want;
+        }
+        d.arena = c->arena;
+        d.arena_cap = c->arena_cap;
     }
-    d.arena = c->arena;
-    d.arena_cap = c->arena_cap;
     set_partitions(d, 0);
 
     hipStream_t st = c->stream;
     const unsigned gm = grid_for(m, kBlock, 65536);
-    PMS_HIP(hipMemsetAsync(d.cnt, 0, sizeof(Counters), st));
+    PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, 1, kBlock, (unsigned long long *)d.cnt,
+               (int64_t)(sizeof(Counters) / 8), 0ull);
     PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, grid_for(S_NUM * kStripe * 16), kBlock, d.stats,
                (int64_t)S_NUM * kStripe * 16, 0ull);
     PMS_LAUNCH(c, K_FILL, 0, k_part_init, 1, kPart, d);
@@ -2381,7 +2423,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         c->diag.push_back(e);
     };
     if (diag) {
-        d.ess = (uint32_t *)scratch(c, B_ESS, (size_t)nwords * 4);
+        d.ess = (uint32_t *)S.get(B_ESS, (size_t)nwords * 4);
         if (!d.ess) return set_err(c, PMS_ERR_OOM, "diagnostics scratch");
         PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_diag_init, grid_for(nwords, kBlock, 65536), kBlock, d.ess, m, nwords);
         pms_status sd = launch_diag();
@@ -2479,8 +2521,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             if (e != hipSuccess) return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
             round = h->round;
             if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
-            if (h->overflow || grow_early(h->n_cur)) {  // the arena moves: grow it (on the caller's stream) and capture again
-                pms_status s = grow_arena(c, d, h, h->overflow ? 0 : want_cap);
+            if (h->overflow || (!S.base && grow_early(h->n_cur))) {  // the arena moves: grow it (on the caller's stream) and capture again
+                pms_status s = grow_arena(c, d, h, S, h->overflow ? 0 : want_cap);
                 if (s != PMS_OK) return s;
                 free_prev = d.arena_cap - d.part_base;
                 PMS_HIP(hipEventRecord(c->graph_ev, st));
@@ -2557,8 +2599,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             const pms_status sdb = dbg_check("in round", (int32_t)round);
             if (sdb != PMS_OK) return sdb;
         }
-        if (h->overflow || grow_early(h->n_next)) {
-            pms_status s = grow_arena(c, d, h, h->overflow ? 0 : want_cap);
+        if (h->overflow || (!S.base && grow_early(h->n_next))) {
+            pms_status s = grow_arena(c, d, h, S, h->overflow ? 0 : want_cap);
             if (s != PMS_OK) return s;
             free_prev = d.arena_cap - d.part_base;
         }
@@ -2610,6 +2652,17 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
 // ==================================================================== ABI
 struct pms_ctx : pms::Ctx {};
+
+// The device region of the allocation-free entry point (pms_reduce_noalloc):
+// PMS_NOALLOC_BYTES bytes on every device the library runs on, held until the
+// process ends.  In host code this name is a host-side stand-in, not a device
+// address: the device address of each device's copy comes from
+// hipGetSymbolAddress (in pms_create, with that device current) and is kept
+// in noalloc_ptr[device]; only that pointer is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[PMS_NOALLOC_BYTES];
+constexpr int kNoAllocDevices = 64;
+static void *noalloc_ptr[kNoAllocDevices];
+static std::mutex noalloc_mu;
 
 namespace pms {
 
@@ -2691,6 +2744,19 @@ pms_status pms_create(pms_ctx **ctx, int device, void *stream)
         delete c;
         return PMS_ERR_OOM;
     }
+    // once per device: the device address of its copy of the allocation-free region
+    if (device < kNoAllocDevices) {
+        std::lock_guard<std::mutex> lk(noalloc_mu);
+        if (!noalloc_ptr[device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                (void)hipHostFree(c->host_pinned);
+                delete c;
+                return PMS_ERR_HIP;
+            }
+            noalloc_ptr[device] = p;
+        }
+    }
     *ctx = c;
     return PMS_OK;
 }
@@ -2761,7 +2827,7 @@ static pms_status debug_selftest(pms::Ctx *c)
         h0.dbg_erem[j] = 0x7FFFFFFF;
     }
     h0.neg[0] = 0;
-    Host *dv = (Host *)scratch(c, B_TMP0, sizeof(Host) + sizeof(Counters) + 256);
+    Host *dv = (Host *)grow_scratch(c, B_TMP0, sizeof(Host) + sizeof(Counters) + 256);
     if (!dv) return set_err(c, PMS_ERR_OOM, "scratch");
     Counters *cnt = (Counters *)((char *)dv + ((sizeof(Host) + 255) / 256) * 256);
     Dev d{};
@@ -2831,7 +2897,7 @@ pms_status pms_selftest(pms_ctx *c)
     if (!c) return PMS_ERR_INVALID_ARG;
     c->err.clear();
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
-    int32_t *bad = (int32_t *)pms::scratch(c, pms::B_TMP1, 64);
+    int32_t *bad = (int32_t *)pms::grow_scratch(c, pms::B_TMP1, 64);
     if (!bad) return pms::set_err(c, PMS_ERR_OOM, "scratch");
     PMS_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
     pms::k_selftest<<<4, 256, 0, c->stream>>>(bad);
@@ -2885,10 +2951,38 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
         o.debug_invariants > 1 || o.reserved != 0)
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
-    pms_status s = pms::reduce_impl(c, bnd, &o, res);
+    pms::ScratchSource S;
+    S.c = c;
+    pms_status s = pms::reduce_impl(c, bnd, &o, res, S);
     if (s != PMS_OK && s != PMS_ERR_CAPACITY && s != PMS_ERR_NOT_CONVERGED) {
         res->n_pairs = res->n_essential = 0;
     }
+    return s;
+}
+
+pms_status pms_reduce_noalloc(pms_ctx *c, const pms_boundary *bnd, const pms_options *opt, pms_result *res)
+{
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!bnd || !res) return pms::set_err(c, PMS_ERR_INVALID_ARG, "null boundary or result");
+    if (bnd->m < 0 || bnd->m >= 0x7FFFFFFF) return pms::set_err(c, PMS_ERR_INVALID_ARG, "m out of range");
+    if (bnd->m > 0 && (!bnd->col_ptr || !bnd->rows || !res->low_star))
+        return pms::set_err(c, PMS_ERR_INVALID_ARG, "null col_ptr / rows / low_star");
+    const pms_options o = opt ? *opt : pms_default_options();
+    if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries != 0 || o.graph_rounds != 0 ||
+        o.diagnostics != 0 || o.debug_invariants < 0 || o.debug_invariants > 1 || o.reserved != 0)
+        return pms::set_err(c, PMS_ERR_INVALID_ARG,
+                            "bad options (without allocation: no graph rounds, no diagnostics, arena_entries 0)");
+    if (c->prof_on) return pms::set_err(c, PMS_ERR_INVALID_ARG, "the profiler is on (it creates events)");
+    void *base = c->device < kNoAllocDevices ? noalloc_ptr[c->device] : nullptr;
+    if (!base) return pms::set_err(c, PMS_ERR_INVALID_ARG, "no allocation-free region on this device");
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    pms::ScratchSource S;
+    S.c = c;
+    S.base = (char *)base;
+    S.cap = PMS_NOALLOC_BYTES;
+    pms_status s = pms::reduce_impl(c, bnd, &o, res, S);
+    if (s != PMS_OK && s != PMS_ERR_CAPACITY && s != PMS_ERR_NOT_CONVERGED) res->n_pairs = res->n_essential = 0;
     return s;
 }
 
