@@ -100,6 +100,7 @@ struct Counters {
     uint32_t round;      // rounds that did work so far
     int32_t dbg_flags;   // debug_invariants: the invariants found broken (DbgBit)
     int32_t dbg_col;     // a column or row that broke one
+    int32_t bad_info[4]; // where k_chain set bad_source: column, low, previous low, step
     unsigned long long trace[S_NUM];  // folded stripes (trace output)
 };
 
@@ -1143,7 +1144,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                     // the stored column) into B, from the top down
                     wantl = false;
                     if (LB <= 0 || LW(LB - 1) != i) {
-                        atomicExch(&d.cnt->bad_source, 2);
+                        atomicExch(&d.cnt->bad_source, 3);
                         dirty = false;
                         fin = true;
                     } else {
@@ -1192,7 +1193,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                         dirty = true;
                         const int32_t ni = top();
                         if (ni >= i) {  // the low must drop; stop rather than spin
-                            atomicExch(&d.cnt->bad_source, 2);
+                            atomicExch(&d.cnt->bad_source, 3);
                             dirty = false;
                             fin = true;
                         } else {
@@ -1267,7 +1268,7 @@ __device__ __forceinline__ void lane_chain(const Dev &d, int compression, const 
                 dirty = true;
                 const int32_t ni = top();
                 if (ni >= i) {  // the low must drop; stop rather than spin
-                    atomicExch(&d.cnt->bad_source, 2);
+                    atomicExch(&d.cnt->bad_source, 3);
                     dirty = false;
                     fin = true;
                 } else {
@@ -1680,7 +1681,13 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             }
             next();
             if (i >= pi) {  // the low must drop; stop rather than spin
-                if (lane == 0) atomicExch(&d.cnt->bad_source, 2);  // never expected
+                if (lane == 0) {  // never expected
+                    d.cnt->bad_info[0] = j;
+                    d.cnt->bad_info[1] = i;
+                    d.cnt->bad_info[2] = pi;
+                    d.cnt->bad_info[3] = cadds;
+                    atomicExch(&d.cnt->bad_source, 2);
+                }
                 failed = true;
                 break;
             }
@@ -2091,6 +2098,19 @@ pms_status set_err(Ctx *c, pms_status s, const std::string &msg)
 {
     if (c) c->err = msg;
     return s;
+}
+
+// the message for a broken internal invariant reported by a kernel
+static std::string bad_source_text(const Counters &h)
+{
+    if (h.bad_source == 1) return "internal: a column was added a column to its right";
+    std::string m = "internal: a chained addition did not lower the low (";
+    if (h.bad_source == 2)
+        m += "k_chain: column " + std::to_string(h.bad_info[0]) + ", low " + std::to_string(h.bad_info[1]) +
+             " after " + std::to_string(h.bad_info[2]) + ", step " + std::to_string(h.bad_info[3]);
+    else
+        m += "k_chain_lane or k_chain_wide";
+    return m + ")";
 }
 
 hipEvent_t prof_event(Ctx *c)
@@ -2520,7 +2540,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             if (e == hipSuccess) e = hipStreamSynchronize(gs);
             if (e != hipSuccess) return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
             round = h->round;
-            if (h->bad_source) return set_err(c, PMS_ERR_HIP, "internal: a chained addition did not lower the low");
+            if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
             if (h->overflow || (!S.base && grow_early(h->n_cur))) {  // the arena moves: grow it (on the caller's stream) and capture again
                 pms_status s = grow_arena(c, d, h, S, h->overflow ? 0 : want_cap);
                 if (s != PMS_OK) return s;
@@ -2592,9 +2612,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
                     (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1));
         }
-        if (h->bad_source)
-            return set_err(c, PMS_ERR_HIP, h->bad_source == 1 ? "internal: a column was added a column to its right"
-                                                                : "internal: a chained addition did not lower the low");
+        if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
         {
             const pms_status sdb = dbg_check("in round", (int32_t)round);
             if (sdb != PMS_OK) return sdb;
