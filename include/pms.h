@@ -138,6 +138,35 @@ typedef struct {
      * Runs one round at a time (no graph) with several extra passes over the
      * columns per round; for testing, not production.  0 = off. */
     int32_t debug_invariants;
+    /* 1 = clearing by local compression (Sec. 3.2, Lemma "Clearing by local
+     * compression" and its Corollary, the case L_j = {0}) every round, after
+     * Phase I: a column j of dimension d >= 1 not known negative (no beta_j)
+     * whose low lies below every (d-1)-simplex of its complex that is not
+     * yet paired (not known negative and not the low* of a found pivot) is
+     * positive, and is cleared without further additions.  With
+     * pms_reduce_batched the complex is the instance that holds column j
+     * (the matrix is block diagonal, so low*(j) is a row of that block).
+     * Needs dim.  0 = off. */
+    int32_t c8;
+    /* 0 = every dimension reduced at once (the default);
+     * 1 = twist order (Alg. "Standard reduction with a twist"): the rounds
+     *     run on the columns of the top dimension until they are reduced,
+     *     then on the next dimension down, and so on; the pivots found in
+     *     dimension d clear (zero) the columns of dimension d-1 that are
+     *     their lows before those columns are reduced.  Needs dim. */
+    int32_t sweep;
+    /* Which colliding columns add in a round when round_budget limits them
+     * (Sec. 3.4, fewer processors than colliding columns):
+     *   0 = in column order;
+     *   1 = the columns of the largest sets N(i) first (the columns whose
+     *       low is i: one known pivot serves them all), then column order;
+     *   2 = the columns known negative (beta_j defined) first, then column
+     *       order (their reduction clears the columns of their low*). */
+    int32_t priority;
+    /* > 0: at most this many columns make the round's first addition (and
+     * chain on, when chaining); the others wait for a later round.
+     * 0 = every colliding column adds (no limit). */
+    int32_t round_budget;
     int32_t reserved; /* 0 */
 } pms_options;
 
@@ -248,6 +277,7 @@ typedef struct {
     int64_t xor_entries;    /* entries those additions read */
     int64_t low_l1;         /* sum_j (low^l(j) + 1) */
     int64_t ess_estimate;   /* |E^l| */
+    int64_t c8_cleared;     /* columns cleared by pms_options.c8 in the round */
 } pms_round_stats;
 
 /* The entries recorded by the context's last reduction with diagnostics

@@ -52,13 +52,14 @@ class PmsOptions(ctypes.Structure):
                 ("tail_active", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph_rounds", ctypes.c_int32), ("diagnostics", ctypes.c_int32),
                 ("arena_entries", ctypes.c_int64), ("debug_invariants", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("c8", ctypes.c_int32), ("sweep", ctypes.c_int32), ("priority", ctypes.c_int32),
+                ("round_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PmsRoundStats(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("active", ctypes.c_int32), ("new_pivots", ctypes.c_int64),
                 ("additions", ctypes.c_int64), ("xor_entries", ctypes.c_int64), ("low_l1", ctypes.c_int64),
-                ("ess_estimate", ctypes.c_int64)]
+                ("ess_estimate", ctypes.c_int64), ("c8_cleared", ctypes.c_int64)]
 
 
 class PmsTuning(ctypes.Structure):

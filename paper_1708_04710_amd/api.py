@@ -227,10 +227,11 @@ def _dptr(t):
 
 
 def _options(variant=0, compression=True, max_rounds=0, chain=True, tail_active=1024, validate=True,
-             arena_entries=0, graph_rounds=0, diagnostics=False, debug_invariants=False):
+             arena_entries=0, graph_rounds=0, diagnostics=False, debug_invariants=False, c8=False, sweep=0,
+             priority=0, round_budget=0):
     return B.PmsOptions(variant, int(bool(compression)), max_rounds, int(bool(chain)), tail_active,
                         int(bool(validate)), graph_rounds, int(bool(diagnostics)), arena_entries,
-                        int(bool(debug_invariants)), 0)
+                        int(bool(debug_invariants)), int(bool(c8)), int(sweep), int(priority), int(round_budget), 0)
 
 
 def _outputs(dev, m, outputs):
@@ -293,7 +294,8 @@ def round_stats(device=None) -> list:
     """The per-round records of the last reduction with ``diagnostics=True``
     on the context of ``device`` (``pms_round_stats_read``), also after one
     stopped by ``max_rounds``: dicts with round, active, new_pivots,
-    additions, xor_entries, low_l1 (sum of low + 1) and ess_estimate (|E|)."""
+    additions, xor_entries, low_l1 (sum of low + 1), ess_estimate (|E|) and
+    c8_cleared (columns cleared by Lemma "Clearing by local compression")."""
     dev = _dev(device)
     ctx = _ctx(dev)
     lib = B.load()
@@ -330,7 +332,7 @@ def multiscale(stats: list, m: int, n_essential: int | None = None) -> list:
                     "rel_error": (s["low_l1"] - final) / final if final else 0.0,
                     "unreduced": s["active"] / m if m else 0.0,
                     "ess_precision": ess / s["ess_estimate"] if s["ess_estimate"] else 1.0,
-                    "additions": s["additions"]})
+                    "additions": s["additions"], "c8_cleared": s["c8_cleared"]})
     return out
 
 
@@ -417,7 +419,8 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
     col_ptr: int64 [m+1]; rows: int32 [nnz] ascending per column; dim: int8 [m]
     or None.  All on the same device.  Keyword options as in ``pms_options``:
     variant, compression, max_rounds, chain, tail_active, validate,
-    graph_rounds, arena_entries, diagnostics, debug_invariants; ``outputs=False``
+    graph_rounds, arena_entries, diagnostics, debug_invariants, c8, sweep,
+    priority, round_budget; ``outputs=False``
     skips the pair / essential lists; ``noalloc=True`` calls the
     allocation-free entry point (``pms_reduce_noalloc``; the output tensors
     are still allocated here, by the caller of the library)."""

@@ -27,7 +27,7 @@ struct Buf {
 enum KernelId {
     K_INIT = 0, K_BETA, K_LOW, K_COLLIDE, K_SCAN, K_PIVOTS, K_XOR, K_COMPACT, K_FINAL, K_FILL, K_DEFRAG,
     K_LS_KEYS, K_SORT, K_LS_INDEX, K_BUILD_SCAN, K_LS_ROWS, K_VR_EDGES, K_VR_TRI, K_VR_INDEX, K_VR_ROWS,
-    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE,
+    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE, K_C8, K_BUDGET,
     K_NUM
 };
 
@@ -74,6 +74,10 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // the batch instances of the reduction in progress (device column
+    // offsets, n_inst + 1 entries; null: one complex)
+    const int64_t *inst_off = nullptr;
+    int32_t n_inst = 1;
     // profiler
     bool prof_on = false;
     std::vector<PendingEv> pend;
@@ -83,7 +87,7 @@ struct Ctx {
     double prof_abytes[K_NUM] = {};
     int64_t prof_launches[K_NUM] = {};
     // named scratch buffers, grown on demand
-    Buf b[48];
+    Buf b[56];
     int32_t *arena = nullptr;
     uint64_t arena_cap = 0;  // entries
     void *host_pinned = nullptr;
@@ -108,10 +112,10 @@ enum BufId {
     B_COLL, B_AGG, B_AGG2, B_CNT, B_FLAGS, B_TMP0, B_TMP1,
     B_BUILD0, B_BUILD1, B_BUILD2, B_BUILD3, B_BUILD4, B_BUILD5, B_BUILD6, B_BUILD7,
     B_BUILD8, B_BUILD9, B_BUILD10, B_BUILD11, B_BUILD12, B_BUILD13, B_BUILD14, B_STATS, B_PART, B_CQN, B_PREC, B_WQ, B_WQ2, B_ESS,
-    B_DBG_LOW, B_DBG_OFF, B_DBG_LEN, B_DBG_STATE, B_DBG_W, B_DBG_EREM,
+    B_DBG_LOW, B_DBG_OFF, B_DBG_LEN, B_DBG_STATE, B_DBG_W, B_DBG_EREM, B_C8, B_INST, B_BUDH, B_BUDN,
     B_NUM
 };
-static_assert(B_NUM <= 48, "Ctx::b holds 48 buffers");
+static_assert(B_NUM <= 56, "Ctx::b holds 56 buffers");
 
 // Grow-only scratch: returns the buffer, reallocating (contents dropped) when
 // it is smaller than `bytes`.

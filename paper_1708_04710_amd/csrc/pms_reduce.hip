@@ -53,6 +53,7 @@ namespace pms {
 
 enum : uint8_t { ST_ACTIVE = 0, ST_PIVOT = 1, ST_ZERO = 2, ST_CLEARED = 3 };
 constexpr int8_t kNotLive = 2;  // coll[q]: column act[q] was not active when the round's collisions were taken
+constexpr int8_t kWaits = 3;    // coll[q]: column act[q] collides but waits for a later round (round_budget)
 
 constexpr uint64_t kArenaBit = 1ull << 62;
 constexpr int kScanThreads = 1024;
@@ -86,6 +87,7 @@ struct Counters {
     unsigned long long diag_ess;     // diagnostics: |E|
     unsigned long long diag_active;  // diagnostics: columns neither pivot nor zero
     unsigned long long arena_free;   // arena entries still free at the end of the round
+    unsigned long long c8_cleared;   // columns cleared by Lemma "Clearing by local compression"
     int32_t error;       // 1 = not compatible
     int32_t overflow;    // an arena partition ran out during this round
     int32_t n_next;      // active columns after compaction
@@ -163,6 +165,13 @@ struct Dev {
     int32_t *wq;       // columns handed from the lane chain passes to the wavefront kernel
     int32_t *wq2;      // columns the first lane pass hands to the wide one (too long for its buffer)
     uint32_t *ess;     // diagnostics: the essential estimate E as a bitmask (null when off)
+    // Lemma "Clearing by local compression" (null when off): the complexes
+    // (batch instances, column / row ranges inst_off[k] .. inst_off[k+1]) and,
+    // per instance and dimension e < kC8Dims, the first row of dimension e
+    // not yet paired
+    const int64_t *inst_off;
+    int32_t n_inst;
+    int32_t *c8_first;
     // debug_invariants (null when off): the last round's low, header and
     // state of every column, writes per column in the current kernel, and
     // the round at which each index left the essential estimate
@@ -660,6 +669,131 @@ __device__ inline int32_t merge_add_stream(const int32_t *__restrict__ x, int32_
     return k;
 }
 
+// The column a colliding active column j adds this round (-1: none): the
+// known pivot of its low, else (variant 0) the leftmost column with that low
+// unless it was cleared.
+__device__ inline int32_t xor_source(const Dev &d, int32_t j, int variant, uint32_t round)
+{
+    const int32_t i = d.low[j];
+    int32_t s = d.piv[i];
+    if (s < 0 && variant == 0) {
+        s = t_decode(d.T[i], round);
+        if (s == j || (s >= 0 && d.state[s] == ST_CLEARED)) s = -1;
+    }
+    return s;
+}
+
+// ------------------------------------------------ priority with a budget
+// Sec. 3.4: with fewer processors than colliding columns only some of them
+// add in a round, chosen by a priority.  Each colliding column with a source
+// gets a key h in [0, 255] (larger first): 0 for all (column order), 1 for
+// the columns known negative (Sec. 3.4 "N(j) and Neg"), or the size of its
+// set N -- the colliding columns with its low, served by one pivot --
+// capped at 255 (Sec. 3.4 "sets N(j) with large cardinality").  With t the
+// largest key at which the columns of key >= t reach the budget, the columns
+// of key > t add, those of key t add in column order up to what is left, and
+// the rest wait (their collision flag is cleared for this round).
+constexpr int kBudKeys = 256;
+
+__device__ inline bool bud_target(const Dev &d, const int32_t *act, int64_t q, int variant, uint32_t round,
+                                  bool waiting = false)
+{
+    const int32_t j = act[q];
+    const int8_t c = d.coll[q];
+    return d.state[j] == ST_ACTIVE && (c == 1 || (waiting && c == kWaits)) && xor_source(d, j, variant, round) >= 0;
+}
+
+__device__ inline int bud_key(const Dev &d, int32_t j, int prio, const int32_t *ncount)
+{
+    if (prio == 2) return d.beta[j] >= 0 ? 1 : 0;
+    if (prio == 1) return min(ncount[d.low[j]], kBudKeys - 1);
+    return 0;
+}
+
+// |N| per low (priority 1): one count per colliding column with a source;
+// sign = -1 takes them back out after the round's choice (the waiting
+// columns included)
+__global__ void __launch_bounds__(kBlock) k_bud_ncount(Dev d, const int32_t *act, int variant, int32_t *ncount,
+                                                       int sign)
+{
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < nA; q += (int64_t)gridDim.x * kBlock)
+        if (bud_target(d, act, q, variant, round, sign < 0)) atomicAdd(&ncount[d.low[act[q]]], sign);
+}
+
+// key histogram (hist[kBudKeys + 2] is zeroed by the previous round's choice)
+__global__ void __launch_bounds__(kBlock) k_bud_hist(Dev d, const int32_t *act, int variant, int prio,
+                                                     const int32_t *ncount, int32_t *hist)
+{
+    __shared__ int32_t s_h[kBudKeys];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < nA; q += (int64_t)gridDim.x * kBlock)
+        if (bud_target(d, act, q, variant, round)) atomicAdd(&s_h[bud_key(d, act[q], prio, ncount)], 1);
+    __syncthreads();
+    if (s_h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_h[threadIdx.x]);
+}
+
+// the threshold key t (hist[kBudKeys]) and the budget left for key t
+// (hist[kBudKeys + 1]); the histogram is cleared for the next round
+__global__ void k_bud_thresh(int32_t *hist, int32_t budget)
+{
+    if (threadIdx.x != 0) return;
+    int32_t above = 0, t = -1;  // t = -1: every column fits the budget
+    for (int h = kBudKeys - 1; h >= 0; h--) {
+        if (above + hist[h] >= budget) {
+            t = h;
+            break;
+        }
+        above += hist[h];
+    }
+    for (int h = 0; h < kBudKeys; h++) hist[h] = 0;
+    hist[kBudKeys] = t;
+    hist[kBudKeys + 1] = budget - above;  // ranks of key t below this add (all of them when the total fits)
+}
+
+// per tile: colliding columns of key t
+__global__ void __launch_bounds__(kBlock) k_bud_count(Dev d, const int32_t *act, int variant, int prio,
+                                                      const int32_t *ncount, const int32_t *hist, int32_t *tcnt)
+{
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    const int32_t t = hist[kBudKeys];
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t q = tile * kBlock + threadIdx.x;
+        const int tie = (q < nA && bud_target(d, act, q, variant, round) && bud_key(d, act[q], prio, ncount) == t);
+        int32_t tot;
+        block_excl_sum32(tie, &tot);
+        if (threadIdx.x == 0) tcnt[tile] = tot;
+        __syncthreads();
+    }
+}
+
+// the choice: colliding columns past the budget wait
+__global__ void __launch_bounds__(kBlock) k_bud_apply(Dev d, const int32_t *act, int variant, int prio,
+                                                      const int32_t *ncount, const int32_t *hist,
+                                                      const int32_t *toff)
+{
+    const int32_t nA = d.cnt->n_cur;
+    const uint32_t round = d.cnt->round;
+    const int32_t t = hist[kBudKeys], left = hist[kBudKeys + 1];
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t q = tile * kBlock + threadIdx.x;
+        const bool tg = q < nA && bud_target(d, act, q, variant, round);
+        const int key = tg ? bud_key(d, act[q], prio, ncount) : -1;
+        const int tie = key == t;
+        int32_t tot;
+        const int32_t r = toff[tile] + block_excl_sum32(tie, &tot);
+        if (tg && (key < t || (tie && r >= left))) d.coll[q] = kWaits;
+        __syncthreads();
+    }
+}
+
 // Phase II, first addition of every colliding column (one lane per
 // column: most columns are a few entries long).  A column that may keep
 // adding known pivots (chaining) and whose new low has one is queued for
@@ -679,12 +813,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     if (q < nA) {
         j = act[q];
         if (d.state[j] == ST_ACTIVE && d.coll[q] == 1) {
-            const int32_t i = d.low[j];
-            s = d.piv[i];
-            if (s < 0 && variant == 0) {
-                s = t_decode(d.T[i], round);
-                if (s == j || (s >= 0 && d.state[s] == ST_CLEARED)) s = -1;
-            }
+            s = xor_source(d, j, variant, round);
             if (s >= 0) {
                 target = true;
                 toff = d.off[j];
@@ -1756,15 +1885,142 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     }
 }
 
-// Per-tile count of the positions that stay active.
-__global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act, int32_t *keep_cnt)
+// ------------------------------------------------- clearing by compression
+// Lemma "Clearing by local compression" (Sec. 3.2) with its Corollary, the
+// case L_j = {0}: low*(j) lies in {0} and the (d-1)-simplices of
+// [beta_j, low(j)] that are not paired yet (d = dim(j)).  For a column with
+// no beta_j the range is [first row of its complex, low(j)], so when every
+// (d-1)-simplex of the complex up to low(j) is paired, low*(j) = 0: column j
+// is positive, and is cleared like a column cleared by a pivot.  A row i is
+// paired once it is known negative (beta_i defined, or a found pivot) or is
+// the low* of a found pivot (piv[i]).
+constexpr int kC8Dims = 8;
+
+__device__ inline bool c8_paired(const Dev &d, int64_t i)
+{
+    return d.beta[i] >= 0 || d.state[i] == ST_PIVOT || d.piv[i] >= 0;
+}
+
+// The first unpaired row of each dimension below the top one, per instance,
+// in three steps.  Rows only ever become paired and lows only decrease, so
+// each round scans [start, end] of an instance: start = the smallest first
+// unpaired row of the last round, end = the largest low among the columns
+// the last clearing pass looked at (a row above every low decides no
+// column; a twist-order stage starts over from the instance's end).  The
+// range is split over many blocks.  Per instance, c8_first holds the
+// kC8Dims first rows, then start, this round's end and the next round's end.
+constexpr int kC8Stride = kC8Dims + 3;
+constexpr int kC8Start = kC8Dims, kC8End = kC8Dims + 1, kC8Next = kC8Dims + 2;
+
+__global__ void k_c8_range(Dev d)
+{
+    const int32_t nd = min(d.cnt->topdim, kC8Dims);  // row dimensions 0 .. topdim-1 are needed
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_inst; k += gridDim.x * blockDim.x) {
+        int32_t *f = d.c8_first + (int64_t)k * kC8Stride;
+        const int64_t lo = d.inst_off[k], hi = d.inst_off[k + 1];
+        int64_t start = hi;
+        for (int e = 0; e < nd; e++) start = min(start, (int64_t)f[e]);
+        f[kC8Start] = (int32_t)max(start, lo);
+        f[kC8End] = (int32_t)min((int64_t)f[kC8Next], hi - 1);
+        f[kC8Next] = -1;  // the clearing pass raises it to the largest low it keeps
+        for (int e = 0; e < kC8Dims; e++) f[e] = 0x7FFFFFFF;
+    }
+}
+
+template <int kChunks>
+__global__ void __launch_bounds__(kBlock) k_c8_scan(Dev d)
+{
+    __shared__ int32_t s_first[kC8Dims];
+    const int32_t nd = min(d.cnt->topdim, kC8Dims);
+    for (int64_t bk = blockIdx.x; bk < (int64_t)d.n_inst * kChunks; bk += gridDim.x) {
+        const int32_t k = (int32_t)(bk / kChunks), ch = (int32_t)(bk % kChunks);
+        int32_t *f = d.c8_first + (int64_t)k * kC8Stride;
+        const int64_t start = f[kC8Start], end = f[kC8End];
+        if (threadIdx.x < kC8Dims) s_first[threadIdx.x] = 0x7FFFFFFF;
+        __syncthreads();
+        if (end >= start) {
+            const int64_t per = (end - start + kChunks) / kChunks;
+            const int64_t a = start + ch * per, b = min(a + per, end + 1);
+            for (int64_t i = a + threadIdx.x; i < b; i += kBlock) {
+                const int e = d.dim[i];
+                if (e < nd && !c8_paired(d, i)) atomicMin(&s_first[e], (int32_t)i);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < nd && s_first[threadIdx.x] != 0x7FFFFFFF) atomicMin(&f[threadIdx.x], s_first[threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+// a dimension with no unpaired row in [start, end]: its first one lies past
+// end (past start, nothing known, when the range is empty)
+__global__ void k_c8_fold(Dev d)
+{
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_inst; k += gridDim.x * blockDim.x) {
+        int32_t *f = d.c8_first + (int64_t)k * kC8Stride;
+        const int32_t past = f[kC8End] >= f[kC8Start] ? f[kC8End] + 1 : f[kC8Start];
+        for (int e = 0; e < kC8Dims; e++)
+            if (f[e] == 0x7FFFFFFF) f[e] = past;
+    }
+}
+
+// the next round scans up to each instance's end (start of a reduction or
+// of a twist-order stage: the columns are new to the clearing pass)
+__global__ void k_c8_reset_end(Dev d)
+{
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_inst; k += gridDim.x * blockDim.x)
+        d.c8_first[(int64_t)k * kC8Stride + kC8Next] = 0x7FFFFFFE;
+}
+
+// The active columns with L_j = {0}: cleared (positive); the others raise
+// the next round's scan end to their low.
+__global__ void __launch_bounds__(kBlock) k_c8_clear(Dev d, const int32_t *act)
 {
     const int32_t nA = d.cnt->n_cur;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
     const XcdSplit xs = xcd_split(tiles);
     for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
         const int64_t q = tile * kBlock + threadIdx.x;
-        const int keep = (q < nA && d.state[act[q]] == ST_ACTIVE) ? 1 : 0;
+        int cleared = 0;
+        if (q < nA) {
+            const int32_t j = act[q];
+            const int e = d.dim[j] - 1;
+            if (e >= 0 && e < kC8Dims && d.state[j] == ST_ACTIVE && d.beta[j] < 0) {
+                int32_t a = 0, b = d.n_inst - 1;  // the instance: inst_off[a] <= j < inst_off[a + 1]
+                while (a < b) {
+                    const int32_t mid = (a + b + 1) >> 1;
+                    if (d.inst_off[mid] <= j) a = mid;
+                    else b = mid - 1;
+                }
+                int32_t *f = d.c8_first + (int64_t)a * kC8Stride;
+                const int32_t lo = d.low[j];
+                if (lo <= f[kC8End] && lo < f[e]) {
+                    dbg_write(d, j);
+                    d.state[j] = ST_CLEARED;
+                    cleared = 1;
+                } else if (lo > f[kC8Next]) {
+                    atomicMax(&f[kC8Next], lo);  // the next round's scan end
+                }
+            }
+        }
+        int32_t tot;
+        block_excl_sum32(cleared, &tot);
+        if (threadIdx.x == 0 && tot) atomicAdd(&d.cnt->c8_cleared, (unsigned long long)tot);
+    }
+}
+
+// Per-tile count of the positions that stay active.
+// (dimsel >= 0: only the active columns of that dimension stay, for the
+// first list of a twist-order stage)
+__global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act, int32_t *keep_cnt, int dimsel)
+{
+    const int32_t nA = d.cnt->n_cur;
+    const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
+    const XcdSplit xs = xcd_split(tiles);
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
+        const int64_t q = tile * kBlock + threadIdx.x;
+        const int keep =
+            (q < nA && d.state[act[q]] == ST_ACTIVE && (dimsel < 0 || d.dim[act[q]] == dimsel)) ? 1 : 0;
         int32_t tk;
         block_excl_sum32(keep, &tk);
         if (threadIdx.x == 0) keep_cnt[tile] = tk;
@@ -1774,7 +2030,7 @@ __global__ void __launch_bounds__(kBlock) k_keep_count(Dev d, const int32_t *act
 
 // Stable compaction of the active list; finalises cleared columns.
 __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, const int32_t *keep_off,
-                                                    int32_t *act_next)
+                                                    int32_t *act_next, int dimsel)
 {
     const int32_t nA = d.cnt->n_cur;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
@@ -1792,7 +2048,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(Dev d, const int32_t *act, c
             d.len[j] = 0;
             d.low[j] = -1;
         }
-        keep = st == ST_ACTIVE;
+        keep = st == ST_ACTIVE && (dimsel < 0 || d.dim[j] == dimsel);
     }
     int32_t tot;
     const int32_t pos = block_excl_sum32(keep, &tot);
@@ -1929,6 +2185,24 @@ __global__ void k_round_init(Dev d, int32_t m)
 {
     d.cnt->n_cur = m;
     d.cnt->round = 0;
+}
+
+// Twist-order stages: the list to filter has n entries; a stage starts from
+// the filtered list and treats its dimension as the top one (nothing can
+// clear its columns any more: the dimension above is reduced).
+__global__ void k_set_active(Dev d, int32_t n) { d.cnt->n_cur = n; }
+
+__global__ void k_stage_start(Dev d, int32_t topd)
+{
+    d.cnt->n_cur = d.cnt->n_next;
+    d.cnt->topdim = topd;
+}
+
+// One complex: instance offsets {0, m}.
+__global__ void k_one_instance(int64_t *off, int64_t m)
+{
+    off[0] = 0;
+    off[1] = m;
 }
 
 // End of a round: the compacted list is the next round's; a round that did
@@ -2197,8 +2471,17 @@ static pms_status grow_arena(Ctx *c, Dev &d, Counters *h, const ScratchSource &S
     return PMS_OK;
 }
 
+// the options added after the first ones: ranges, and dim where they need it
+static bool extra_options_ok(const pms_options &o, const pms_boundary *bnd)
+{
+    if (o.c8 < 0 || o.c8 > 1 || o.sweep < 0 || o.sweep > 1 || o.priority < 0 || o.priority > 2 ||
+        o.round_budget < 0 || o.reserved != 0)
+        return false;
+    return bnd->dim || (!o.c8 && !o.sweep);
+}
+
 static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options *opt, pms_result *res,
-                              ScratchSource &S)
+                              ScratchSource &S, const int64_t *inst_off, int32_t n_inst)
 {
     const int64_t m = bnd->m;
     res->n_pairs = res->n_essential = 0;
@@ -2212,7 +2495,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     const bool dbg = opt->debug_invariants != 0;
     if (m == 0) {
         if (diag) {
-            c->diag.push_back(pms_round_stats{0, 0, 0, 0, 0, 0, 0});
+            c->diag.push_back(pms_round_stats{0, 0, 0, 0, 0, 0, 0, 0});
             c->diag_m = 0;
         }
         return PMS_OK;
@@ -2320,6 +2603,39 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
     PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act0, m);
     PMS_LAUNCH(c, K_FILL, 0, k_round_init, 1, 1, d, (int32_t)m);
+    // priority with a budget: the key histogram (and threshold) and, for
+    // priority 1, the sizes of the sets N per low
+    const bool budget = opt->round_budget > 0;
+    int32_t *bud_h = nullptr, *bud_n = nullptr;
+    if (budget) {
+        bud_h = (int32_t *)S.get(B_BUDH, (kBudKeys + 3) * 4);
+        if (opt->priority == 1) bud_n = (int32_t *)S.get(B_BUDN, (size_t)m * 4);
+        if (!bud_h || (opt->priority == 1 && !bud_n)) return set_err(c, PMS_ERR_OOM, "round budget scratch");
+        PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, 1, kBlock, bud_h, (int64_t)kBudKeys + 3, 0);
+        if (bud_n) PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, gm, kBlock, bud_n, m, 0);
+    }
+    // clearing by local compression: the complexes and their first unpaired rows
+    const bool c8on = opt->c8 != 0;
+    d.inst_off = nullptr;
+    d.n_inst = 0;
+    d.c8_first = nullptr;
+    if (c8on) {
+        if (!inst_off) {
+            int64_t *one = (int64_t *)S.get(B_INST, 16);
+            if (!one) return set_err(c, PMS_ERR_OOM, "instance offsets");
+            PMS_LAUNCH(c, K_FILL, 0, k_one_instance, 1, 1, one, m);
+            inst_off = one;
+            n_inst = 1;
+        }
+        d.inst_off = inst_off;
+        d.n_inst = n_inst;
+        d.c8_first = (int32_t *)S.get(B_C8, (size_t)n_inst * kC8Stride * 4);
+        if (!d.c8_first) return set_err(c, PMS_ERR_OOM, "clearing-by-compression scratch");
+        // first rows 0 (scan from each instance's start); end: every row (m)
+        PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, grid_for((int64_t)n_inst * kC8Stride), kBlock, d.c8_first,
+                   (int64_t)n_inst * kC8Stride, 0);
+        PMS_LAUNCH(c, K_FILL, 0, k_c8_reset_end, grid_for(n_inst), kBlock, d);
+    }
     if (dbg) {
         PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, gm, kBlock, d.dbg_w, m, 0);
         PMS_LAUNCH(c, K_FILL, 0, k_fill_i32, gm, kBlock, d.dbg_erem, m, 0x7FFFFFFF);
@@ -2384,6 +2700,27 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         // act, state, low, coll, dim, beta; aggregates
         PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, gT, kBlock, d, a, agg, opt->compression);
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
+        if (c8on) {
+            // the first unpaired rows (a scan from the last ones, usually short); act, dim, beta, state, low
+            const unsigned gi = grid_for(d.n_inst, kBlock, 4096);
+            PMS_LAUNCH(c, K_C8, 0, k_c8_range, gi, kBlock, d);
+            if (d.n_inst >= 512) PMS_LAUNCH(c, K_C8, 0, k_c8_scan<2>, (unsigned)std::min<int64_t>(2LL * d.n_inst, 4096), kBlock, d);
+            else if (d.n_inst >= 16) PMS_LAUNCH(c, K_C8, 0, k_c8_scan<32>, (unsigned)std::min<int64_t>(32LL * d.n_inst, 4096), kBlock, d);
+            else PMS_LAUNCH(c, K_C8, 0, k_c8_scan<1024>, (unsigned)std::min<int64_t>(1024LL * d.n_inst, 4096), kBlock, d);
+            PMS_LAUNCH(c, K_C8, 0, k_c8_fold, gi, kBlock, d);
+            PMS_LAUNCH(c, K_C8, 14 * dA, k_c8_clear, gT, kBlock, d, a);
+            if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
+        }
+        if (budget) {  // which colliding columns add this round
+            const int pr = opt->priority, va = opt->variant;
+            if (pr == 1) PMS_LAUNCH(c, K_BUDGET, 0, k_bud_ncount, gA, kBlock, d, a, va, bud_n, 1);
+            PMS_LAUNCH(c, K_BUDGET, 0, k_bud_hist, gA, kBlock, d, a, va, pr, bud_n, bud_h);
+            PMS_LAUNCH(c, K_BUDGET, 0, k_bud_thresh, 1, kWave, bud_h, opt->round_budget);
+            PMS_LAUNCH(c, K_BUDGET, 0, k_bud_count, gT, kBlock, d, a, va, pr, bud_n, bud_h, keep2);
+            PMS_LAUNCH(c, K_SCAN, 0, k_scan_sum, 1, kScanThreads, keep2, 0, &d.cnt->n_cur, bud_h + kBudKeys + 2);
+            PMS_LAUNCH(c, K_BUDGET, 0, k_bud_apply, gT, kBlock, d, a, va, pr, bud_n, bud_h, keep2);
+            if (pr == 1) PMS_LAUNCH(c, K_BUDGET, 0, k_bud_ncount, gA, kBlock, d, a, va, bud_n, -1);
+        }
         PMS_LAUNCH(c, K_XOR, -1.0, k_xor, gT, kBlock, d, a, opt->variant, opt->compression, opt->chain,
                    opt->tail_active);
         xor_slot = c->pend.size() - 1;
@@ -2410,10 +2747,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
         chain_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
-        PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep);
+        PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep, -1);
         PMS_LAUNCH(c, K_SCAN, 8 * dt, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
         // act, state, act_next
-        PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an);
+        PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an, -1);
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (c->prof_on || trace || diag) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
         PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, 1, d);
@@ -2427,7 +2764,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_diag_count, grid_for(nwords, kBlock, 65536), kBlock, d, nwords);
         return PMS_OK;
     };
-    unsigned long long diag_adds = 0, diag_xe = 0, diag_np = 0;
+    unsigned long long diag_adds = 0, diag_xe = 0, diag_np = 0, diag_c8 = 0;
     auto record_diag = [&](int32_t r) {
         pms_round_stats e;
         e.round = r;
@@ -2437,6 +2774,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         e.xor_entries = (int64_t)(h->xor_entries - diag_xe);
         e.low_l1 = (int64_t)h->diag_low_l1;
         e.ess_estimate = (int64_t)h->diag_ess;
+        e.c8_cleared = (int64_t)(h->c8_cleared - diag_c8);
+        diag_c8 = h->c8_cleared;
         diag_np = (unsigned long long)h->new_pivots;
         diag_adds = h->additions;
         diag_xe = h->xor_entries;
@@ -2475,7 +2814,35 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // convergence find no active column and return at once.
     const int graph_k = (opt->graph_rounds > 0 && !c->prof_on && !trace && !diag && !dbg && opt->max_rounds == 0)
                             ? (opt->graph_rounds + 1) & ~1 : 0;
-    if (graph_k > 0) {
+    // Twist order (pms_options.sweep): one stage per dimension, from the top
+    // down; a stage's first list holds the active columns of its dimension,
+    // and the stage runs rounds until none is left.  Without it one stage
+    // holds every column.
+    int32_t sd = opt->sweep ? h->topdim : -1;
+    auto stage_build = [&](int32_t dsel) -> pms_status {
+        const int64_t tiles_m = (m + kBlock - 1) / kBlock;
+        const unsigned gTm = (unsigned)(tiles_m > 0 ? tiles_m : 1);
+        PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act1, m);
+        PMS_LAUNCH(c, K_FILL, 0, k_set_active, 1, 1, d, (int32_t)m);
+        PMS_LAUNCH(c, K_COMPACT, 6 * dm, k_keep_count, gTm, kBlock, d, act1, keep, (int)dsel);
+        PMS_LAUNCH(c, K_SCAN, 8.0 * tiles_m, k_scan_sum, 1, kScanThreads, keep, 0, &d.cnt->n_cur, &d.cnt->n_next);
+        PMS_LAUNCH(c, K_COMPACT, 10 * dm, k_compact, gTm, kBlock, d, act1, keep, act0, (int)dsel);
+        PMS_LAUNCH(c, K_FILL, 0, k_stage_start, 1, 1, d, dsel);
+        if (c8on) PMS_LAUNCH(c, K_FILL, 0, k_c8_reset_end, grid_for(d.n_inst), kBlock, d);
+        PMS_HIP(hipGetLastError());
+        PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        PMS_HIP(hipStreamSynchronize(st));
+        act = act0;
+        act_next = act1;
+        nA = h->n_cur;
+        return PMS_OK;
+    };
+    if (sd >= 0) {
+        const pms_status sb = stage_build(sd);
+        if (sb != PMS_OK) return sb;
+    }
+    for (;;) {
+    if (graph_k > 0 && nA > 0) {
         // fixed grids: enough blocks to fill the device, looping over tiles
         const int64_t gtiles = std::min<int64_t>((m + kBlock - 1) / kBlock, 2048);
         if (!c->graph_stream) PMS_HIP(hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
@@ -2626,6 +2993,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         nA = h->n_next;
         std::swap(act, act_next);
     }
+    if (sd <= 0) break;
+    sd--;
+    const pms_status sb = stage_build(sd);
+    if (sb != PMS_OK) return sb;
+    }
     PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
     if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_final, gm, kBlock, d);
     PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -2743,6 +3115,10 @@ pms_options pms_default_options(void)
     o.diagnostics = 0;
     o.arena_entries = 0;
     o.debug_invariants = 0;
+    o.c8 = 0;
+    o.sweep = 0;
+    o.priority = 0;
+    o.round_budget = 0;
     o.reserved = 0;
     return o;
 }
@@ -2799,7 +3175,7 @@ void pms_destroy(pms_ctx *c)
 static const char *const kKernelNames[pms::K_NUM] = {
     "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
     "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
-    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide"};
+    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide", "k_c8", "k_budget"};
 
 pms_status pms_profile_enable(pms_ctx *c, int enable)
 {
@@ -2966,12 +3342,12 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
     pms_options o = opt ? *opt : pms_default_options();
     if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0 || o.graph_rounds < 0 ||
         o.graph_rounds > 1024 || o.diagnostics < 0 || o.diagnostics > 1 || o.debug_invariants < 0 ||
-        o.debug_invariants > 1 || o.reserved != 0)
-        return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options");
+        o.debug_invariants > 1 || !pms::extra_options_ok(o, bnd))
+        return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options (c8 and sweep need dim)");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
     pms::ScratchSource S;
     S.c = c;
-    pms_status s = pms::reduce_impl(c, bnd, &o, res, S);
+    pms_status s = pms::reduce_impl(c, bnd, &o, res, S, c->inst_off, c->n_inst);
     if (s != PMS_OK && s != PMS_ERR_CAPACITY && s != PMS_ERR_NOT_CONVERGED) {
         res->n_pairs = res->n_essential = 0;
     }
@@ -2988,7 +3364,7 @@ pms_status pms_reduce_noalloc(pms_ctx *c, const pms_boundary *bnd, const pms_opt
         return pms::set_err(c, PMS_ERR_INVALID_ARG, "null col_ptr / rows / low_star");
     const pms_options o = opt ? *opt : pms_default_options();
     if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries != 0 || o.graph_rounds != 0 ||
-        o.diagnostics != 0 || o.debug_invariants < 0 || o.debug_invariants > 1 || o.reserved != 0)
+        o.diagnostics != 0 || o.debug_invariants < 0 || o.debug_invariants > 1 || !pms::extra_options_ok(o, bnd))
         return pms::set_err(c, PMS_ERR_INVALID_ARG,
                             "bad options (without allocation: no graph rounds, no diagnostics, arena_entries 0)");
     if (c->prof_on) return pms::set_err(c, PMS_ERR_INVALID_ARG, "the profiler is on (it creates events)");
@@ -2999,7 +3375,7 @@ pms_status pms_reduce_noalloc(pms_ctx *c, const pms_boundary *bnd, const pms_opt
     S.c = c;
     S.base = (char *)base;
     S.cap = PMS_NOALLOC_BYTES;
-    pms_status s = pms::reduce_impl(c, bnd, &o, res, S);
+    pms_status s = pms::reduce_impl(c, bnd, &o, res, S, nullptr, 1);
     if (s != PMS_OK && s != PMS_ERR_CAPACITY && s != PMS_ERR_NOT_CONVERGED) res->n_pairs = res->n_essential = 0;
     return s;
 }
@@ -3116,7 +3492,11 @@ pms_status pms_reduce_batched(pms_ctx *c, int32_t count, const int64_t *inst_col
             return pms::set_err(c, PMS_ERR_INVALID_ARG,
                                 "inst_col_off must ascend from 0 to m (count + 1 entries)");
     }
+    c->inst_off = inst_col_off;  // the complexes, for clearing by local compression
+    c->n_inst = count;
     pms_status s = pms_reduce(c, bnd, opt, res);
+    c->inst_off = nullptr;
+    c->n_inst = 1;
     if (s != PMS_OK) return s;
     const bool pairs = res->pair_birth && res->pair_death;
     if (inst_pair_off || inst_ess_off)

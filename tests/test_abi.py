@@ -39,14 +39,14 @@ def test_options_layout_and_defaults():
     lib = _binding.load()
     o = lib.pms_default_options()
     assert (o.variant, o.compression, o.max_rounds, o.chain, o.validate, o.arena_entries) == (0, 1, 0, 1, 1, 0)
-    assert ctypes.sizeof(_binding.PmsOptions) == 48
-    assert (o.debug_invariants, o.reserved) == (0, 0)
+    assert ctypes.sizeof(_binding.PmsOptions) == 64
+    assert (o.debug_invariants, o.c8, o.sweep, o.priority, o.round_budget, o.reserved) == (0, 0, 0, 0, 0, 0)
     assert ctypes.sizeof(_binding.PmsBoundary) == 32
     assert lib.pms_version().decode().startswith("pms-gfx950")
     # no context: the error text is static, and a null handle is rejected
     assert lib.pms_last_error(None) == b"no context"
     assert lib.pms_reduce(None, None, None, None) == _binding.PMS_ERR_INVALID_ARG
-    assert o.diagnostics == 0 and ctypes.sizeof(_binding.PmsRoundStats) == 48
+    assert o.diagnostics == 0 and ctypes.sizeof(_binding.PmsRoundStats) == 56
     assert lib.pms_round_stats_read(None, 0, None, None) == _binding.PMS_ERR_INVALID_ARG
     assert lib.pms_essential_estimate(None, 0, None) == _binding.PMS_ERR_INVALID_ARG
 
