@@ -599,13 +599,31 @@ def main():
             "per_round": [fmt(r) for r in keep],
         }
 
-    multiscale = multiscale_paper = None
+    multiscale = multiscale_paper = multiscale_priority = None
     if not args.no_multiscale:
         multiscale = multiscale_block(rkw, None)
         paper_kw = dict(variant=1, chain=False)
         multiscale_paper = multiscale_block(paper_kw, {0, 1, 2, 3, 5, 10, 20, 50, 100, 200, 500, 1000, 2000})
         multiscale_paper["schedule"] = ("Phase II adds known pivots only, one addition per column per round "
                                         "(no chaining): variant=1, chain=False")
+        # Sec. 3.4: fewer processors than colliding columns -- at most a
+        # budget of columns add per round, chosen by priority (0 column
+        # order, 1 largest sets N first, 2 known negative first), on the
+        # paper's schedule over a 24^3 grid of the same field recipe
+        f24 = api.build_lowerstar(torch.as_tensor(synth.gaussian_field(n=24), device=dev))
+        m24 = int(f24.m)
+        multiscale_priority = {"grid": "24^3 lower-star, Gaussian field (seed 5, sigma 4)", "m": m24,
+                               "schedule": "variant=1, chain=False, round_budget=2048"}
+        for prio, name in ((0, "column_order"), (1, "largest_N_first"), (2, "known_negative_first")):
+            dres = api.reduce_filtration(f24, diagnostics=True, variant=1, chain=False, round_budget=2048,
+                                         priority=prio)
+            rows = api.multiscale(dres.round_stats, m24, int(dres.essential.numel()))
+            first = lambda pred: next((r["round"] for r in rows if pred(r)), None)
+            multiscale_priority[name] = {
+                "rounds": dres.rounds, "additions": dres.additions,
+                "rounds_to_rel_l1_error": {f"1e-{k}": first(lambda r, k=k: r["rel_error"] <= 10.0 ** -k)
+                                           for k in (1, 2, 3, 4)},
+                "rounds_to_unreduced": {str(q): first(lambda r, q=q: r["unreduced"] <= q) for q in (0.5, 0.1, 0.01)}}
 
     roof = roof_s8d = None
     kernels = {}
@@ -687,6 +705,7 @@ def main():
         "phases": phases,
         "multiscale": multiscale,
         "multiscale_paper": multiscale_paper,
+        "multiscale_priority": multiscale_priority,
         "kernels": kernels,
         "cpu_baseline": None,
     }

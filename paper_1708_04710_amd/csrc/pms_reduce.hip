@@ -295,28 +295,58 @@ __global__ void k_iota(int32_t *p, int64_t n)
 __global__ void k_init(Dev d, int64_t nnz, int validate)
 {
     int top = 0;
+    const int lane = threadIdx.x & (kWave - 1);
     const XcdSplit xs = xcd_split((d.m + blockDim.x - 1) / blockDim.x);
     for (int64_t t = xs.first; t < xs.end; t += xs.step) {
         const int64_t j = t * blockDim.x + threadIdx.x;
-        if (j >= d.m) continue;
-        const int64_t s = d.col_ptr[j], e = d.col_ptr[j + 1];
+        const bool inr = j < d.m;
+        const int64_t s = inr ? d.col_ptr[j] : 0, e = inr ? d.col_ptr[j + 1] : 0;
         bool bad = e < s || s < 0 || e > nnz || (j == 0 && s != 0) || e - s > 0x7FFFFFFF;
         int32_t n = bad ? 0 : (int32_t)(e - s);
+        // Neighbouring columns often share their last row (VR triangles with
+        // one longest edge are consecutive in the order), and would all take
+        // the atomic on left at once; the first column of such a run has the
+        // smallest index, so the others leave that row to it.
+        const int32_t last = n > 0 ? d.rows[s + n - 1] : -1 - lane;
+        const int32_t prev_last = __shfl_up(last, 1, kWave);
+        const bool skip_last = lane > 0 && prev_last == last;
+        if (!inr) continue;
+        const int dj = validate && d.dim ? d.dim[j] : 0;
+        // the rows four at a time: their loads (and the facets' dimensions)
+        // go out together instead of one dependent chain per row
         int32_t prev = -1;
-        for (int64_t p = s; p < s + n; p++) {
-            const int32_t r = d.rows[p];
-            if (r <= prev || (int64_t)r >= j) { bad = true; break; }
-            if (validate && d.dim && d.dim[r] != d.dim[j] - 1) { bad = true; break; }
-            prev = r;
-            if ((int32_t)j < d.left[r]) atomicMin(&d.left[r], (int32_t)j);  // left only decreases
+        for (int32_t p0 = 0; p0 < n; p0 += 4) {
+            int32_t r[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) r[u] = p0 + u < n ? d.rows[s + p0 + u] : 0x7FFFFFFF;
+            int dr[4] = {0, 0, 0, 0};
+            if (validate && d.dim) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) dr[u] = p0 + u < n && r[u] >= 0 && (int64_t)r[u] < j ? d.dim[r[u]] : dj - 1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (p0 + u >= n) break;
+                if (r[u] <= prev || (int64_t)r[u] >= j || (validate && d.dim && dr[u] != dj - 1)) bad = true;
+                prev = r[u];
+            }
+            if (bad) break;
+#pragma unroll
+            for (int u = 0; u < 4; u++)  // left only decreases
+                if (p0 + u < n && !(skip_last && p0 + u == n - 1) && (int32_t)j < d.left[r[u]])
+                    atomicMin(&d.left[r[u]], (int32_t)j);
         }
-        if (validate && d.dim && d.dim[j] < 0) bad = true;
+        if (validate && d.dim && dj < 0) bad = true;
         if (bad) { atomicExch(&d.cnt->error, 1); n = 0; }
         d.off[j] = bad ? 0 : s;
         d.len[j] = n;
         d.low[j] = n ? d.rows[s + n - 1] : -1;
         d.state[j] = n ? ST_ACTIVE : ST_ZERO;
-        *reinterpret_cast<int2 *>(&d.prec[j]) = make_int2(-1, 0);  // row j: no pivot, not known negative
+        // row j: no pivot, not known negative (the whole 32-byte record, so
+        // the stores fill whole memory sectors)
+        int4 *pr = reinterpret_cast<int4 *>(&d.prec[j]);
+        pr[0] = make_int4(-1, 0, 0, 0);
+        pr[1] = make_int4(0, 0, 0, 0);
         if (d.dim && d.dim[j] > top) top = d.dim[j];
     }
     if (d.dim) {
@@ -349,30 +379,36 @@ __global__ void k_low(Dev d, const int32_t *act)
 {
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
+    const int lane = threadIdx.x & (kWave - 1);
     const XcdSplit xs = xcd_split(((int64_t)nA + blockDim.x - 1) / blockDim.x);
     for (int64_t t = xs.first; t < xs.end; t += xs.step) {
         const int64_t q = t * blockDim.x + threadIdx.x;
-        if (q >= nA) continue;
-        const int32_t j = act[q];
-        dbg_write(d, j);
-        int32_t n = d.len[j];
-        const int32_t *c = col_base(d, d.off[j]);
-        // rows of known-negative simplices at the bottom of the column are
-        // deleted outright (compression); the column's low is the last row left
-        while (n > 0 && is_neg(d.neg, c[n - 1])) n--;
-        d.len[j] = n;
-        if (n == 0) {
-            d.low[j] = -1;
-            d.state[j] = ST_ZERO;
-            continue;
+        int32_t j = -1, i = -1 - lane;  // (distinct in every lane without a low)
+        if (q < nA) {
+            j = act[q];
+            dbg_write(d, j);
+            int32_t n = d.len[j];
+            const int32_t *c = col_base(d, d.off[j]);
+            // rows of known-negative simplices at the bottom of the column are
+            // deleted outright (compression); the column's low is the last row left
+            while (n > 0 && is_neg(d.neg, c[n - 1])) n--;
+            d.len[j] = n;
+            if (n == 0) {
+                d.low[j] = -1;
+                d.state[j] = ST_ZERO;
+            } else {
+                i = c[n - 1];
+                d.low[j] = i;
+            }
         }
-        const int32_t i = c[n - 1];
-        d.low[j] = i;
         // T (the leftmost column per low) is read only for lows without a
         // known pivot (a pivot's low collides, and Phase II adds the pivot);
         // T only ever decreases, so a plain read that already shows a
-        // smaller key saves the atomic (many columns share a low)
-        if (d.piv[i] < 0) {
+        // smaller key saves the atomic, and of neighbouring positions with
+        // one low (the active list ascends) only the first, the smallest
+        // column, takes it
+        const int32_t prev_i = __shfl_up(i, 1, kWave);
+        if (i >= 0 && !(lane > 0 && prev_i == i) && d.piv[i] < 0) {
             const unsigned long long key = t_key(round, j);
             if (key < d.T[i]) atomicMin(&d.T[i], key);
         }
@@ -2243,6 +2279,9 @@ __global__ void k_defrag(Dev d, int32_t *dst, unsigned long long *dst_top)
             const int32_t *src = d.arena + (off & ~(int64_t)kArenaBit);
             for (int64_t k = 0; k < n; k++) dst[o + k] = src[k];
             d.off[j] = o | (int64_t)kArenaBit;
+            // debug_invariants: the move keeps the column's entries (a pivot
+            // column that moves has not changed)
+            if (d.dbg_off) d.dbg_off[j] = o | (int64_t)kArenaBit;
         }
     }
 }
