@@ -73,6 +73,11 @@ def _host_threads():
     return max(1, min(16, n))
 
 
+def _progress(msg):
+    """A finished phase of the run, on stderr (the JSON line is stdout's only line)."""
+    print(f"bench: {msg} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(grid_np, m_gpu, batches=True):
     """The oracle as it stands on the host cores.  The headline value: the
     full 64^3 grid, oracle build + standard reduction (Alg. "Standard
@@ -384,9 +389,13 @@ def _slot(kernel_name):
             "k_tile_apply": "k_build_scan"}.get(name, name)
 
 
-def rocprof_summary(tdir, fdir, wdir, out_md):
+def rocprof_summary(tdir, fdir, wdir, out_md, bench_json=None):
     """Summarise the three rocprofv3 runs (PROFILE_CMDS) into a text summary
-    and profiles/traffic.json (HBM bytes per launch, scaled by the copy)."""
+    and profiles/traffic.json (HBM bytes per launch, scaled by the copy);
+    with the JSON line of the first (unprofiled) bench run, also each
+    kernel's algorithmic bytes per launch (the library's byte model and
+    the unit cost of the additions), its launch time from HIP events and the
+    fraction of the HBM peak they make."""
     import csv
     import glob
     from collections import defaultdict
@@ -430,12 +439,13 @@ def rocprof_summary(tdir, fdir, wdir, out_md):
                            "bytes_per_launch": fb / fn + wb / wn}
     tj = {"source_hash": _source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
           "copy_bytes": COPY_BYTES, "kernels": kernels}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(os.path.join(os.path.dirname(os.path.abspath(out_md)), "traffic.json"), "w") as fh:
         json.dump(tj, fh, indent=1, sort_keys=True)
     lines = ["# rocprofv3 summary: 64^3 lower-star step (build + pms reduce + pairs + backward)", "",
              "Commands (run from the repository root; <T>, <F>, <W> are output folders, <C> the tuning cache the first writes):", ""]
     lines += [f"    {c}" for c in PROFILE_CMDS]
-    lines += ["", "Summarised with: python3 bench.py --rocprof-summary <T> <F> <W> <this file>",
+    lines += ["", "Summarised with: python3 bench.py --rocprof-summary <T> <F> <W> <this file> <the first command's "
+              "JSON line>",
               "", "## Kernel time (kernel trace: 1 warm-up step, then 3 steps timed without and 3 with per-kernel events)", "",
               "| kernel (rocprof name, shortened) | calls | total ms | avg us |", "|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
@@ -451,16 +461,78 @@ def rocprof_summary(tdir, fdir, wdir, out_md):
         avg = sum(d) / len(d) if d else float("nan")
         lines.append(f"| {sl} | {len(d)} | {avg:.1f} | {k['fetch_bytes_per_launch'] / 1e6:.3f} | "
                      f"{k['write_bytes_per_launch'] / 1e6:.3f} |")
+    if bench_json:
+        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        steps = b["steps"]
+        lines += ["", "## Algorithmic bytes per kernel (the first command's run: HIP events around each launch)", "",
+                  f"Step: {b['ms_per_step']} ms ({b['value']:.4g} {b['unit']}).  alg = the library's byte model "
+                  "(every array a launch must read or write once); add = 4 (len t + len s + len t+s) summed over "
+                  "the launch's column additions; GB/s and frac = alg bytes / average launch time against "
+                  f"{HBM_PEAK_GBS:.0f} GB/s; counted/alg = (FETCH_SIZE + WRITE_SIZE) per launch / alg.", "",
+                  "| kernel | launches/step | avg us | alg MB/launch | add MB/launch | GB/s | frac | counted/alg |",
+                  "|---|---|---|---|---|---|---|---|"]
+        for name, k in sorted(b["kernels"].items(), key=lambda kv: -kv[1]["ms_total"]):
+            avg = k["avg_us"]
+            alg = k.get("alg_bytes_per_launch", 0.0)
+            add = k.get("addition_bytes_per_launch")
+            gbs = alg / (avg * 1e-6) / 1e9 if avg > 0 else 0.0
+            cnt = kernels.get(name, {}).get("bytes_per_launch")
+            ratio = f"{cnt / alg:.2f}" if cnt and alg > 0 else "-"
+            lines.append(f"| {name} | {k['launches'] / steps:.1f} | {avg:.1f} | {alg / 1e6:.3f} | "
+                         f"{(add / 1e6) if add else 0.0:.3f} | {gbs:.1f} | {gbs / HBM_PEAK_GBS:.4f} | {ratio} |")
+        if b.get("roofline_s8d"):
+            lines += ["", "Sec. 8(d) roofline of the step: " + json.dumps(b["roofline_s8d"])]
     lines += ["", f"Source hash of the kernels measured: {tj['source_hash']}", ""]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines))
     print(out_md)
 
 
+def batch_summary(tdir, workload, bench_json, out_md):
+    """Kernel-time summary of a batched workload's rocprofv3 kernel trace
+    (the commands in BATCH_PROFILE_CMDS), with the unprofiled run's line."""
+    import csv
+    import glob
+    hits = glob.glob(os.path.join(tdir, "*kernel_stats.csv"))
+    if not hits:
+        raise SystemExit(f"no kernel_stats.csv under {tdir}")
+    stats = list(csv.DictReader(open(hits[0])))
+    b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    title = {"circles64": "64 FP32 circles x 128 points, batched (build + reduce + backward)",
+             "vr512": "512 integer Vietoris-Rips clouds, batched (build + reduce)"}[workload]
+    lines = [f"# rocprofv3 summary: {title}", "",
+             "Commands (run from the repository root; <C> is the tuning cache the first writes, <T> the output "
+             "folder):", ""]
+    lines += [f"    {c.replace('<W>', workload)}" for c in BATCH_PROFILE_CMDS]
+    lines += ["", f"Summarised with: python3 bench.py --batch-summary <T> {workload} <the first command's JSON line> "
+              "<this file>", "",
+              f"The first command's line: {b['ms_per_step']} ms per step, m = {b['config']['m']}, "
+              f"{b['value']:.3g} simplices/s.", "",
+              "## Kernel time (kernel trace: 1 warm-up step + 3 steps)", "",
+              "| kernel (rocprof name, shortened) | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
+        lines.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    lines += [""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print(out_md)
+
+
+BATCH_PROFILE_CMDS = [
+    "python3 bench.py --workload <W> --steps 5 --warmup 2 --tune-cache <C>",
+    "rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o b -- python3 bench.py --workload <W> "
+    "--steps 3 --warmup 1 --tune-cache <C>",
+]
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--batch-summary":
+        batch_summary(*sys.argv[2:6])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
         t, f, w, out = sys.argv[2:6]
-        rocprof_summary(t, f, w, out)
+        rocprof_summary(t, f, w, out, sys.argv[6] if len(sys.argv) > 6 else None)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -505,6 +577,7 @@ def main():
     f = api.build_lowerstar(grid)
     tune = False if args.no_autotune else args.tune_cache
     rkw, tune_rec = _tune(tune, f)
+    _progress("64^3 built and tuned")
 
     state = {}
 
@@ -600,6 +673,7 @@ def main():
         }
 
     multiscale = multiscale_paper = multiscale_priority = None
+    _progress("timed steps done")
     if not args.no_multiscale:
         multiscale = multiscale_block(rkw, None)
         paper_kw = dict(variant=1, chain=False)
@@ -709,12 +783,16 @@ def main():
         "kernels": kernels,
         "cpu_baseline": None,
     }
+    _progress("multiscale and profile done")
     if not args.no_batched:
         out["batched"] = batched_vs_plain(api, autograd, synth, torch, dev, tune)
+        _progress("batched workloads done")
     if not args.no_dim3:
         out["vr_dim3"] = vr_dim3(api, synth, torch, dev, tune)
+        _progress("dimension-3 workload done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid_np, m, batches=not args.no_batched)
+        _progress("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 
