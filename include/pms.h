@@ -291,9 +291,10 @@ pms_status pms_essential_estimate(pms_ctx *ctx, int64_t m, uint32_t *bits);
 
 /* ------------------------------------------------------------------------
  * Tuning.  Pivot chaining (an addition to Phase II of Sec. 3.1: a column
- * keeps adding the known pivot of its low within a round) runs in two
- * kernels: a lane kernel, one lane per queued column, and a wavefront
- * kernel for the columns the lanes hand on.  Their launch shapes and
+ * keeps adding the known pivot of its low within a round) runs in lane
+ * kernels, one lane per queued column, then, for the columns the lanes
+ * hand on, a workgroup kernel that solves each chain by sweeps and a
+ * wavefront kernel that walks a chain one addition at a time.  Their launch shapes and
  * hand-over thresholds are a per-context pms_tuning.  Every valid setting
  * gives the same low*, pairs and essential simplices (a reduced matrix's
  * lows are unique, Sec. 2.3); only speed changes, and with it possibly the
@@ -316,10 +317,16 @@ typedef struct {
                                first pass; 1..65535 */
     int32_t lane_cap;       /* entries of the first pass's per-lane buffer in use (longer
                                columns go to the second pass); 0..39 */
-    int32_t reserved;       /* 0 */
+    int32_t solve;          /* when the lanes hand on at most this many columns in a
+                               round, they are reduced by sweeps of the triangular system
+                               their chain solves (one workgroup per column, chain_blocks
+                               256-thread blocks; the pivots added are the serial chain's),
+                               those that do not fit its LDS table by the wavefront
+                               kernel; more columns, or 0, go to the wavefront kernel
+                               only; 0..2^30 */
 } pms_tuning;
 
-/* The built-in setting: 2048, 512, 128, 0, 65536, 32, 16, 2048, 39. */
+/* The built-in setting: 2048, 512, 128, 0, 65536, 32, 16, 2048, 39, 512. */
 pms_tuning pms_default_tuning(void);
 /* Make *t the context's setting for later reductions (NULL = the built-in
  * one).  PMS_ERR_INVALID_ARG, setting unchanged, when a field is out of range. */

@@ -67,7 +67,7 @@ class PmsTuning(ctypes.Structure):
                 ("lane_steps", ctypes.c_int32), ("lane_steps_few", ctypes.c_int32),
                 ("lane_many", ctypes.c_int32), ("lane_refill", ctypes.c_int32),
                 ("lane_flush", ctypes.c_int32), ("wide_blocks", ctypes.c_int32),
-                ("lane_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lane_cap", ctypes.c_int32), ("solve", ctypes.c_int32)]
 
 
 class PmsFiltrationView(ctypes.Structure):

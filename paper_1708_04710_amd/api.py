@@ -337,7 +337,7 @@ def multiscale(stats: list, m: int, n_essential: int | None = None) -> list:
 
 
 # ------------------------------------------------------------------ tuning
-TUNING_FIELDS = tuple(f for f, _ in B.PmsTuning._fields_ if f != "reserved")
+TUNING_FIELDS = tuple(f for f, _ in B.PmsTuning._fields_)
 
 
 def default_tuning() -> dict:

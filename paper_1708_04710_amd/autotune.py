@@ -40,6 +40,8 @@ GRID = {
     "lane_flush": (8, 16, 32),
     "wide_blocks": (1024, 2048, 4096),
     "lane_cap": (24, 32, 39),
+    # most handed-over columns a round solves by sweeps (0: walk every chain)
+    "solve": (0, 512, 4096),
     "graph_rounds": (0, 8),
     # Phase II source: 0 the leftmost column per low, 1 pivots only (Alg. 2);
     # both reach the same low*, so the faster one is kept

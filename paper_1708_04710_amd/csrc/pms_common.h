@@ -27,7 +27,7 @@ struct Buf {
 enum KernelId {
     K_INIT = 0, K_BETA, K_LOW, K_COLLIDE, K_SCAN, K_PIVOTS, K_XOR, K_COMPACT, K_FINAL, K_FILL, K_DEFRAG,
     K_LS_KEYS, K_SORT, K_LS_INDEX, K_BUILD_SCAN, K_LS_ROWS, K_VR_EDGES, K_VR_TRI, K_VR_INDEX, K_VR_ROWS,
-    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE, K_C8, K_BUDGET,
+    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE, K_C8, K_BUDGET, K_SOLVE,
     K_NUM
 };
 
@@ -57,7 +57,7 @@ inline pms_tuning default_tuning()
     t.lane_flush = 16;
     t.wide_blocks = 2048;
     t.lane_cap = kLaneCap;
-    t.reserved = 0;
+    t.solve = 512;  // rounds that hand on a few long chains (the 64^3 lower-star's later rounds)
     return t;
 }
 
@@ -67,7 +67,7 @@ inline bool tuning_valid(const pms_tuning &t)
            t.lane_steps >= 0 && t.lane_steps <= (1 << 30) && t.lane_steps_few >= 0 &&
            t.lane_steps_few <= (1 << 30) && t.lane_many >= 0 && t.lane_refill >= 1 && t.lane_refill <= 64 &&
            t.lane_flush >= 1 && t.lane_flush <= 64 && t.wide_blocks >= 1 && t.wide_blocks <= 65535 &&
-           t.lane_cap >= 0 && t.lane_cap <= kLaneCap && t.reserved == 0;
+           t.lane_cap >= 0 && t.lane_cap <= kLaneCap && t.solve >= 0 && t.solve <= (1 << 30);
 }
 
 struct Ctx {

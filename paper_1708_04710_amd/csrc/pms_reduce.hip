@@ -68,6 +68,9 @@ enum StatId {
     // bytes of the additions by the unit cost of one column addition,
     // 4 (len t + len s + len t+s), per kernel
     S_ABYTES_XOR, S_ABYTES_LANE, S_ABYTES_WIDE, S_ABYTES_CHAIN,
+    // k_chain_solve: algorithmic bytes, bytes of its additions as multi-way sums, sweeps,
+    // columns solved, columns handed to k_chain
+    S_SBYTES, S_ABYTES_SOLVE, S_T_SWEEPS, S_T_SOLVED, S_T_SFALL,
     S_NUM
 };
 
@@ -82,6 +85,9 @@ struct Counters {
     // 4 (len t + len s + len t+s) summed over the additions of k_xor, the two
     // lane passes and k_chain (the bytes of a column addition by itself)
     unsigned long long abytes_xor, abytes_lane, abytes_wide, abytes_chain;
+    unsigned long long solve_bytes;  // algorithmic bytes moved by k_chain_solve
+    // its additions as multi-way sums: 4 (len c + the pivots' lengths + len out) per column
+    unsigned long long abytes_solve;
     unsigned long long active_sum;   // sum over rounds of the round's active columns
     unsigned long long diag_low_l1;  // diagnostics: sum_j (low(j) + 1)
     unsigned long long diag_ess;     // diagnostics: |E|
@@ -98,6 +104,7 @@ struct Counters {
     int32_t n_ess;
     int32_t bad_source;  // internal invariant broken (never expected)
     int32_t max_chain;   // trace: most additions one column made in k_chain this round
+    int32_t max_sweeps;  // most sweeps one column took in k_chain_solve this round
     int32_t n_cur;       // active columns of the current round (read by the round kernels)
     uint32_t round;      // rounds that did work so far
     int32_t dbg_flags;   // debug_invariants: the invariants found broken (DbgBit)
@@ -160,7 +167,8 @@ struct Dev {
     PivRec *prec;      // [m] pivot records by row
     int32_t *cq;       // chain queue, kPart slices of cq_slice entries
     int32_t *cq_n;     // entries per slice, one cache line each: cq_n[p*32]; cq_n[kPart*32] = wq entries,
-                       // cq_n[(kPart+1)*32] = wq2 entries
+                       // cq_n[(kPart+1)*32] = wq2 entries, cq_n[(kPart+2)*32] = wq2 entries k_chain_solve
+                       // hands to k_chain (after the wide pass has read the first ones)
     int64_t cq_slice;
     int32_t *wq;       // columns handed from the lane chain passes to the wavefront kernel
     int32_t *wq2;      // columns the first lane pass hands to the wide one (too long for its buffer)
@@ -420,8 +428,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
 {
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
-    if (blockIdx.x == 0 && threadIdx.x <= kPart + 1) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = 0;
+    if (blockIdx.x == 0 && threadIdx.x <= kPart + 2) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = d.cnt->max_sweeps = 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
     const XcdSplit xs = xcd_split(tiles);
     for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
@@ -1519,8 +1527,10 @@ __device__ inline void wait_vmem()
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies to LDS have landed
 }
 
+// With solve_max > 0 and at most that many columns handed over, only those
+// k_chain_solve passes on (wq2); else the lane passes' hand-over queue (wq).
 template <bool kTrace>
-__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression)
+__global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compression, int32_t solve_max)
 {
     __shared__ int32_t sW[kChainWaves][2][kCapW];
     __shared__ int32_t sS[kChainWaves][kCapS];
@@ -1530,13 +1540,15 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
     const int w = bcast_first(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);  // w: uniform by construction
     const unsigned gw = blockIdx.x * kChainWaves + w, nw = gridDim.x * kChainWaves;
     int4 *RPa = sRP[w][0], *RPb = sRP[w][1], *RWa = sRW[w][0], *RWb = sRW[w][1];
-    const int32_t total = d.cq_n[kPart * 32];  // columns the lane kernel handed over
+    const bool fallback = solve_max > 0 && d.cq_n[kPart * 32] <= solve_max;
+    const int32_t *queue = fallback ? d.wq2 : d.wq;
+    const int32_t total = d.cq_n[(fallback ? kPart + 2 : kPart) * 32];
     int64_t adds = 0, xe = 0, by = 0, ab = 0;
     // trace: short, long, global, sum |W|, toggle / next / flush cycles, flushes, queued, lows from P, deletions
     unsigned long long tr[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (kTrace && gw == 0) tr[8] = (unsigned long long)total;
     for (int32_t t = (int32_t)gw; t < total; t += (int32_t)nw) {
-        const int32_t j = d.wq[t];
+        const int32_t j = queue[t];
         const int32_t L0 = d.len[j];
         by += 4 + 12 + 4 * (int64_t)L0;  // queue entry, header, column in
         const int32_t *g = col_base(d, d.off[j]);
@@ -1918,6 +1930,346 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
             stat_add(d, S_T_FROMP, tr[9], gw);
             stat_add(d, S_T_DEL, tr[10], gw);
         }
+    }
+}
+
+// ------------------------------------------ chaining as a triangular solve
+// The pivots a chained column j adds are fixed by a unit-triangular system
+// over F2 (the inner loop of Alg. "Standard reduction", on known pivots).
+// Let c be the column, P_s the pivot column of a row s that has a known pivot
+// (its low is s: every other entry lies below s) and S the rows whose pivot
+// gets added.  With v(r) = c(r) + the sum of P_s(r) over s in S with s > r,
+// row r is in S exactly when it has a known pivot, v(r) = 1 and r lies above
+// L, the highest row with v = 1 and no known pivot (the chain ends there: it
+// is the new low; with no such row the column reduces to zero).  The result
+// is c + the sum of P_s over S, and low(j) becomes L.  Whether r is in S
+// depends only on rows above r, so the system has one solution, and the
+// sweep "S from v, then v from S" is exact on every row whose dependencies
+// are: it reaches the solution after as many sweeps as the longest path of
+// dependencies among the rows involved.  The serial walk (k_chain) makes one
+// dependent addition per step: thousands on the longest columns of a 64^3
+// lower-star filtration, whose dependency paths are 10 to 80 rows long.
+//
+// One workgroup per column.  The rows the column touches live in an LDS hash
+// table (row -> flags, one byte per slot); a sweep is a pass that finds L, a
+// pass that flips the membership of the rows whose test changed (into a
+// list), and a pass that toggles the entries of those rows' pivots (from
+// their records, one load each) into the table.  The head of each entry's
+// own record (pivot, length) is loaded before it is toggled: rows known to
+// be negative are left out (compression deletes them), and a new row enters
+// the table with its flags.  The result is written back sorted.  A column
+// whose rows would overfill the table goes to k_chain.
+constexpr int kSolveThreads = 256;
+constexpr int kSolveH = 12288;                    // hash slots
+constexpr int kSolveMaxU = kSolveH / 4 * 3;       // rows one column may touch
+constexpr int kSolveSort = 8192;                  // longest result (sorted in the table's first slots)
+constexpr int kSolveDelta = 2048;                 // membership changes applied per sweep
+constexpr int kSolveSweeps = 4096;                // a column still changing then goes to k_chain
+constexpr int kSolvePer = kSolveH / 4 / kSolveThreads;  // flag words (4 slots each) per thread
+static_assert(kSolveH % (4 * kSolveThreads) == 0 && kSolveSort <= kSolveH && kSolveMaxU < kSolveH,
+              "k_chain_solve's table: whole flag words per thread, the sort fits, probes end");
+// flags of a slot
+constexpr uint32_t kSV = 1;   // v(r)
+constexpr uint32_t kSX = 2;   // r is in S
+constexpr uint32_t kSP = 4;   // r has a known pivot
+constexpr uint32_t kSN = 8;   // r is known negative (deleted by compression)
+constexpr uint32_t kSR = 16;  // r's pivot lies right of column j (never expected in S)
+
+__device__ inline uint32_t solve_hash(int32_t r)
+{
+    return (uint32_t)(((uint64_t)((uint32_t)r * 2654435761u) * kSolveH) >> 32);
+}
+
+// Toggles v(e), inserting row e with flags fl when it is new.  The table
+// holds at most kSolveMaxU rows (probes always find a free slot); past that
+// *fail is set and the column goes to the serial kernel.
+__device__ inline void solve_toggle(int32_t *hk, uint32_t *hf, int32_t *nu, int32_t *fail, int32_t e, uint32_t fl)
+{
+    uint32_t h = solve_hash(e);
+    for (;;) {
+        const int32_t k = __hip_atomic_load(&hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == e) break;
+        if (k < 0) {
+            if (atomicAdd(nu, 1) >= kSolveMaxU) {
+                atomicExch(fail, 1);
+                return;
+            }
+            const int32_t old = atomicCAS(&hk[h], -1, e);
+            if (old == -1) {
+                fl |= kSV;  // with the toggle below, one atomic
+                atomicXor(&hf[h >> 2], fl << (8 * (h & 3)));
+                return;
+            }
+            atomicSub(nu, 1);
+            if (old == e) break;
+        }
+        h = h + 1 == (uint32_t)kSolveH ? 0 : h + 1;
+    }
+    atomicXor(&hf[h >> 2], kSV << (8 * (h & 3)));
+}
+
+// Flags of row r from the head of its record (pivot, length).
+__device__ inline uint32_t solve_flags(int2 head, int32_t j, int compression)
+{
+    if (head.x >= 0) return head.x < j ? kSP : (kSP | kSR);
+    return (compression && head.y < 0) ? kSN : 0u;
+}
+
+// Toggles up to kN rows: the heads of their records are loaded together
+// first; known-negative rows are skipped.
+template <int kN>
+__device__ inline void solve_toggle_n(const Dev &d, int32_t *hk, uint32_t *hf, int32_t *nu, int32_t *fail,
+                                      const int32_t (&rows)[kN], int32_t n, int32_t j, int compression)
+{
+    int2 head[kN];
+#pragma unroll
+    for (int u = 0; u < kN; u++)
+        head[u] = u < n ? *reinterpret_cast<const int2 *>(&d.prec[rows[u]]) : make_int2(-1, 0);
+#pragma unroll
+    for (int u = 0; u < kN; u++) {
+        const uint32_t fl = solve_flags(head[u], j, compression);
+        if (u < n && !(fl & kSN)) solve_toggle(hk, hf, nu, fail, rows[u], fl);
+    }
+}
+
+// The kernel takes the handed-over columns when there are at most solve_max
+// of them (a round of few, long chains, bound by its longest one); more
+// columns are walked by k_chain, whose waves hold more columns per CU.
+__global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compression, int32_t solve_max)
+{
+    __shared__ int32_t hk[kSolveH];       // row of each slot, -1 = free; reused to sort the result
+    __shared__ uint32_t hf[kSolveH / 4];  // flags, byte (slot & 3) of word slot / 4
+    __shared__ int32_t dl[kSolveDelta];   // this sweep's changes of S: r (joins) or ~r (leaves)
+    __shared__ int32_t s_nu, s_fail, s_bad, s_L[2], s_nd[2];
+    __shared__ long long s_o;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int32_t total = d.cq_n[kPart * 32];  // columns the lane passes handed over
+    if (total > solve_max) return;             // k_chain takes them all
+    int64_t adds = 0, pk = 0, by = 0, ab = 0, sweeps = 0;  // pk: entries of the added pivots
+    int32_t nsolved = 0, nfall = 0;
+    for (int32_t t = (int32_t)blockIdx.x; t < total; t += (int32_t)gridDim.x) {
+        __syncthreads();  // the previous column's last reads of the table and counters are done
+        const int32_t j = d.wq[t];
+        const int32_t L0 = d.len[j];
+        const int32_t *g = col_base(d, d.off[j]);
+        if (L0 > kSolveMaxU / 2) {
+            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
+            nfall++;
+            continue;
+        }
+        for (int a = tid; a < kSolveH; a += kSolveThreads) hk[a] = -1;
+        for (int a = tid; a < kSolveH / 4; a += kSolveThreads) hf[a] = 0;
+        if (tid == 0) {
+            s_nu = 0;
+            s_fail = 0;
+            s_bad = 0;
+            s_L[0] = s_L[1] = 0;
+            s_nd[0] = s_nd[1] = 0;
+        }
+        __syncthreads();
+        // v = c
+        for (int32_t a0 = 0; a0 < L0; a0 += 4 * kSolveThreads) {
+            int32_t rows[4];
+            int32_t n = 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int32_t a = a0 + u * kSolveThreads + tid;
+                rows[u] = a < L0 ? g[a] : -1;
+                n += a < L0 ? 1 : 0;
+            }
+            solve_toggle_n<4>(d, hk, hf, &s_nu, &s_fail, rows, n, j, compression);
+        }
+        __syncthreads();
+        bool ok = false;
+        int64_t cxe = 0;  // entries of the pivots in S (this thread's share)
+        for (int it = 0;; it++) {
+            const int p = it & 1;
+            // L + 1 (0: no row with v = 1 lacks a pivot)
+            int32_t lm = 0;
+#pragma unroll
+            for (int u = 0; u < kSolvePer; u++) {
+                const int w = u * kSolveThreads + tid;
+                const uint32_t f = hf[w];
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    if (((f >> (8 * b)) & (kSV | kSP | kSN)) == kSV) lm = max(lm, hk[4 * w + b] + 1);
+            }
+            lm = wave_max_dpp(lm);
+            if (lane == 0 && lm > 0) atomicMax(&s_L[p], lm);
+            __syncthreads();
+            const int32_t Lp1 = s_L[p];
+            // the membership test; at most kSolveDelta changes a sweep (the rest wait for the next)
+#pragma unroll
+            for (int u = 0; u < kSolvePer; u++) {
+                const int w = u * kSolveThreads + tid;
+                const uint32_t f = hf[w];
+                uint32_t nf = f;
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const uint32_t fb = f >> (8 * b);
+                    if (!(fb & (kSV | kSX))) continue;
+                    const int32_t r = hk[4 * w + b];
+                    const bool want = (fb & (kSV | kSP | kSN)) == (kSV | kSP) && r >= Lp1;
+                    if (want != ((fb & kSX) != 0)) {
+                        const int32_t q = atomicAdd(&s_nd[p], 1);
+                        if (q < kSolveDelta) {
+                            dl[q] = want ? r : ~r;
+                            nf ^= kSX << (8 * b);
+                        }
+                    }
+                }
+                if (nf != f) hf[w] = nf;
+            }
+            __syncthreads();
+            const int32_t nd = min(s_nd[p], kSolveDelta);
+            if (s_fail || nd == 0 || it >= kSolveSweeps) {
+                ok = !s_fail && nd == 0;
+                sweeps += it;
+                if (tid == 0) atomicMax(&d.cnt->max_sweeps, it);
+                break;
+            }
+            if (tid == 0) {
+                s_L[p ^ 1] = 0;
+                s_nd[p ^ 1] = 0;
+            }
+            // toggle the entries of the changed rows' pivots
+            for (int32_t q = tid; q < nd; q += kSolveThreads) {
+                const int32_t code = dl[q];
+                const int32_t r = code >= 0 ? code : ~code;
+                const PivRec rec = d.prec[r];
+                const int32_t k = rec.k;  // the pivot's length, its low r included
+                cxe += code >= 0 ? k : -k;
+                by += 32;
+                if (k - 1 <= kRecInline) {
+                    const int32_t rows[kRecInline] = {rec.e[0], rec.e[1], rec.e[2], rec.e[3], rec.e[4], rec.e[5]};
+                    solve_toggle_n<kRecInline>(d, hk, hf, &s_nu, &s_fail, rows, k - 1, j, compression);
+                } else {
+                    const int32_t *pc = col_base(d, d.off[rec.s]);
+                    by += 12 + 4 * (int64_t)k;
+                    for (int32_t a0 = 0; a0 < k - 1; a0 += 4) {
+                        int32_t rows[4];
+                        int32_t n = 0;
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            rows[u] = a0 + u < k - 1 ? pc[a0 + u] : -1;
+                            n += a0 + u < k - 1 ? 1 : 0;
+                        }
+                        solve_toggle_n<4>(d, hk, hf, &s_nu, &s_fail, rows, n, j, compression);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!ok) {
+            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
+            nfall++;
+            continue;
+        }
+        nsolved++;
+        // the result: the rows with v = 1 outside S (and not deleted), sorted
+        int32_t keys[kSolvePer * 4];
+        int32_t nw = 0, ns = 0;
+        bool bad = false;
+#pragma unroll
+        for (int u = 0; u < kSolvePer; u++) {
+            const int w = u * kSolveThreads + tid;
+            const uint32_t f = hf[w];
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const uint32_t fb = f >> (8 * b);
+                const bool keep = (fb & (kSV | kSX | kSN)) == kSV;
+                keys[u * 4 + b] = keep ? hk[4 * w + b] : -1;
+                nw += keep ? 1 : 0;
+                ns += (fb & kSX) ? 1 : 0;
+                bad = bad || (fb & (kSX | kSR)) == (kSX | kSR);
+            }
+        }
+        if (bad) s_bad = 1;
+        int32_t tot_w, tot_s;
+        int32_t o = block_excl_sum32(nw, &tot_w);  // its barriers order the reads above before the writes below
+        block_excl_sum32(ns, &tot_s);
+        if (tot_w > kSolveSort) {  // too long for the sort buffer: the serial kernel redoes it
+            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
+            nfall++;
+            nsolved--;
+            continue;
+        }
+        if (s_bad) {  // a pivot right of the column would be added: never expected
+            if (tid == 0) {
+                d.cnt->bad_info[0] = j;
+                d.cnt->bad_info[1] = -1;
+                d.cnt->bad_info[2] = L0;
+                d.cnt->bad_info[3] = tot_s;
+                atomicExch(&d.cnt->bad_source, 4);
+            }
+            continue;
+        }
+        int32_t n2 = 1;
+        while (n2 < tot_w) n2 <<= 1;
+#pragma unroll
+        for (int u = 0; u < kSolvePer * 4; u++)
+            if (keys[u] >= 0) hk[o++] = keys[u];
+        for (int32_t a = tot_w + tid; a < n2; a += kSolveThreads) hk[a] = 0x7FFFFFFF;
+        __syncthreads();
+        // bitonic sort of hk[0, n2)
+        for (int32_t kk = 2; kk <= n2; kk <<= 1)
+            for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int32_t a = tid; a < n2; a += kSolveThreads) {
+                    const int32_t b = a ^ jj;
+                    if (b > a) {
+                        const int32_t x = hk[a], y = hk[b];
+                        if ((x > y) == ((a & kk) == 0)) {
+                            hk[a] = y;
+                            hk[b] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        pk += cxe;
+        if (tid == 0) {
+            adds += tot_s;
+            by += 4 + 12 + 4 * (int64_t)L0;  // queue entry, header, column in
+            ab += 4 * (int64_t)tot_w;  // + 4 (len c + the pivots' lengths) from pk
+            pk += L0;
+        }
+        if (tot_w == 0) {
+            if (tid == 0) {
+                dbg_write(d, j);
+                d.len[j] = 0;
+                d.low[j] = -1;
+                d.state[j] = ST_ZERO;  // column j is positive
+            }
+            continue;
+        }
+        if (tid == 0) s_o = arena_alloc(d, blockIdx.x, tot_w);
+        __syncthreads();
+        const long long oa = s_o;
+        if (oa < 0) {
+            if (tid == 0) atomicExch(&d.cnt->overflow, 1);
+            continue;  // progress of this column is dropped; the stored column is still valid
+        }
+        for (int32_t a = tid; a < tot_w; a += kSolveThreads) d.arena[oa + a] = hk[a];
+        if (tid == 0) {
+            by += 4 * (int64_t)tot_w + 16;  // column and header out
+            dbg_write(d, j);
+            d.off[j] = (int64_t)oa | (int64_t)kArenaBit;
+            d.len[j] = tot_w;
+            d.low[j] = hk[tot_w - 1];
+        }
+    }
+    // the additions' bytes as one multi-way sum: 4 (len c + the pivots' lengths + len out)
+    const int64_t b_adds = block_sum64(adds), b_xe = block_sum64(pk), b_by = block_sum64(by);
+    const int64_t b_ab = block_sum64(ab) + 4 * b_xe;
+    const int64_t b_sw = block_sum64(sweeps) / kSolveThreads;
+    if (tid == 0) {
+        stat_add(d, S_ADDS, (unsigned long long)b_adds, blockIdx.x);
+        stat_add(d, S_XE, (unsigned long long)b_xe, blockIdx.x);
+        stat_add(d, S_SBYTES, (unsigned long long)b_by, blockIdx.x);
+        stat_add(d, S_ABYTES_SOLVE, (unsigned long long)b_ab, blockIdx.x);
+        stat_add(d, S_T_SWEEPS, (unsigned long long)b_sw, blockIdx.x);
+        stat_add(d, S_T_SOLVED, (unsigned long long)nsolved, blockIdx.x);
+        stat_add(d, S_T_SFALL, (unsigned long long)nfall, blockIdx.x);
     }
 }
 
@@ -2353,6 +2705,8 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->abytes_lane = s_sum[S_ABYTES_LANE];
         d.cnt->abytes_wide = s_sum[S_ABYTES_WIDE];
         d.cnt->abytes_chain = s_sum[S_ABYTES_CHAIN];
+        d.cnt->solve_bytes = s_sum[S_SBYTES];
+        d.cnt->abytes_solve = s_sum[S_ABYTES_SOLVE];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
         for (int q = 0; q < S_NUM; q++) d.cnt->trace[q] = s_sum[q];
@@ -2417,6 +2771,8 @@ pms_status set_err(Ctx *c, pms_status s, const std::string &msg)
 static std::string bad_source_text(const Counters &h)
 {
     if (h.bad_source == 1) return "internal: a column was added a column to its right";
+    if (h.bad_source == 4)
+        return "internal: k_chain_solve would add a pivot right of column " + std::to_string(h.bad_info[0]);
     std::string m = "internal: a chained addition did not lower the low (";
     if (h.bad_source == 2)
         m += "k_chain: column " + std::to_string(h.bad_info[0]) + ", low " + std::to_string(h.bad_info[1]) +
@@ -2572,7 +2928,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t *keep2 = (int32_t *)S.get(B_FLAGS, (nblk + 1) * 4);
     d.cq_slice = (nblk + kPart - 1) / kPart * kBlock;  // a slice takes every kPart-th tile
     d.cq = (int32_t *)S.get(B_TMP0, (size_t)kPart * d.cq_slice * 4);
-    d.cq_n = (int32_t *)S.get(B_CQN, (kPart + 2) * 32 * 4);
+    d.cq_n = (int32_t *)S.get(B_CQN, (kPart + 3) * 32 * 4);
     d.wq = (int32_t *)S.get(B_WQ, (size_t)m * 4);
     d.wq2 = (int32_t *)S.get(B_WQ2, (size_t)m * 4);
     d.stats = (unsigned long long *)S.get(B_STATS, (size_t)S_NUM * kStripe * 16 * 8);
@@ -2714,7 +3070,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
     unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0, wide_bytes_prev = 0;
-    unsigned long long ab_prev[4] = {0, 0, 0, 0};
+    unsigned long long solve_bytes_prev = 0;
+    unsigned long long ab_prev[5] = {0, 0, 0, 0, 0};
     const char *tr_env = getenv("PMS_TRACE");
     const int trace = tr_env && tr_env[0] == '1';
     unsigned long long tprev[S_NUM] = {};
@@ -2724,7 +3081,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // The kernels read the round's active count and number from the device
     // (they loop over tiles), so `grid_tiles` only bounds their grids: the
     // exact tile count when the host knows it, a fixed size in a graph.
-    size_t xor_slot = 0, lane_slot = 0, wide_slot = 0, chain_slot = 0;
+    size_t xor_slot = 0, lane_slot = 0, wide_slot = 0, chain_slot = 0, solve_slot = 0;
     const pms_tuning tn = c->tune;
     auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
         const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
@@ -2780,10 +3137,18 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                        opt->compression, tn);
         wide_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
+        if (tn.solve > 0) {  // few handed-over columns: by sweeps; what does not fit, serially
+            PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve, (unsigned)tn.chain_blocks, kSolveThreads, d, opt->compression,
+                       tn.solve);
+            solve_slot = c->pend.size() - 1;
+            if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
+        }
         if (trace)
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression,
+                       tn.solve);
         else
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression,
+                       tn.solve);
         chain_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep, -1);
@@ -2989,9 +3354,15 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             lane_bytes_prev = h->lane_bytes;
             c->pend[wide_slot].bytes = (double)(h->wide_bytes - wide_bytes_prev);
             wide_bytes_prev = h->wide_bytes;
-            const unsigned long long abn[4] = {h->abytes_xor, h->abytes_lane, h->abytes_wide, h->abytes_chain};
-            const size_t slots[4] = {xor_slot, lane_slot, wide_slot, chain_slot};
-            for (int q = 0; q < 4; q++) {
+            const unsigned long long abn[5] = {h->abytes_xor, h->abytes_lane, h->abytes_wide, h->abytes_chain,
+                                               h->abytes_solve};
+            const size_t slots[5] = {xor_slot, lane_slot, wide_slot, chain_slot, solve_slot};
+            const int nslots = tn.solve > 0 ? 5 : 4;
+            if (tn.solve > 0) {
+                c->pend[solve_slot].bytes = (double)(h->solve_bytes - solve_bytes_prev);
+                solve_bytes_prev = h->solve_bytes;
+            }
+            for (int q = 0; q < nslots; q++) {
                 c->pend[slots[q]].abytes = (double)(abn[q] - ab_prev[q]);
                 ab_prev[q] = abn[q];
             }
@@ -3007,7 +3378,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "%llu, chain steps short %llu long %llu global %llu, mean |W| %.1f, lows from P %llu, flushes "
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
                     "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu, toggles %llu; first lane pass: toggle rounds %llu, wave iterations %llu, refill phases %llu, "
-                    "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f\n",
+                    "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f; solve: columns %llu, "
+                    "sweeps %llu, most sweeps %d, to k_chain %llu\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
@@ -3016,7 +3388,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     (double)dl[S_T_LSUML] / (double)(dl[S_T_LANE] ? dl[S_T_LANE] : 1), dl[S_T_LGT16], dl[S_T_LGT32], dl[S_T_LLONG], dl[S_T_LTOG], dl[S_T_LTROUND],
                     dl[S_T_LITER], dl[S_T_LREFILL], dl[S_T_LFLUSH],
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
-                    (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1));
+                    (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1), dl[S_T_SOLVED],
+                    dl[S_T_SWEEPS], h->max_sweeps, dl[S_T_SFALL]);
         }
         if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
         {
@@ -3049,7 +3422,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     res->additions = (int64_t)h->additions;
     res->xor_entries = (int64_t)h->xor_entries;
     res->active_sum = (int64_t)h->active_sum;
-    res->addition_bytes = (int64_t)(h->abytes_xor + h->abytes_lane + h->abytes_wide + h->abytes_chain);
+    res->addition_bytes =
+        (int64_t)(h->abytes_xor + h->abytes_lane + h->abytes_wide + h->abytes_chain + h->abytes_solve);
     res->phase0_pivots = h->beta_pivots;
 
     // pairs and essential simplices, canonical order
@@ -3214,7 +3588,8 @@ void pms_destroy(pms_ctx *c)
 static const char *const kKernelNames[pms::K_NUM] = {
     "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
     "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
-    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide", "k_c8", "k_budget"};
+    "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide", "k_c8", "k_budget",
+    "k_chain_solve"};
 
 pms_status pms_profile_enable(pms_ctx *c, int enable)
 {

@@ -15,10 +15,10 @@ def test_tuning_layout_defaults_and_null_handles():
     assert ctypes.sizeof(_binding.PmsTuning) == 40
     t = lib.pms_default_tuning()
     assert (t.lane_blocks, t.chain_blocks, t.lane_steps, t.lane_steps_few, t.lane_many, t.lane_refill,
-            t.lane_flush, t.wide_blocks, t.lane_cap, t.reserved) == (2048, 512, 128, 0, 65536, 32, 16, 2048, 39, 0)
+            t.lane_flush, t.wide_blocks, t.lane_cap, t.solve) == (2048, 512, 128, 0, 65536, 32, 16, 2048, 39, 512)
     assert api.default_tuning() == dict(lane_blocks=2048, chain_blocks=512, lane_steps=128, lane_steps_few=0,
                                         lane_many=65536, lane_refill=32, lane_flush=16, wide_blocks=2048,
-                                        lane_cap=39)
+                                        lane_cap=39, solve=512)
     assert lib.pms_set_tuning(None, None) == _binding.PMS_ERR_INVALID_ARG
     assert lib.pms_get_tuning(None, None) == _binding.PMS_ERR_INVALID_ARG
     assert lib.pms_autotune(None, None, 0, None, None, 0, None, None, None) == _binding.PMS_ERR_INVALID_ARG
@@ -28,7 +28,7 @@ def test_tuning_struct_overlays_the_builtin_values():
     t = api._tuning_struct(dict(lane_steps=7, lane_flush=3))
     assert (t.lane_steps, t.lane_flush, t.lane_blocks, t.wide_blocks) == (7, 3, 2048, 2048)
     with pytest.raises(KeyError):
-        api._tuning_struct(dict(reserved=1))
+        api._tuning_struct(dict(reserved=0))
 
 
 def test_size_class_buckets():

@@ -228,18 +228,29 @@ def _long_pivot_matrix(seed):
     return cp, rows
 
 
-def test_long_pivots_global_paths(gpu, capfd, monkeypatch):
-    """The wavefront chain kernel's paths for columns and pivots too long for
-    LDS (a long pivot merged in global memory, and the working column flushed
-    to the arena) give the oracle's low*; the kernel's trace counters show
-    that the global-memory merge ran."""
+@pytest.mark.parametrize("solve", [0, 1 << 30])
+def test_long_pivots_global_paths(gpu, capfd, monkeypatch, solve):
+    """With the sweep kernel off, the wavefront chain kernel's paths for
+    columns and pivots too long for LDS (a long pivot merged in global memory,
+    and the working column flushed to the arena) give the oracle's low*; the
+    kernel's trace counters show that the global-memory merge ran.  With it
+    on, the same chains (long pivots read from their columns) are solved by
+    sweeps or handed on, with the same low*."""
     monkeypatch.setenv("PMS_TRACE", "1")
-    for seed in (1, 2):
-        cp, rows = _long_pivot_matrix(seed)
-        ref = oracle.reduce_standard(cp, rows)
-        for kw in (dict(), dict(compression=False), dict(variant=1)):
-            res = _reduce(cp, rows, None, gpu, validate=False, tail_active=1 << 30, **kw)
-            _check(res, ref)
+    api.set_tuning(dict(solve=solve), device=gpu)
+    try:
+        for seed in (1, 2):
+            cp, rows = _long_pivot_matrix(seed)
+            ref = oracle.reduce_standard(cp, rows)
+            for kw in (dict(), dict(compression=False), dict(variant=1)):
+                res = _reduce(cp, rows, None, gpu, validate=False, tail_active=1 << 30, **kw)
+                _check(res, ref)
+    finally:
+        api.set_tuning(None, device=gpu)
     err = capfd.readouterr().err
-    glob = [int(x) for x in __import__("re").findall(r"global (\d+)", err)]
-    assert glob and sum(glob) > 0, err[-2000:]
+    if solve == 0:
+        glob = [int(x) for x in __import__("re").findall(r"global (\d+)", err)]
+        assert glob and sum(glob) > 0, err[-2000:]
+    else:
+        solved = [int(x) for x in __import__("re").findall(r"solve: columns (\d+)", err)]
+        assert solved and sum(solved) > 0, err[-2000:]

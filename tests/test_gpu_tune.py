@@ -24,6 +24,11 @@ SETTINGS = [
     dict(lane_blocks=65535, chain_blocks=4096, lane_steps=3, lane_steps_few=1),
     dict(lane_cap=4),                          # most columns go through the wide pass
     dict(lane_cap=0, wide_blocks=2, lane_refill=1),  # every column does
+    dict(solve=0),                             # handed-over chains walked by wavefronts, not solved by sweeps
+    dict(solve=0, lane_steps=0, lane_steps_few=0),
+    dict(lane_steps=0, lane_steps_few=0, chain_blocks=1),  # one workgroup solves every chain
+    dict(solve=1 << 30, lane_steps=1, lane_steps_few=1),   # sweeps at any queue length
+    dict(solve=1),                             # sweeps only in rounds that hand on one column
 ]
 
 
@@ -107,16 +112,12 @@ def test_invalid_settings_are_rejected_and_change_nothing(gpu, builtin_after):
     for bad in (dict(lane_refill=0), dict(lane_refill=65), dict(lane_flush=0), dict(lane_flush=65),
                 dict(lane_blocks=0), dict(lane_blocks=65536), dict(chain_blocks=0), dict(chain_blocks=65536),
                 dict(lane_steps=-1), dict(lane_steps_few=(1 << 30) + 1), dict(lane_many=-1),
-                dict(wide_blocks=0), dict(wide_blocks=65536), dict(lane_cap=-1), dict(lane_cap=40)):
+                dict(wide_blocks=0), dict(wide_blocks=65536), dict(lane_cap=-1), dict(lane_cap=40),
+                dict(solve=-1), dict(solve=(1 << 30) + 1)):
         with pytest.raises(_binding.PmsError) as e:
             api.set_tuning(bad, device=gpu)
         assert e.value.status == _binding.PMS_ERR_INVALID_ARG, bad
         assert api.get_tuning(device=gpu) == want
-    t = _binding.load().pms_default_tuning()
-    t.reserved = 1
-    ctx = api._ctx(gpu)
-    assert _binding.load().pms_set_tuning(ctx, t) == _binding.PMS_ERR_INVALID_ARG
-    assert api.get_tuning(device=gpu) == want
     with pytest.raises(KeyError):
         api.set_tuning(dict(lane_width=3), device=gpu)
 
