@@ -291,18 +291,20 @@ __device__ inline I4 wave_incl_max4(I4 x)
     return x;
 }
 
-// Block-wide exclusive sum over kBlock threads; *total receives the sum.
+// Block-wide exclusive sum over kThreads threads; *total receives the sum.
 // Must be reached by every thread of the block.
+template <int kThreads = kBlock>
 __device__ inline int32_t block_excl_sum32(int32_t v, int32_t *total)
 {
-    __shared__ int32_t s_w[kWavesPerBlock];
+    constexpr int kW = kThreads / kWave;
+    __shared__ int32_t s_w[kW];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int32_t inc = wave_incl_sum32(v);
     if (lane == kWave - 1) s_w[wid] = inc;
     __syncthreads();
     int32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWavesPerBlock; w++) {
+    for (int w = 0; w < kW; w++) {
         int32_t t = s_w[w];
         if (w < wid) pre += t;
         tot += t;
@@ -327,16 +329,18 @@ __device__ inline int64_t block_excl_sum64(int64_t v)
     return pre + inc - v;
 }
 
+template <int kThreads = kBlock>
 __device__ inline int64_t block_sum64(int64_t v)
 {
-    __shared__ int64_t s_w64[kWavesPerBlock];
+    constexpr int kW = kThreads / kWave;
+    __shared__ int64_t s_w64[kW];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int64_t inc = wave_incl_sum64(v);
     if (lane == kWave - 1) s_w64[wid] = inc;
     __syncthreads();
     int64_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWavesPerBlock; w++) tot += s_w64[w];
+    for (int w = 0; w < kW; w++) tot += s_w64[w];
     __syncthreads();
     return tot;
 }

@@ -71,6 +71,9 @@ enum StatId {
     // k_chain_solve: algorithmic bytes, bytes of its additions as multi-way sums, sweeps,
     // columns solved, columns handed to k_chain
     S_SBYTES, S_ABYTES_SOLVE, S_T_SWEEPS, S_T_SOLVED, S_T_SFALL,
+    // trace of k_chain_solve: shader cycles in set-up, the two passes, the toggles and the
+    // write-back (thread 0, summed over columns), membership changes
+    S_T_SINIT, S_T_SA, S_T_SB, S_T_SC, S_T_SOUT, S_T_SDELTA, S_T_SLONG, S_T_SLONGE,
     S_NUM
 };
 
@@ -105,6 +108,7 @@ struct Counters {
     int32_t bad_source;  // internal invariant broken (never expected)
     int32_t max_chain;   // trace: most additions one column made in k_chain this round
     int32_t max_sweeps;  // most sweeps one column took in k_chain_solve this round
+    int32_t max_solve_us;  // trace: longest time one column took in k_chain_solve this round (us)
     int32_t n_cur;       // active columns of the current round (read by the round kernels)
     uint32_t round;      // rounds that did work so far
     int32_t dbg_flags;   // debug_invariants: the invariants found broken (DbgBit)
@@ -429,7 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
     const int32_t nA = d.cnt->n_cur;
     const uint32_t round = d.cnt->round;
     if (blockIdx.x == 0 && threadIdx.x <= kPart + 2) d.cq_n[threadIdx.x * 32] = 0;  // the chain queues start empty
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = d.cnt->max_sweeps = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt->max_chain = d.cnt->max_sweeps = d.cnt->max_solve_us = 0;
     const int64_t tiles = ((int64_t)nA + kBlock - 1) / kBlock;
     const XcdSplit xs = xcd_split(tiles);
     for (int64_t tile = xs.first; tile < xs.end; tile += xs.step) {
@@ -1950,117 +1954,162 @@ __global__ void __launch_bounds__(kChainWaves *kWave) k_chain(Dev d, int compres
 // dependent addition per step: thousands on the longest columns of a 64^3
 // lower-star filtration, whose dependency paths are 10 to 80 rows long.
 //
-// One workgroup per column.  The rows the column touches live in an LDS hash
-// table (row -> flags, one byte per slot); a sweep is a pass that finds L, a
-// pass that flips the membership of the rows whose test changed (into a
-// list), and a pass that toggles the entries of those rows' pivots (from
-// their records, one load each) into the table.  The head of each entry's
-// own record (pivot, length) is loaded before it is toggled: rows known to
-// be negative are left out (compression deletes them), and a new row enters
-// the table with its flags.  The result is written back sorted.  A column
-// whose rows would overfill the table goes to k_chain.
-constexpr int kSolveThreads = 256;
-constexpr int kSolveH = 12288;                    // hash slots
-constexpr int kSolveMaxU = kSolveH / 4 * 3;       // rows one column may touch
-constexpr int kSolveSort = 8192;                  // longest result (sorted in the table's first slots)
-constexpr int kSolveDelta = 2048;                 // membership changes applied per sweep
-constexpr int kSolveSweeps = 4096;                // a column still changing then goes to k_chain
-constexpr int kSolvePer = kSolveH / 4 / kSolveThreads;  // flag words (4 slots each) per thread
-static_assert(kSolveH % (4 * kSolveThreads) == 0 && kSolveSort <= kSolveH && kSolveMaxU < kSolveH,
-              "k_chain_solve's table: whole flag words per thread, the sort fits, probes end");
-// flags of a slot
+// One workgroup per column.  The rows the column touches are kept in LDS as
+// a dense list (row, one byte of flags) in the order they were met, found
+// through a hash table of list positions, so a pass costs the rows touched,
+// not the table.  A sweep is a pass that finds L, a pass that flips the
+// membership of the rows whose test changed (into a list of changes), and a
+// pass that toggles the entries of those rows' pivots (from their records,
+// one load each).  The head of each entry's own record (pivot, length) is
+// loaded before it is toggled: rows known to be negative are left out
+// (compression deletes them), and a new row enters the list with its flags.
+// The result is written back sorted.  A column whose rows overfill the list
+// goes to k_chain.
+constexpr int kSolveThreads = 512;
+constexpr int kSolveH = 8192;            // hash slots (list positions, -1 = free)
+constexpr int kSolveMaxU = 6144;         // rows one column may touch (list length)
+constexpr int kSolveDelta = 2048;        // membership changes applied per sweep
+constexpr int kSolveSweeps = 4096;       // a column still changing then goes to k_chain
+constexpr int kSolveB = 2;               // changed rows a thread handles at a time
+constexpr int kSolveLong = 64;           // long pivots a sweep spreads over the workgroup (more: per thread)
+constexpr int kSolvePer = kSolveMaxU / 4 / kSolveThreads;  // flag words (4 rows each) per thread
+static_assert(kSolveMaxU % (4 * kSolveThreads) == 0 && kSolveMaxU < kSolveH && (kSolveH & (kSolveH - 1)) == 0,
+              "k_chain_solve: whole flag words per thread; probes always end; the result sorts in the table");
+// flags of a row
 constexpr uint32_t kSV = 1;   // v(r)
 constexpr uint32_t kSX = 2;   // r is in S
 constexpr uint32_t kSP = 4;   // r has a known pivot
-constexpr uint32_t kSN = 8;   // r is known negative (deleted by compression)
-constexpr uint32_t kSR = 16;  // r's pivot lies right of column j (never expected in S)
+constexpr uint32_t kSR = 8;   // r's pivot lies right of column j (never expected in S)
+
+struct SolveLds {
+    int32_t *hk;       // hash slot -> list position
+    int32_t *key;      // list position -> row
+    uint32_t *flag;    // flags, byte (position & 3) of word position / 4
+    int32_t *n;        // list length (positions handed out)
+    int32_t *fail;
+};
 
 __device__ inline uint32_t solve_hash(int32_t r)
 {
-    return (uint32_t)(((uint64_t)((uint32_t)r * 2654435761u) * kSolveH) >> 32);
+    return ((uint32_t)r * 2654435761u) >> 19;  // 13 bits: kSolveH slots
 }
 
-// Toggles v(e), inserting row e with flags fl when it is new.  The table
-// holds at most kSolveMaxU rows (probes always find a free slot); past that
-// *fail is set and the column goes to the serial kernel.
-__device__ inline void solve_toggle(int32_t *hk, uint32_t *hf, int32_t *nu, int32_t *fail, int32_t e, uint32_t fl)
+// Toggles v(e), appending row e with flags fl when it is new.  A full list
+// sets *fail (the column then goes to the serial kernel).  A new row's list
+// entry is written before its position is published in the hash table, so a
+// thread that finds the position finds the row: LDS performs one wave's
+// operations in issue order, so only the compiler must keep them in order
+// (a fence would also wait for this thread's global loads in flight).
+__device__ inline void solve_toggle(const SolveLds &t, int32_t e, uint32_t fl)
 {
     uint32_t h = solve_hash(e);
+    int32_t mine = -1;
     for (;;) {
-        const int32_t k = __hip_atomic_load(&hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == e) break;
-        if (k < 0) {
-            if (atomicAdd(nu, 1) >= kSolveMaxU) {
-                atomicExch(fail, 1);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int32_t x = __hip_atomic_load(&t.hk[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (x >= 0) {
+            if (t.key[x] == e) {
+                if (mine >= 0) t.key[mine] = -1;  // reserved for nothing: a dead entry (flags 0)
+                atomicXor(&t.flag[x >> 2], kSV << (8 * (x & 3)));
                 return;
             }
-            const int32_t old = atomicCAS(&hk[h], -1, e);
-            if (old == -1) {
-                fl |= kSV;  // with the toggle below, one atomic
-                atomicXor(&hf[h >> 2], fl << (8 * (h & 3)));
-                return;
-            }
-            atomicSub(nu, 1);
-            if (old == e) break;
+            h = (h + 1) & (kSolveH - 1);
+            continue;
         }
-        h = h + 1 == (uint32_t)kSolveH ? 0 : h + 1;
+        if (mine < 0) {
+            mine = atomicAdd(t.n, 1);
+            if (mine >= kSolveMaxU) {
+                atomicExch(t.fail, 1);
+                return;
+            }
+            t.key[mine] = e;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int32_t old = atomicCAS(&t.hk[h], -1, mine);
+        if (old == -1) {
+            atomicXor(&t.flag[mine >> 2], (fl | kSV) << (8 * (mine & 3)));
+            return;
+        }
+        // the slot was taken meanwhile: look at it again
     }
-    atomicXor(&hf[h >> 2], kSV << (8 * (h & 3)));
 }
 
-// Flags of row r from the head of its record (pivot, length).
+// Flags of a row from the head of its record (pivot, length); kSolveNeg for a
+// row known to be negative.
+constexpr uint32_t kSolveNeg = 0x80000000u;
 __device__ inline uint32_t solve_flags(int2 head, int32_t j, int compression)
 {
     if (head.x >= 0) return head.x < j ? kSP : (kSP | kSR);
-    return (compression && head.y < 0) ? kSN : 0u;
+    return (compression && head.y < 0) ? kSolveNeg : 0u;
 }
 
 // Toggles up to kN rows: the heads of their records are loaded together
 // first; known-negative rows are skipped.
 template <int kN>
-__device__ inline void solve_toggle_n(const Dev &d, int32_t *hk, uint32_t *hf, int32_t *nu, int32_t *fail,
-                                      const int32_t (&rows)[kN], int32_t n, int32_t j, int compression)
+__device__ inline void solve_toggle_n(const Dev &d, const SolveLds &t, const int32_t (&rows)[kN], int32_t n,
+                                      int32_t j, int compression)
 {
-    int2 head[kN];
+    int2 head[kN];  // loaded unconditionally (row 0 for the unused ones): one wait for all
 #pragma unroll
-    for (int u = 0; u < kN; u++)
-        head[u] = u < n ? *reinterpret_cast<const int2 *>(&d.prec[rows[u]]) : make_int2(-1, 0);
+    for (int u = 0; u < kN; u++) head[u] = *reinterpret_cast<const int2 *>(&d.prec[u < n ? rows[u] : 0]);
 #pragma unroll
     for (int u = 0; u < kN; u++) {
         const uint32_t fl = solve_flags(head[u], j, compression);
-        if (u < n && !(fl & kSN)) solve_toggle(hk, hf, nu, fail, rows[u], fl);
+        if (u < n && fl != kSolveNeg) solve_toggle(t, rows[u], fl);
     }
 }
 
 // The kernel takes the handed-over columns when there are at most solve_max
 // of them (a round of few, long chains, bound by its longest one); more
 // columns are walked by k_chain, whose waves hold more columns per CU.
+template <bool kTrace>
 __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compression, int32_t solve_max)
 {
-    __shared__ int32_t hk[kSolveH];       // row of each slot, -1 = free; reused to sort the result
-    __shared__ uint32_t hf[kSolveH / 4];  // flags, byte (slot & 3) of word slot / 4
-    __shared__ int32_t dl[kSolveDelta];   // this sweep's changes of S: r (joins) or ~r (leaves)
-    __shared__ int32_t s_nu, s_fail, s_bad, s_L[2], s_nd[2];
+    __shared__ __align__(16) int32_t hk[kSolveH];        // hash table; then the result, sorted
+    __shared__ __align__(16) int32_t key[kSolveMaxU];    // the rows touched, in the order met (-1: dead)
+    __shared__ uint32_t flag[kSolveMaxU / 4];            // their flags, 4 per word
+    __shared__ int32_t dl[kSolveDelta];                  // this sweep's changes of S: r (joins) or ~r (leaves)
+    __shared__ int32_t s_n, s_fail, s_bad, s_L[2], s_nd[2];
     __shared__ long long s_o;
+    __shared__ long long s_loff[kSolveLong];  // this sweep's long pivots: stored column, entries below the low
+    __shared__ int32_t s_lpre[kSolveLong + 1], s_nl;
+    const SolveLds t{hk, key, flag, &s_n, &s_fail};
+    const int4 *key4 = reinterpret_cast<const int4 *>(key);
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int32_t total = d.cq_n[kPart * 32];  // columns the lane passes handed over
     if (total > solve_max) return;             // k_chain takes them all
-    int64_t adds = 0, pk = 0, by = 0, ab = 0, sweeps = 0;  // pk: entries of the added pivots
+    int64_t adds = 0, pk = 0, by = 0, ab = 0, sweeps = 0;  // pk: entries read (column and added pivots)
     int32_t nsolved = 0, nfall = 0;
-    for (int32_t t = (int32_t)blockIdx.x; t < total; t += (int32_t)gridDim.x) {
-        __syncthreads();  // the previous column's last reads of the table and counters are done
-        const int32_t j = d.wq[t];
+    // trace: set-up, pass A, pass B, toggles, out cycles; changes; long pivots, their entries
+    unsigned long long tr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long c0 = 0;
+    auto tick = [&](int q) {
+        if (kTrace) {
+            const long long c1 = clock64();
+            tr[q] += (unsigned long long)(c1 - c0);
+            c0 = c1;
+        }
+    };
+    auto hand_on = [&](int32_t j) {
+        if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
+        nfall++;
+    };
+    for (int32_t q0 = (int32_t)blockIdx.x; q0 < total; q0 += (int32_t)gridDim.x) {
+        __syncthreads();  // the previous column's last reads of LDS are done
+        const int32_t j = d.wq[q0];
         const int32_t L0 = d.len[j];
         const int32_t *g = col_base(d, d.off[j]);
         if (L0 > kSolveMaxU / 2) {
-            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
-            nfall++;
+            hand_on(j);
             continue;
         }
-        for (int a = tid; a < kSolveH; a += kSolveThreads) hk[a] = -1;
-        for (int a = tid; a < kSolveH / 4; a += kSolveThreads) hf[a] = 0;
+        if (kTrace) c0 = clock64();
+        const long long w0 = kTrace ? wall_clock64() : 0;
+        for (int a = tid; a < kSolveH / 4; a += kSolveThreads) reinterpret_cast<int4 *>(hk)[a] = make_int4(-1, -1, -1, -1);
+        for (int a = tid; a < kSolveMaxU / 4; a += kSolveThreads) flag[a] = 0;
         if (tid == 0) {
-            s_nu = 0;
+            s_n = 0;
             s_fail = 0;
             s_bad = 0;
             s_L[0] = s_L[1] = 0;
@@ -2077,51 +2126,74 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                 rows[u] = a < L0 ? g[a] : -1;
                 n += a < L0 ? 1 : 0;
             }
-            solve_toggle_n<4>(d, hk, hf, &s_nu, &s_fail, rows, n, j, compression);
+            solve_toggle_n<4>(d, t, rows, n, j, compression);
         }
         __syncthreads();
+        tick(0);
         bool ok = false;
         int64_t cxe = 0;  // entries of the pivots in S (this thread's share)
         for (int it = 0;; it++) {
             const int p = it & 1;
+            const int32_t nwords = (min(s_n, kSolveMaxU) + 3) >> 2;
+            // this thread's rows, read once for both passes (nothing writes them in between)
+            uint32_t fw[kSolvePer];
+            int32_t kw[kSolvePer][4];
+#pragma unroll
+            for (int u = 0; u < kSolvePer; u++) {
+                const int w = u * kSolveThreads + tid;
+                fw[u] = 0;
+                kw[u][0] = kw[u][1] = kw[u][2] = kw[u][3] = -1;
+                if (w < nwords) {
+                    fw[u] = flag[w];
+                    const int4 k4 = key4[w];
+                    kw[u][0] = k4.x;
+                    kw[u][1] = k4.y;
+                    kw[u][2] = k4.z;
+                    kw[u][3] = k4.w;
+                }
+            }
             // L + 1 (0: no row with v = 1 lacks a pivot)
             int32_t lm = 0;
 #pragma unroll
-            for (int u = 0; u < kSolvePer; u++) {
-                const int w = u * kSolveThreads + tid;
-                const uint32_t f = hf[w];
+            for (int u = 0; u < kSolvePer; u++)
 #pragma unroll
                 for (int b = 0; b < 4; b++)
-                    if (((f >> (8 * b)) & (kSV | kSP | kSN)) == kSV) lm = max(lm, hk[4 * w + b] + 1);
-            }
+                    lm = ((fw[u] >> (8 * b)) & (kSV | kSP)) == kSV ? max(lm, kw[u][b] + 1) : lm;
             lm = wave_max_dpp(lm);
             if (lane == 0 && lm > 0) atomicMax(&s_L[p], lm);
             __syncthreads();
+            tick(1);
             const int32_t Lp1 = s_L[p];
             // the membership test; at most kSolveDelta changes a sweep (the rest wait for the next)
+            uint32_t chg = 0;  // bit 4u + b: row b of word u changes
 #pragma unroll
-            for (int u = 0; u < kSolvePer; u++) {
-                const int w = u * kSolveThreads + tid;
-                const uint32_t f = hf[w];
-                uint32_t nf = f;
+            for (int u = 0; u < kSolvePer; u++)
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    const uint32_t fb = f >> (8 * b);
-                    if (!(fb & (kSV | kSX))) continue;
-                    const int32_t r = hk[4 * w + b];
-                    const bool want = (fb & (kSV | kSP | kSN)) == (kSV | kSP) && r >= Lp1;
-                    if (want != ((fb & kSX) != 0)) {
-                        const int32_t q = atomicAdd(&s_nd[p], 1);
-                        if (q < kSolveDelta) {
-                            dl[q] = want ? r : ~r;
-                            nf ^= kSX << (8 * b);
-                        }
-                    }
+                    const uint32_t fb = fw[u] >> (8 * b);
+                    const bool want = (fb & (kSV | kSP)) == (kSV | kSP) && kw[u][b] >= Lp1;
+                    chg |= (uint32_t)(want != ((fb & kSX) != 0)) << (4 * u + b);
                 }
-                if (nf != f) hf[w] = nf;
+            if (tid == 0) s_nl = 0;
+            if (chg) {
+                int32_t q = atomicAdd(&s_nd[p], __popc(chg));
+                while (chg) {
+                    const int i = __builtin_ctz(chg);
+                    chg &= chg - 1;
+                    const int w = (i >> 2) * kSolveThreads + tid, b = i & 3;
+                    if (q < kSolveDelta) {
+                        const int32_t r = key[4 * w + b];
+                        const bool has = ((flag[w] >> (8 * b)) & kSX) != 0;  // it leaves S, else joins
+                        dl[q] = has ? ~r : r;
+                        flag[w] ^= kSX << (8 * b);  // this thread's word: no other writer in this pass
+                    }
+                    q++;
+                }
             }
             __syncthreads();
+            tick(2);
             const int32_t nd = min(s_nd[p], kSolveDelta);
+            tr[5] += kTrace ? nd : 0;
             if (s_fail || nd == 0 || it >= kSolveSweeps) {
                 ok = !s_fail && nd == 0;
                 sweeps += it;
@@ -2132,68 +2204,125 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                 s_L[p ^ 1] = 0;
                 s_nd[p ^ 1] = 0;
             }
-            // toggle the entries of the changed rows' pivots
-            for (int32_t q = tid; q < nd; q += kSolveThreads) {
-                const int32_t code = dl[q];
-                const int32_t r = code >= 0 ? code : ~code;
-                const PivRec rec = d.prec[r];
-                const int32_t k = rec.k;  // the pivot's length, its low r included
-                cxe += code >= 0 ? k : -k;
-                by += 32;
-                if (k - 1 <= kRecInline) {
-                    const int32_t rows[kRecInline] = {rec.e[0], rec.e[1], rec.e[2], rec.e[3], rec.e[4], rec.e[5]};
-                    solve_toggle_n<kRecInline>(d, hk, hf, &s_nu, &s_fail, rows, k - 1, j, compression);
-                } else {
-                    const int32_t *pc = col_base(d, d.off[rec.s]);
-                    by += 12 + 4 * (int64_t)k;
-                    for (int32_t a0 = 0; a0 < k - 1; a0 += 4) {
-                        int32_t rows[4];
-                        int32_t n = 0;
+            // toggle the entries of the changed rows' pivots: kSolveB changed rows per
+            // thread at a time, their records loaded together, then the heads of
+            // all their entries together (two memory latencies per batch)
+            for (int32_t q0 = tid; q0 < nd; q0 += kSolveThreads * kSolveB) {
+                // loads are unconditional (row 0 stands in for unused ones), so each
+                // group waits once
+                PivRec rec[kSolveB];
+                int32_t sign[kSolveB];
 #pragma unroll
-                        for (int u = 0; u < 4; u++) {
-                            rows[u] = a0 + u < k - 1 ? pc[a0 + u] : -1;
-                            n += a0 + u < k - 1 ? 1 : 0;
+                for (int v = 0; v < kSolveB; v++) {
+                    const int32_t q = q0 + v * kSolveThreads;
+                    const int32_t code = q < nd ? dl[q] : 0;
+                    sign[v] = q < nd ? (code >= 0 ? 1 : -1) : 0;
+                    rec[v] = d.prec[code >= 0 ? code : ~code];
+                }
+                int32_t kv[kSolveB];
+                int2 head[kSolveB][kRecInline];
+#pragma unroll
+                for (int v = 0; v < kSolveB; v++) {
+                    kv[v] = sign[v] ? rec[v].k : 1;  // the pivot's length, its low included
+                    cxe += sign[v] * kv[v];
+                    by += sign[v] ? 32 : 0;
+#pragma unroll
+                    for (int u = 0; u < kRecInline; u++) {
+                        const bool use = u < kv[v] - 1 && kv[v] - 1 <= kRecInline;
+                        head[v][u] = *reinterpret_cast<const int2 *>(&d.prec[use ? rec[v].e[u] : 0]);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < kSolveB; v++) {
+                    const int32_t k = kv[v];
+                    if (k - 1 <= kRecInline) {
+#pragma unroll
+                        for (int u = 0; u < kRecInline; u++) {
+                            const uint32_t fl = solve_flags(head[v][u], j, compression);
+                            if (u < k - 1 && fl != kSolveNeg) solve_toggle(t, rec[v].e[u], fl);
                         }
-                        solve_toggle_n<4>(d, hk, hf, &s_nu, &s_fail, rows, n, j, compression);
+                    } else {  // a long pivot: its entries from its stored column
+                        const int64_t off = d.off[rec[v].s];
+                        by += 12 + 4 * (int64_t)k;
+                        if (kTrace) {
+                            tr[6]++;
+                            tr[7] += k - 1;
+                        }
+                        const int32_t li = atomicAdd(&s_nl, 1);
+                        if (li < kSolveLong) {  // the workgroup toggles its entries below
+                            s_loff[li] = off;
+                            s_lpre[li + 1] = k - 1;
+                            continue;
+                        }
+                        const int32_t *pc = col_base(d, off);
+                        for (int32_t a0 = 0; a0 < k - 1; a0 += 4) {
+                            int32_t rows[4];
+                            int32_t n = 0;
+#pragma unroll
+                            for (int u = 0; u < 4; u++) {
+                                rows[u] = a0 + u < k - 1 ? pc[a0 + u] : -1;
+                                n += a0 + u < k - 1 ? 1 : 0;
+                            }
+                            solve_toggle_n<4>(d, t, rows, n, j, compression);
+                        }
                     }
                 }
             }
             __syncthreads();
+            const int32_t nl = min(s_nl, kSolveLong);
+            if (nl > 0) {  // the long pivots' entries, spread over every thread
+                if (tid < kWave) {
+                    const int32_t c = tid < nl ? s_lpre[tid + 1] : 0;
+                    const int32_t incl = wave_incl_sum32(c);
+                    if (tid < nl) s_lpre[tid + 1] = incl;
+                    if (tid == 0) s_lpre[0] = 0;
+                }
+                __syncthreads();
+                const int32_t tot = s_lpre[nl];
+                for (int32_t e0 = tid; e0 < tot; e0 += 4 * kSolveThreads) {
+                    int32_t rows[4];
+                    int32_t n = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int32_t ei = e0 + u * kSolveThreads;
+                        const int32_t ec = min(ei, tot - 1);  // loaded unconditionally: one wait
+                        int32_t lo = 0, hi = nl - 1;          // the pivot whose entries hold ec
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi + 1) >> 1;
+                            if (s_lpre[mid] <= ec) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        rows[u] = col_base(d, s_loff[lo])[ec - s_lpre[lo]];
+                        n += ei < tot ? 1 : 0;
+                    }
+                    solve_toggle_n<4>(d, t, rows, n, j, compression);
+                }
+                __syncthreads();
+            }
+            tick(3);
         }
         if (!ok) {
-            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
-            nfall++;
+            hand_on(j);
             continue;
         }
-        nsolved++;
-        // the result: the rows with v = 1 outside S (and not deleted), sorted
-        int32_t keys[kSolvePer * 4];
+        // the result: the rows with v = 1 outside S, sorted
+        const int32_t nwords = (min(s_n, kSolveMaxU) + 3) >> 2;
         int32_t nw = 0, ns = 0;
         bool bad = false;
-#pragma unroll
-        for (int u = 0; u < kSolvePer; u++) {
-            const int w = u * kSolveThreads + tid;
-            const uint32_t f = hf[w];
+        for (int w = tid; w < nwords; w += kSolveThreads) {
+            const uint32_t f = flag[w];
 #pragma unroll
             for (int b = 0; b < 4; b++) {
                 const uint32_t fb = f >> (8 * b);
-                const bool keep = (fb & (kSV | kSX | kSN)) == kSV;
-                keys[u * 4 + b] = keep ? hk[4 * w + b] : -1;
-                nw += keep ? 1 : 0;
+                nw += (fb & (kSV | kSX)) == kSV ? 1 : 0;
                 ns += (fb & kSX) ? 1 : 0;
                 bad = bad || (fb & (kSX | kSR)) == (kSX | kSR);
             }
         }
         if (bad) s_bad = 1;
         int32_t tot_w, tot_s;
-        int32_t o = block_excl_sum32(nw, &tot_w);  // its barriers order the reads above before the writes below
-        block_excl_sum32(ns, &tot_s);
-        if (tot_w > kSolveSort) {  // too long for the sort buffer: the serial kernel redoes it
-            if (tid == 0) d.wq2[atomicAdd(&d.cq_n[(kPart + 2) * 32], 1)] = j;
-            nfall++;
-            nsolved--;
-            continue;
-        }
+        int32_t o = block_excl_sum32<kSolveThreads>(nw, &tot_w);  // its barriers end every use of the hash table
+        block_excl_sum32<kSolveThreads>(ns, &tot_s);
         if (s_bad) {  // a pivot right of the column would be added: never expected
             if (tid == 0) {
                 d.cnt->bad_info[0] = j;
@@ -2204,11 +2333,18 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
             }
             continue;
         }
-        int32_t n2 = 1;
-        while (n2 < tot_w) n2 <<= 1;
+        nsolved++;
+        pk += cxe;
+        for (int w = tid; w < nwords; w += kSolveThreads) {
+            const uint32_t f = flag[w];
+            const int4 k4 = key4[w];
+            const int32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
 #pragma unroll
-        for (int u = 0; u < kSolvePer * 4; u++)
-            if (keys[u] >= 0) hk[o++] = keys[u];
+            for (int b = 0; b < 4; b++)
+                if (((f >> (8 * b)) & (kSV | kSX)) == kSV) hk[o++] = kk[b];
+        }
+        int32_t n2 = 1;
+        while (n2 < tot_w) n2 <<= 1;  // <= kSolveMaxU rounded up <= kSolveH
         for (int32_t a = tot_w + tid; a < n2; a += kSolveThreads) hk[a] = 0x7FFFFFFF;
         __syncthreads();
         // bitonic sort of hk[0, n2)
@@ -2226,11 +2362,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                 }
                 __syncthreads();
             }
-        pk += cxe;
         if (tid == 0) {
             adds += tot_s;
             by += 4 + 12 + 4 * (int64_t)L0;  // queue entry, header, column in
-            ab += 4 * (int64_t)tot_w;  // + 4 (len c + the pivots' lengths) from pk
+            ab += 4 * (int64_t)tot_w;        // + 4 (len c + the pivots' lengths) from pk
             pk += L0;
         }
         if (tot_w == 0) {
@@ -2250,6 +2385,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
             continue;  // progress of this column is dropped; the stored column is still valid
         }
         for (int32_t a = tid; a < tot_w; a += kSolveThreads) d.arena[oa + a] = hk[a];
+        tick(4);
+        if (kTrace && tid == 0) atomicMax(&d.cnt->max_solve_us, (int32_t)((wall_clock64() - w0) / 100));  // 100 MHz
         if (tid == 0) {
             by += 4 * (int64_t)tot_w + 16;  // column and header out
             dbg_write(d, j);
@@ -2259,9 +2396,13 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
         }
     }
     // the additions' bytes as one multi-way sum: 4 (len c + the pivots' lengths + len out)
-    const int64_t b_adds = block_sum64(adds), b_xe = block_sum64(pk), b_by = block_sum64(by);
-    const int64_t b_ab = block_sum64(ab) + 4 * b_xe;
-    const int64_t b_sw = block_sum64(sweeps) / kSolveThreads;
+    const int64_t b_adds = block_sum64<kSolveThreads>(adds), b_xe = block_sum64<kSolveThreads>(pk), b_by = block_sum64<kSolveThreads>(by);
+    const int64_t b_ab = block_sum64<kSolveThreads>(ab) + 4 * b_xe;
+    const int64_t b_sw = block_sum64<kSolveThreads>(sweeps) / kSolveThreads;
+    if (kTrace) {  // per-thread counts (the cycle counts are thread 0's)
+        tr[6] = (unsigned long long)block_sum64<kSolveThreads>((int64_t)tr[6]);
+        tr[7] = (unsigned long long)block_sum64<kSolveThreads>((int64_t)tr[7]);
+    }
     if (tid == 0) {
         stat_add(d, S_ADDS, (unsigned long long)b_adds, blockIdx.x);
         stat_add(d, S_XE, (unsigned long long)b_xe, blockIdx.x);
@@ -2270,6 +2411,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
         stat_add(d, S_T_SWEEPS, (unsigned long long)b_sw, blockIdx.x);
         stat_add(d, S_T_SOLVED, (unsigned long long)nsolved, blockIdx.x);
         stat_add(d, S_T_SFALL, (unsigned long long)nfall, blockIdx.x);
+        if (kTrace)
+            for (int q = 0; q < 8; q++) stat_add(d, S_T_SINIT + q, tr[q], blockIdx.x);
     }
 }
 
@@ -3138,8 +3281,12 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         wide_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (tn.solve > 0) {  // few handed-over columns: by sweeps; what does not fit, serially
-            PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve, (unsigned)tn.chain_blocks, kSolveThreads, d, opt->compression,
-                       tn.solve);
+            if (trace)
+                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<true>, (unsigned)tn.chain_blocks, kSolveThreads, d,
+                           opt->compression, tn.solve);
+            else
+                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<false>, (unsigned)tn.chain_blocks, kSolveThreads, d,
+                           opt->compression, tn.solve);
             solve_slot = c->pend.size() - 1;
             if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         }
@@ -3379,7 +3526,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "%llu, deletions %llu, longest chain %d, cycles/short step: toggle %.0f next %.0f flush %.0f; lane steps: "
                     "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu, toggles %llu; first lane pass: toggle rounds %llu, wave iterations %llu, refill phases %llu, "
                     "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f; solve: columns %llu, "
-                    "sweeps %llu, most sweeps %d, to k_chain %llu\n",
+                    "sweeps %llu, most sweeps %d, to k_chain %llu, cycles: set-up %llu, pass A %llu, pass B %llu, "
+                    "toggles %llu, out %llu, changes %llu, longest column %d us, long pivots %llu (entries %llu)\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
@@ -3389,7 +3537,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     dl[S_T_LITER], dl[S_T_LREFILL], dl[S_T_LFLUSH],
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
                     (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1), dl[S_T_SOLVED],
-                    dl[S_T_SWEEPS], h->max_sweeps, dl[S_T_SFALL]);
+                    dl[S_T_SWEEPS], h->max_sweeps, dl[S_T_SFALL], dl[S_T_SINIT], dl[S_T_SA], dl[S_T_SB], dl[S_T_SC],
+                    dl[S_T_SOUT], dl[S_T_SDELTA], h->max_solve_us, dl[S_T_SLONG], dl[S_T_SLONGE]);
         }
         if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
         {
