@@ -699,6 +699,16 @@ def main():
                                            for k in (1, 2, 3, 4)},
                 "rounds_to_unreduced": {str(q): first(lambda r, q=q: r["unreduced"] <= q) for q in (0.5, 0.1, 0.01)}}
 
+    # how each dominant-kernel candidate's bytes are counted (the library counts them in-kernel)
+    OWN_BYTES_MODEL = {
+        "k_chain": "the bytes the kernel's own design must move: each chained column read and written once, "
+                   "one 32-byte record per chained step (plus a long pivot's column)",
+        "k_chain_solve": "the bytes the kernel's own design must move: each chained column read and written once, "
+                         "one 32-byte record per pivot that joins or leaves the added set (plus a long pivot's "
+                         "column)"}
+    ADD_BYTES_MODEL = {
+        "k_chain_solve": "4 (len c + the added pivots' lengths + len out) per chained column: its additions "
+                         "as one multi-way sum (each input read once, the result written once)"}
     roof = roof_s8d = None
     kernels = {}
     if prof:
@@ -715,14 +725,14 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
                 "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": by / n,
-                "bytes_model": "the bytes the kernel's own design must move (one record per chained step)"}
+                "bytes_model": OWN_BYTES_MODEL.get(dom, "the bytes the kernel's own design must move")}
         # the same kernel priced by the unit cost of a column addition: each
         # addition t <- t + s reads t and s and writes t + s, 4 bytes an entry
         ach2 = (ab / n) / avg_s / 1e9 if avg_s > 0 else 0.0
         roof_s8d = {"kernel": dom, "bound": "hbm", "achieved": round(ach2, 2), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach2 / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom),
                     "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": ab / n,
-                    "bytes_model": "4 (len t + len s + len t+s) per column addition"}
+                    "bytes_model": ADD_BYTES_MODEL.get(dom, "4 (len t + len s + len t+s) per column addition")}
         # the whole step's HBM traffic (rocprof FETCH+WRITE per kernel launch,
         # when the counters match these kernels) and algorithmic bytes
         alg = sum(v[2] for v in prof.values()) / args.steps
