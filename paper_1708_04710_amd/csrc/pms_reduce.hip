@@ -846,6 +846,8 @@ __global__ void __launch_bounds__(kBlock) k_bud_apply(Dev d, const int32_t *act,
 // column: most columns are a few entries long).  A column that may keep
 // adding known pivots (chaining) and whose new low has one is queued for
 // k_chain.
+constexpr int32_t kXorDefer = 128;  // merges longer than this go to the chain kernels in tail rounds
+
 __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int variant, int compression, int chain,
                                                 int tail)
 {
@@ -857,7 +859,7 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     const int64_t q = tile * kBlock + threadIdx.x;
     int32_t j = -1, s = -1, tlen = 0, slen = 0;
     int64_t toff = 0, soff = 0;
-    bool target = false;
+    bool target = false, push = false;
     if (q < nA) {
         j = act[q];
         if (d.state[j] == ST_ACTIVE && d.coll[q] == 1) {
@@ -869,6 +871,13 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
                 soff = d.off[s];
                 slen = d.len[s];
                 if (s >= j) atomicExch(&d.cnt->bad_source, 1);
+                // a long merge with the low's known pivot in a round where every
+                // column chains: it is the chain's first step, left to the chain
+                // kernels (one lane merging thousands of entries would hold the round)
+                if (chain && nA < tail && tlen + slen > kXorDefer && d.piv[d.low[j]] == s) {
+                    target = false;
+                    push = true;
+                }
             }
         }
     }
@@ -884,7 +893,6 @@ __global__ void __launch_bounds__(kBlock) k_xor(Dev d, const int32_t *act, int v
     if (threadIdx.x == 0 && bbase < 0) atomicExch(&d.cnt->overflow, 1);  // once per block: one flag for all
     if (target && bbase < 0) target = false;  // the column stays as it is this round
     int64_t adds = 0, xe = 0, by = q < nA ? 6 : 0, ab = 0;  // act, state, coll
-    bool push = false;
     if (target) {
         const int64_t dst = bbase + excl;
         int32_t *out = d.arena + dst;
