@@ -1978,7 +1978,6 @@ constexpr int kSolveH = 8192;            // hash slots (list positions, -1 = fre
 constexpr int kSolveMaxU = 6144;         // rows one column may touch (list length)
 constexpr int kSolveDelta = 2048;        // membership changes applied per sweep
 constexpr int kSolveSweeps = 4096;       // a column still changing then goes to k_chain
-constexpr int kSolveB = 2;               // changed rows a thread handles at a time
 constexpr int kSolveLong = 64;           // long pivots a sweep spreads over the workgroup (more: per thread)
 constexpr int kSolvePer = kSolveMaxU / 4 / kSolveThreads;  // flag words (4 rows each) per thread
 static_assert(kSolveMaxU % (4 * kSolveThreads) == 0 && kSolveMaxU < kSolveH && (kSolveH & (kSolveH - 1)) == 0,
@@ -2043,28 +2042,27 @@ __device__ inline void solve_toggle(const SolveLds &t, int32_t e, uint32_t fl)
     }
 }
 
-// Flags of a row from the head of its record (pivot, length); kSolveNeg for a
-// row known to be negative.
-constexpr uint32_t kSolveNeg = 0x80000000u;
-__device__ inline uint32_t solve_flags(int2 head, int32_t j, int compression)
-{
-    if (head.x >= 0) return head.x < j ? kSP : (kSP | kSR);
-    return (compression && head.y < 0) ? kSolveNeg : 0u;
-}
-
-// Toggles up to kN rows: the heads of their records are loaded together
-// first; known-negative rows are skipped.
+// Toggles the rows rows[u] with bit u of use set: each row's pivot (piv) and
+// known-negative bit (neg; both dense, so mostly cache hits) are loaded
+// together first (row 0 stands in for unused slots: the loads are
+// unconditional and the group waits once); known-negative rows are skipped.
 template <int kN>
-__device__ inline void solve_toggle_n(const Dev &d, const SolveLds &t, const int32_t (&rows)[kN], int32_t n,
+__device__ inline void solve_toggle_n(const Dev &d, const SolveLds &t, const int32_t (&rows)[kN], uint32_t use,
                                       int32_t j, int compression)
 {
-    int2 head[kN];  // loaded unconditionally (row 0 for the unused ones): one wait for all
-#pragma unroll
-    for (int u = 0; u < kN; u++) head[u] = *reinterpret_cast<const int2 *>(&d.prec[u < n ? rows[u] : 0]);
+    int32_t pv[kN];
+    uint32_t nw[kN];
 #pragma unroll
     for (int u = 0; u < kN; u++) {
-        const uint32_t fl = solve_flags(head[u], j, compression);
-        if (u < n && fl != kSolveNeg) solve_toggle(t, rows[u], fl);
+        const int32_t r = (use >> u) & 1u ? rows[u] : 0;
+        pv[u] = d.piv[r];
+        nw[u] = d.neg[r >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < kN; u++) {
+        const bool negative = compression && ((nw[u] >> (rows[u] & 31)) & 1u);
+        if (((use >> u) & 1u) && !negative)
+            solve_toggle(t, rows[u], pv[u] >= 0 ? (pv[u] < j ? kSP : (kSP | kSR)) : 0u);
     }
 }
 
@@ -2134,7 +2132,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                 rows[u] = a < L0 ? g[a] : -1;
                 n += a < L0 ? 1 : 0;
             }
-            solve_toggle_n<4>(d, t, rows, n, j, compression);
+            solve_toggle_n<4>(d, t, rows, (1u << n) - 1u, j, compression);
         }
         __syncthreads();
         tick(0);
@@ -2212,66 +2210,62 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                 s_L[p ^ 1] = 0;
                 s_nd[p ^ 1] = 0;
             }
-            // toggle the entries of the changed rows' pivots: kSolveB changed rows per
-            // thread at a time, their records loaded together, then the heads of
-            // all their entries together (two memory latencies per batch)
-            for (int32_t q0 = tid; q0 < nd; q0 += kSolveThreads * kSolveB) {
-                // loads are unconditional (row 0 stands in for unused ones), so each
-                // group waits once
-                PivRec rec[kSolveB];
-                int32_t sign[kSolveB];
-#pragma unroll
-                for (int v = 0; v < kSolveB; v++) {
-                    const int32_t q = q0 + v * kSolveThreads;
+            // toggle the entries of the changed rows' pivots.  G lanes share a changed
+            // row (G = 8 when the changes are few: each lane then toggles one entry,
+            // so the probe chains run side by side; G = 1 when they are many); the
+            // lanes of a row load its record together, then their entries' pivots
+            // and known-negative bits, then toggle
+            {
+                const int32_t G = nd <= kSolveThreads / 8 ? 8 : nd <= kSolveThreads / 4 ? 4
+                                : nd <= kSolveThreads / 2 ? 2 : 1;
+                const int32_t sub = tid & (G - 1), grp = tid / G, per = kSolveThreads / G;
+                for (int32_t q0 = 0; q0 < nd; q0 += per) {
+                    const int32_t q = q0 + grp;
                     const int32_t code = q < nd ? dl[q] : 0;
-                    sign[v] = q < nd ? (code >= 0 ? 1 : -1) : 0;
-                    rec[v] = d.prec[code >= 0 ? code : ~code];
-                }
-                int32_t kv[kSolveB];
-                int2 head[kSolveB][kRecInline];
+                    const int32_t sign = q < nd ? (code >= 0 ? 1 : -1) : 0;
+                    const PivRec rec = d.prec[code >= 0 ? code : ~code];  // row 0 stands in for no row
+                    const int32_t k = sign ? rec.k : 1;  // the pivot's length, its low included
+                    const bool inl = k - 1 <= kRecInline;
+                    // this lane's entries: e[sub], e[sub + G], ...
+                    int32_t ent[kRecInline];
+                    uint32_t use = 0;
 #pragma unroll
-                for (int v = 0; v < kSolveB; v++) {
-                    kv[v] = sign[v] ? rec[v].k : 1;  // the pivot's length, its low included
-                    cxe += sign[v] * kv[v];
-                    by += sign[v] ? 32 : 0;
+                    for (int i = 0; i < kRecInline; i++) {
+                        const int32_t u = sub + i * G;
+                        int32_t x = rec.e[0];
 #pragma unroll
-                    for (int u = 0; u < kRecInline; u++) {
-                        const bool use = u < kv[v] - 1 && kv[v] - 1 <= kRecInline;
-                        head[v][u] = *reinterpret_cast<const int2 *>(&d.prec[use ? rec[v].e[u] : 0]);
+                        for (int c = 1; c < kRecInline; c++) x = u == c ? rec.e[c] : x;
+                        ent[i] = x;
+                        use |= (uint32_t)(inl && u < k - 1) << i;
                     }
-                }
-#pragma unroll
-                for (int v = 0; v < kSolveB; v++) {
-                    const int32_t k = kv[v];
-                    if (k - 1 <= kRecInline) {
-#pragma unroll
-                        for (int u = 0; u < kRecInline; u++) {
-                            const uint32_t fl = solve_flags(head[v][u], j, compression);
-                            if (u < k - 1 && fl != kSolveNeg) solve_toggle(t, rec[v].e[u], fl);
-                        }
-                    } else {  // a long pivot: its entries from its stored column
-                        const int64_t off = d.off[rec[v].s];
-                        by += 12 + 4 * (int64_t)k;
-                        if (kTrace) {
-                            tr[6]++;
-                            tr[7] += k - 1;
-                        }
-                        const int32_t li = atomicAdd(&s_nl, 1);
-                        if (li < kSolveLong) {  // the workgroup toggles its entries below
-                            s_loff[li] = off;
-                            s_lpre[li + 1] = k - 1;
-                            continue;
-                        }
-                        const int32_t *pc = col_base(d, off);
-                        for (int32_t a0 = 0; a0 < k - 1; a0 += 4) {
-                            int32_t rows[4];
-                            int32_t n = 0;
-#pragma unroll
-                            for (int u = 0; u < 4; u++) {
-                                rows[u] = a0 + u < k - 1 ? pc[a0 + u] : -1;
-                                n += a0 + u < k - 1 ? 1 : 0;
+                    solve_toggle_n<kRecInline>(d, t, ent, use, j, compression);
+                    if (sub == 0 && sign) {
+                        cxe += sign * k;
+                        by += 32;
+                        if (!inl) {  // a long pivot: its entries from its stored column
+                            const int64_t off = d.off[rec.s];
+                            by += 12 + 4 * (int64_t)k;
+                            if (kTrace) {
+                                tr[6]++;
+                                tr[7] += k - 1;
                             }
-                            solve_toggle_n<4>(d, t, rows, n, j, compression);
+                            const int32_t li = atomicAdd(&s_nl, 1);
+                            if (li < kSolveLong) {  // the workgroup toggles its entries below
+                                s_loff[li] = off;
+                                s_lpre[li + 1] = k - 1;
+                            } else {
+                                const int32_t *pc = col_base(d, off);
+                                for (int32_t a0 = 0; a0 < k - 1; a0 += 4) {
+                                    int32_t rows[4];
+                                    int32_t n = 0;
+#pragma unroll
+                                    for (int u = 0; u < 4; u++) {
+                                        rows[u] = a0 + u < k - 1 ? pc[a0 + u] : -1;
+                                        n += a0 + u < k - 1 ? 1 : 0;
+                                    }
+                                    solve_toggle_n<4>(d, t, rows, (1u << n) - 1u, j, compression);
+                                }
+                            }
                         }
                     }
                 }
@@ -2303,7 +2297,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                         rows[u] = col_base(d, s_loff[lo])[ec - s_lpre[lo]];
                         n += ei < tot ? 1 : 0;
                     }
-                    solve_toggle_n<4>(d, t, rows, n, j, compression);
+                    solve_toggle_n<4>(d, t, rows, (1u << n) - 1u, j, compression);
                 }
                 __syncthreads();
             }
