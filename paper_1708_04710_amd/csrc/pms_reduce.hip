@@ -73,7 +73,7 @@ enum StatId {
     S_SBYTES, S_ABYTES_SOLVE, S_T_SWEEPS, S_T_SOLVED, S_T_SFALL,
     // trace of k_chain_solve: shader cycles in set-up, the two passes, the toggles and the
     // write-back (thread 0, summed over columns), membership changes
-    S_T_SINIT, S_T_SA, S_T_SB, S_T_SC, S_T_SOUT, S_T_SDELTA, S_T_SLONG, S_T_SLONGE,
+    S_T_SINIT, S_T_SA, S_T_SB, S_T_SC, S_T_SOUT, S_T_SDELTA, S_T_SLONG, S_T_SLONGE, S_T_SDEFER,
     S_NUM
 };
 
@@ -2087,8 +2087,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
     if (total > solve_max) return;             // k_chain takes them all
     int64_t adds = 0, pk = 0, by = 0, ab = 0, sweeps = 0;  // pk: entries read (column and added pivots)
     int32_t nsolved = 0, nfall = 0;
-    // trace: set-up, pass A, pass B, toggles, out cycles; changes; long pivots, their entries
-    unsigned long long tr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // trace: set-up, pass A, pass B, toggles, out cycles; changes; long pivots, their entries;
+    // changes left for the next sweep (more than kSolveDelta in one)
+    unsigned long long tr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     long long c0 = 0;
     auto tick = [&](int q) {
         if (kTrace) {
@@ -2192,6 +2193,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
                         const bool has = ((flag[w] >> (8 * b)) & kSX) != 0;  // it leaves S, else joins
                         dl[q] = has ? ~r : r;
                         flag[w] ^= kSX << (8 * b);  // this thread's word: no other writer in this pass
+                    } else if (kTrace) {
+                        tr[8]++;
                     }
                     q++;
                 }
@@ -2404,6 +2407,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
     if (kTrace) {  // per-thread counts (the cycle counts are thread 0's)
         tr[6] = (unsigned long long)block_sum64<kSolveThreads>((int64_t)tr[6]);
         tr[7] = (unsigned long long)block_sum64<kSolveThreads>((int64_t)tr[7]);
+        tr[8] = (unsigned long long)block_sum64<kSolveThreads>((int64_t)tr[8]);
     }
     if (tid == 0) {
         stat_add(d, S_ADDS, (unsigned long long)b_adds, blockIdx.x);
@@ -2414,7 +2418,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_chain_solve(Dev d, int compre
         stat_add(d, S_T_SOLVED, (unsigned long long)nsolved, blockIdx.x);
         stat_add(d, S_T_SFALL, (unsigned long long)nfall, blockIdx.x);
         if (kTrace)
-            for (int q = 0; q < 8; q++) stat_add(d, S_T_SINIT + q, tr[q], blockIdx.x);
+            for (int q = 0; q < 9; q++) stat_add(d, S_T_SINIT + q, tr[q], blockIdx.x);
     }
 }
 
@@ -3529,7 +3533,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     "mean L %.1f, L>16 %llu, L>32 %llu, long-pivot steps %llu, toggles %llu; first lane pass: toggle rounds %llu, wave iterations %llu, refill phases %llu, "
                     "merge phases %llu, busy lanes per iteration %.1f, steps per iteration %.1f; solve: columns %llu, "
                     "sweeps %llu, most sweeps %d, to k_chain %llu, cycles: set-up %llu, pass A %llu, pass B %llu, "
-                    "toggles %llu, out %llu, changes %llu, longest column %d us, long pivots %llu (entries %llu)\n",
+                    "toggles %llu, out %llu, changes %llu, longest column %d us, long pivots %llu (entries %llu), deferred changes %llu\n",
                     round, nA_prev, h->n_next, dl[S_NEWPIV], dl[S_ADDS], dl[S_T_LANE], dl[S_T_TOWIDE], dl[S_T_WIDE],
                     dl[S_T_QUEUED], dl[S_T_SHORT],
                     dl[S_T_LONG], dl[S_T_GLOBAL],
@@ -3540,7 +3544,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                     (double)dl[S_T_LBUSY] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1),
                     (double)dl[S_T_LANE] / (double)(dl[S_T_LITER] ? dl[S_T_LITER] : 1), dl[S_T_SOLVED],
                     dl[S_T_SWEEPS], h->max_sweeps, dl[S_T_SFALL], dl[S_T_SINIT], dl[S_T_SA], dl[S_T_SB], dl[S_T_SC],
-                    dl[S_T_SOUT], dl[S_T_SDELTA], h->max_solve_us, dl[S_T_SLONG], dl[S_T_SLONGE]);
+                    dl[S_T_SOUT], dl[S_T_SDELTA], h->max_solve_us, dl[S_T_SLONG], dl[S_T_SLONGE], dl[S_T_SDEFER]);
         }
         if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
         {
