@@ -33,27 +33,7 @@ pms_status scan_i64(Ctx *c, int64_t *data, int64_t n, int64_t *tmp, int64_t *tot
 // Exclusive scan of n int64 in place, one block of 1024 threads.
 static __global__ void __launch_bounds__(1024) k_scan_i64(int64_t *a, int64_t n)
 {
-    __shared__ int64_t s_w[1024 / kWave];
-    __shared__ int64_t s_carry;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < n ? a[i] : 0;
-        const int64_t inc = wave_incl_sum64(v);
-        if (lane == kWave - 1) s_w[wid] = inc;
-        __syncthreads();
-        int64_t pre = s_carry, tot = s_carry;
-        for (int w = 0; w < 1024 / kWave; w++) {
-            if (w < wid) pre += s_w[w];
-            tot += s_w[w];
-        }
-        if (i < n) a[i] = pre + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry = tot;
-        __syncthreads();
-    }
+    block_seg_scan(a, n, (int64_t)0, [](int64_t x, int64_t y) { return x + y; });
 }
 
 }  // namespace pms

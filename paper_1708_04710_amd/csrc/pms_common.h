@@ -345,6 +345,66 @@ __device__ inline int64_t block_sum64(int64_t v)
     return tot;
 }
 
+// One-block exclusive scan of n values in place (1024 threads): per pass
+// each thread takes kSeg consecutive values (loaded together: the index is
+// clamped rather than branched on, so one wait covers them), the block scans
+// the threads' sums, and each thread writes its values back.  A pass covers
+// 16 K values with two barriers, where a 1024-value chunk loop needs three
+// barriers and one dependent load per chunk.  Returns the total.
+__device__ inline int32_t shfl_up_t(int32_t x, int dd) { return __shfl_up(x, dd, kWave); }
+__device__ inline int64_t shfl_up_t(int64_t x, int dd) { return __shfl_up(x, dd, kWave); }
+__device__ inline I4 shfl_up_t(I4 x, int dd)
+{
+    I4 y;
+#pragma unroll
+    for (int k = 0; k < 4; k++) y.v[k] = __shfl_up(x.v[k], dd, kWave);
+    return y;
+}
+template <typename T, typename Op>
+__device__ inline T block_seg_scan(T *a, int64_t n, T ident, Op op)
+{
+    constexpr int kThr = 1024, kSeg = 16;
+    __shared__ T s_part[kThr / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    T carry = ident;
+    for (int64_t base = 0; base < n; base += (int64_t)kThr * kSeg) {
+        const int64_t s0 = base + (int64_t)tid * kSeg;
+        T v[kSeg];
+#pragma unroll
+        for (int u = 0; u < kSeg; u++) v[u] = a[min(s0 + u, n - 1)];
+        T loc = ident;
+#pragma unroll
+        for (int u = 0; u < kSeg; u++) {
+            if (s0 + u >= n) v[u] = ident;
+            loc = op(loc, v[u]);
+        }
+        T inc = loc;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+            const T y = shfl_up_t(inc, dd);
+            if (lane >= dd) inc = op(inc, y);
+        }
+        if (lane == kWave - 1) s_part[wid] = inc;
+        __syncthreads();
+        T pre = carry, tot = carry;
+        for (int w = 0; w < kThr / kWave; w++) {
+            const T x = s_part[w];
+            if (w < wid) pre = op(pre, x);
+            tot = op(tot, x);
+        }
+        const T below = shfl_up_t(inc, 1);
+        T ex = lane ? op(pre, below) : pre;
+#pragma unroll
+        for (int u = 0; u < kSeg; u++) {
+            if (s0 + u < n) a[s0 + u] = ex;
+            ex = op(ex, v[u]);
+        }
+        carry = tot;
+        __syncthreads();  // s_part is reused by the next pass
+    }
+    return carry;
+}
+
 // Block-wide exclusive max-scan of I4 (identity -1); *total = block max.
 __device__ inline I4 block_excl_max4(I4 v, I4 *total)
 {

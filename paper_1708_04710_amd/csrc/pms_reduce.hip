@@ -462,33 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(Dev d, const int32_t *act, I
 __global__ void __launch_bounds__(kScanThreads) k_scan_max4(I4 *agg, const int32_t *n_cur)
 {
     const int64_t nb = ((int64_t)*n_cur + kBlock - 1) / kBlock;  // one aggregate per tile of the round
-    __shared__ I4 s_w[kScanThreads / kWave];
-    __shared__ I4 s_carry;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (threadIdx.x == 0) s_carry = i4_fill(-1);
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += kScanThreads) {
-        const int64_t i = base + threadIdx.x;
-        I4 v = i < nb ? agg[i] : i4_fill(-1);
-        I4 inc = wave_incl_max4(v);
-        I4 exc;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            int32_t y = __shfl_up(inc.v[k], 1, kWave);
-            exc.v[k] = lane == 0 ? -1 : y;
-        }
-        if (lane == kWave - 1) s_w[wid] = inc;
-        __syncthreads();
-        I4 pre = s_carry, tot = s_carry;
-        for (int w = 0; w < kScanThreads / kWave; w++) {
-            if (w < wid) pre = i4_max(pre, s_w[w]);
-            tot = i4_max(tot, s_w[w]);
-        }
-        if (i < nb) agg[i] = i4_max(pre, exc);
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry = tot;
-        __syncthreads();
-    }
+    block_seg_scan(agg, nb, i4_fill(-1), [](const I4 &x, const I4 &y) { return i4_max(x, y); });
 }
 
 // nb entries, or, when n_cur is given, one entry per tile of *n_cur columns
@@ -496,28 +470,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sum(int32_t *cnt, int64_t
                                                            int32_t *total)
 {
     if (n_cur) nb = ((int64_t)*n_cur + kBlock - 1) / kBlock;
-    __shared__ int32_t s_w[kScanThreads / kWave];
-    __shared__ int32_t s_carry;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += kScanThreads) {
-        const int64_t i = base + threadIdx.x;
-        int32_t v = i < nb ? cnt[i] : 0;
-        int32_t inc = wave_incl_sum32(v);
-        if (lane == kWave - 1) s_w[wid] = inc;
-        __syncthreads();
-        int32_t pre = s_carry, tot = s_carry;
-        for (int w = 0; w < kScanThreads / kWave; w++) {
-            if (w < wid) pre += s_w[w];
-            tot += s_w[w];
-        }
-        if (i < nb) cnt[i] = pre + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry = tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *total = s_carry;
+    const int32_t tot = block_seg_scan(cnt, nb, 0, [](int32_t x, int32_t y) { return x + y; });
+    if (threadIdx.x == 0) *total = tot;
 }
 
 // Phase I + the beta test + clearing.
