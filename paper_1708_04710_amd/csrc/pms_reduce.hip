@@ -74,6 +74,8 @@ enum StatId {
     // trace of k_chain_solve: shader cycles in set-up, the two passes, the toggles and the
     // write-back (thread 0, summed over columns), membership changes
     S_T_SINIT, S_T_SA, S_T_SB, S_T_SC, S_T_SOUT, S_T_SDELTA, S_T_SLONG, S_T_SLONGE, S_T_SDEFER,
+    // k_pivots: bytes a new pivot moves (its record, the column entries it copies, the tables)
+    S_PBYTES,
     S_NUM
 };
 
@@ -89,6 +91,7 @@ struct Counters {
     // lane passes and k_chain (the bytes of a column addition by itself)
     unsigned long long abytes_xor, abytes_lane, abytes_wide, abytes_chain;
     unsigned long long solve_bytes;  // algorithmic bytes moved by k_chain_solve
+    unsigned long long pivot_bytes;  // bytes k_pivots moves for its new pivots
     // its additions as multi-way sums: 4 (len c + the pivots' lengths + len out) per column
     unsigned long long abytes_solve;
     unsigned long long active_sum;   // sum over rounds of the round's active columns
@@ -501,6 +504,8 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
     I4 tot;
     I4 mc = i4_max(block_excl_max4(e, &tot), agg[tile]);
     int np = 0, nb = 0;
+    int64_t pb = 0;  // a new pivot: piv, its 32-byte record and the entries copied into it (+ off),
+                     // low_star, its state, its row's record head, the cleared column's state
     if (live && !cl) {
         const bool by_beta = d.beta[j] == i;                  // beta_j = low(j): Thm. P.5
         const bool by_li = i > mc.v[slot_of(d, j)];           // low(j) > maxCollision
@@ -509,9 +514,11 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
             PivRec r;
             r.s = j;
             r.k = d.len[j];
+            pb = 4 + 32 + 8 + 4 + 1 + 4 + 2;
             if (r.k - 1 <= kRecInline) {
                 const int32_t *c = col_base(d, d.off[j]);
                 for (int t = 0; t < r.k - 1; t++) r.e[t] = c[t];
+                pb += 4 * (int64_t)(r.k - 1);
             }
             d.prec[i] = r;
             d.state[j] = ST_PIVOT;
@@ -534,7 +541,11 @@ __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, co
         block_excl_sum32(nb, &tnb);
         if (threadIdx.x == 0) stat_add(d, S_BETAPIV, (unsigned long long)tnb, (unsigned)tile);
     }
-    if (threadIdx.x == 0) stat_add(d, S_NEWPIV, (unsigned long long)tnp, (unsigned)tile);
+    const int64_t bpb = block_sum64(pb);
+    if (threadIdx.x == 0) {
+        stat_add(d, S_NEWPIV, (unsigned long long)tnp, (unsigned)tile);
+        stat_add(d, S_PBYTES, (unsigned long long)bpb, (unsigned)tile);
+    }
     __syncthreads();
     }
 }
@@ -2809,6 +2820,7 @@ __global__ void k_stats_fold(Dev d)
         d.cnt->abytes_wide = s_sum[S_ABYTES_WIDE];
         d.cnt->abytes_chain = s_sum[S_ABYTES_CHAIN];
         d.cnt->solve_bytes = s_sum[S_SBYTES];
+        d.cnt->pivot_bytes = s_sum[S_PBYTES];
         d.cnt->abytes_solve = s_sum[S_ABYTES_SOLVE];
         d.cnt->new_pivots = (int32_t)s_sum[S_NEWPIV];
         d.cnt->beta_pivots = (int32_t)s_sum[S_BETAPIV];
@@ -3095,7 +3107,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_fill_i32, grid_for(nwords, kBlock, 65536), kBlock, (int32_t *)d.neg, nwords, 0);
     PMS_LAUNCH(c, K_FILL, 8 * dm, k_fill_u64, gm, kBlock, d.T, m, ~0ull);
     // col_ptr, rows, left updates, dims (facets and columns), headers out
-    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm, k_init, gm, kBlock, d, nnz,
+    // + the 32-byte record of every row (no pivot, not known negative)
+    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm + 32 * dm, k_init, gm, kBlock, d, nnz,
                opt->validate);
     // col_ptr, len, rows, left, beta out, neg bits
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
@@ -3173,7 +3186,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     int32_t nA = (int32_t)m;
     uint32_t round = 0;
     unsigned long long xor_bytes_prev = 0, chain_bytes_prev = 0, lane_bytes_prev = 0, wide_bytes_prev = 0;
-    unsigned long long solve_bytes_prev = 0;
+    unsigned long long solve_bytes_prev = 0, pivot_bytes_prev = 0;
     unsigned long long ab_prev[5] = {0, 0, 0, 0, 0};
     const char *tr_env = getenv("PMS_TRACE");
     const int trace = tr_env && tr_env[0] == '1';
@@ -3184,7 +3197,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // The kernels read the round's active count and number from the device
     // (they loop over tiles), so `grid_tiles` only bounds their grids: the
     // exact tile count when the host knows it, a fixed size in a graph.
-    size_t xor_slot = 0, lane_slot = 0, wide_slot = 0, chain_slot = 0, solve_slot = 0;
+    size_t xor_slot = 0, lane_slot = 0, wide_slot = 0, chain_slot = 0, solve_slot = 0, pivots_slot = 0;
+    double pivots_base = 0;
     const pms_tuning tn = c->tune;
     auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
         const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
@@ -3197,7 +3211,9 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_COLLIDE, 23 * dA + 16 * dt, k_collide, gT, kBlock, d, a, agg);
         PMS_LAUNCH(c, K_SCAN, 32 * dt, k_scan_max4, 1, kScanThreads, agg, &d.cnt->n_cur);
         // act, state, low, coll, dim, beta; aggregates
-        PMS_LAUNCH(c, K_PIVOTS, 15 * dA + 16 * dt, k_pivots, gT, kBlock, d, a, agg, opt->compression);
+        PMS_LAUNCH(c, K_PIVOTS, -1.0, k_pivots, gT, kBlock, d, a, agg, opt->compression);
+        pivots_slot = c->pend.size() - 1;
+        pivots_base = 15 * dA + 16 * dt;  // act, coll, low, beta, dim, scan aggregates; + the new pivots' bytes
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (c8on) {
             // the first unpaired rows (a scan from the last ones, usually short); act, dim, beta, state, low
@@ -3455,6 +3471,8 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         if (c->prof_on) {
             c->pend[xor_slot].bytes = (double)(h->xor_bytes - xor_bytes_prev);
             xor_bytes_prev = h->xor_bytes;
+            c->pend[pivots_slot].bytes = pivots_base + (double)(h->pivot_bytes - pivot_bytes_prev);
+            pivot_bytes_prev = h->pivot_bytes;
             c->pend[chain_slot].bytes = (double)(h->chain_bytes - chain_bytes_prev);
             chain_bytes_prev = h->chain_bytes;
             c->pend[lane_slot].bytes = (double)(h->lane_bytes - lane_bytes_prev);
