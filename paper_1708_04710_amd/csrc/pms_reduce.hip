@@ -2683,12 +2683,6 @@ __global__ void __launch_bounds__(kBlock) k_dbg_final(Dev d)
     }
 }
 
-__global__ void k_round_init(Dev d, int32_t m)
-{
-    d.cnt->n_cur = m;
-    d.cnt->round = 0;
-}
-
 // Twist-order stages: the list to filter has n entries; a stage starts from
 // the filtered list and treats its dimension as the top one (nothing can
 // clear its columns any more: the dimension above is reduced).
@@ -2793,6 +2787,34 @@ __global__ void __launch_bounds__(kBlock) k_fin_scatter(Dev d, const int32_t *of
 
 // Partition bump pointers after (re)allocation: partition p starts at
 // part_base + p * part_size.
+// The reduction's state before Phase 0, in one pass: counters and stripes
+// cleared, arena partitions set, and per column left = none, no pivot, no
+// low*, the leftmost table empty, the active list 0..m-1; the negative
+// bitmask cleared; the round counters (count m, round 0) after the clear.
+__global__ void __launch_bounds__(kBlock) k_setup(Dev d, int32_t *act0, int64_t nwords, int64_t nstats)
+{
+    const int64_t gid = blockIdx.x * (int64_t)kBlock + threadIdx.x, gstride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = gid; j < d.m; j += gstride) {
+        d.left[j] = 0x7FFFFFFF;
+        d.piv[j] = -1;
+        d.low_star[j] = -1;
+        d.T[j] = ~0ull;
+        act0[j] = (int32_t)j;
+    }
+    for (int64_t w = gid; w < nwords; w += gstride) d.neg[w] = 0u;
+    for (int64_t w = gid; w < nstats; w += gstride) d.stats[w] = 0ull;
+    if (blockIdx.x == 0) {
+        unsigned long long *cw = reinterpret_cast<unsigned long long *>(d.cnt);
+        for (int w = threadIdx.x; w < (int)(sizeof(Counters) / 8); w += kBlock) cw[w] = 0ull;
+        if (threadIdx.x < kPart) d.part[threadIdx.x * 16] = d.part_base + (unsigned long long)threadIdx.x * d.part_size;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            d.cnt->n_cur = (int32_t)d.m;
+            d.cnt->round = 0;
+        }
+    }
+}
+
 __global__ void k_part_init(Dev d)
 {
     const int p = threadIdx.x;
@@ -3095,25 +3117,16 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
 
     hipStream_t st = c->stream;
     const unsigned gm = grid_for(m, kBlock, 65536);
-    PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, 1, kBlock, (unsigned long long *)d.cnt,
-               (int64_t)(sizeof(Counters) / 8), 0ull);
-    PMS_LAUNCH(c, K_FILL, 0, k_fill_u64, grid_for(S_NUM * kStripe * 16), kBlock, d.stats,
-               (int64_t)S_NUM * kStripe * 16, 0ull);
-    PMS_LAUNCH(c, K_FILL, 0, k_part_init, 1, kPart, d);
     const double dm = (double)m, dz = (double)nnz;
-    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.left, m, 0x7FFFFFFF);
-    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.piv, m, -1);
-    PMS_LAUNCH(c, K_FILL, 4 * dm, k_fill_i32, gm, kBlock, d.low_star, m, -1);
-    PMS_LAUNCH(c, K_FILL, 4.0 * nwords, k_fill_i32, grid_for(nwords, kBlock, 65536), kBlock, (int32_t *)d.neg, nwords, 0);
-    PMS_LAUNCH(c, K_FILL, 8 * dm, k_fill_u64, gm, kBlock, d.T, m, ~0ull);
+    // left, piv, low*, T, the active list; the negative bitmask
+    PMS_LAUNCH(c, K_FILL, 24 * dm + 4.0 * nwords, k_setup, gm, kBlock, d, act0, (int64_t)nwords,
+               (int64_t)S_NUM * kStripe * 16);
     // col_ptr, rows, left updates, dims (facets and columns), headers out
     // + the 32-byte record of every row (no pivot, not known negative)
     PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm + 32 * dm, k_init, gm, kBlock, d, nnz,
                opt->validate);
     // col_ptr, len, rows, left, beta out, neg bits
     PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
-    PMS_LAUNCH(c, K_FILL, 4 * dm, k_iota, gm, kBlock, act0, m);
-    PMS_LAUNCH(c, K_FILL, 0, k_round_init, 1, 1, d, (int32_t)m);
     // priority with a budget: the key histogram (and threshold) and, for
     // priority 1, the sizes of the sets N per low
     const bool budget = opt->round_budget > 0;
