@@ -82,6 +82,14 @@ typedef struct {
     const int64_t *col_ptr; /* [m+1], col_ptr[0] = 0, non-decreasing */
     const int32_t *rows;    /* [col_ptr[m]] */
     const int8_t *dim;      /* [m] or NULL */
+    /* Optional, both or neither (NULL): left (Def. "left": the first column
+     * holding row i, 2^31 - 1 when none) and beta (Def. "beta": the largest
+     * row r of column j with left(r) = j, -1 when none), device [m], as a
+     * filtration builder can produce them (Sec. 3, after Alg. "Building
+     * beta").  Given, Phase 0 reads them instead of computing them; they must
+     * equal the definitions (debug_invariants then checks beta's bounds). */
+    const int32_t *left;
+    const int32_t *beta;
 } pms_boundary;
 
 /* Options.  Zero-initialise and set what you need; pms_default_options()
@@ -368,6 +376,9 @@ typedef struct {
                                  edge whose length is the simplex's value, latest in the
                                  filtration; -1 -1 for vertices) that fixes each value */
     const int32_t *verts;     /* [4m] device, ascending vertex ids, -1 padded */
+    const int32_t *left;      /* [m] device, Def. "left" (2^31 - 1: none), or NULL when the
+                                 builder does not produce it (lower-star does) */
+    const int32_t *beta;      /* [m] device, Def. "beta" (-1: none), or NULL likewise */
 } pms_filtration_view;
 
 /* Lower-star filtration of the Freudenthal triangulation of an
@@ -414,6 +425,11 @@ pms_status pms_filtration_view_get(const pms_filtration *f, pms_filtration_view 
  * copies complete. */
 pms_status pms_filtration_copy_out(pms_ctx *ctx, const pms_filtration *f, int64_t *col_ptr, int32_t *rows,
                                    int8_t *dim, void *value, int32_t *crit, int32_t *verts);
+/* Copy the filtration's left and beta (Defs. "left", "beta"; see
+ * pms_filtration_view) into caller-owned device arrays of m entries on ctx's
+ * stream (either may be NULL); returns after the copies complete.
+ * PMS_ERR_INVALID_ARG when the builder did not produce them. */
+pms_status pms_filtration_copy_left_beta(pms_ctx *ctx, const pms_filtration *f, int32_t *left, int32_t *beta);
 /* Release a filtration (synchronises its device).  NULL is accepted. */
 void pms_filtration_free(pms_filtration *f);
 

@@ -37,13 +37,13 @@ EXPORTED = [
     "pms_reduce", "pms_reduce_noalloc", "pms_reduce_batched", "pms_round_stats_read", "pms_essential_estimate", "pms_default_tuning", "pms_set_tuning", "pms_get_tuning", "pms_autotune",
     "pms_profile_enable", "pms_profile_kernels", "pms_profile_kernel_name",
     "pms_profile_read", "pms_profile_read_addition_bytes", "pms_build_lowerstar", "pms_build_vr_i32", "pms_build_vr_f32", "pms_filtration_view_get", "pms_filtration_copy_out",
-    "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
+    "pms_filtration_copy_left_beta", "pms_filtration_free", "pms_gather", "pms_backward_lowerstar", "pms_backward_vr_f32",
 ]
 
 
 class PmsBoundary(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("col_ptr", ctypes.c_void_p), ("rows", ctypes.c_void_p),
-                ("dim", ctypes.c_void_p)]
+                ("dim", ctypes.c_void_p), ("left", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
 
 
 class PmsOptions(ctypes.Structure):
@@ -73,7 +73,8 @@ class PmsTuning(ctypes.Structure):
 class PmsFiltrationView(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("nnz", ctypes.c_int64), ("col_ptr", ctypes.c_void_p),
                 ("rows", ctypes.c_void_p), ("dim", ctypes.c_void_p), ("value_f32", ctypes.c_void_p),
-                ("value_i64", ctypes.c_void_p), ("crit", ctypes.c_void_p), ("verts", ctypes.c_void_p)]
+                ("value_i64", ctypes.c_void_p), ("crit", ctypes.c_void_p), ("verts", ctypes.c_void_p),
+                ("left", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
 
 
 class PmsResult(ctypes.Structure):
@@ -169,6 +170,8 @@ def load(path: str = LIB_PATH):
     lib.pms_filtration_view_get.restype = ctypes.c_int
     lib.pms_filtration_copy_out.argtypes = [P, P, P, P, P, P, P, P]
     lib.pms_filtration_copy_out.restype = ctypes.c_int
+    lib.pms_filtration_copy_left_beta.argtypes = [P, P, P, P]
+    lib.pms_filtration_copy_left_beta.restype = ctypes.c_int
     lib.pms_filtration_free.argtypes = [P]
     lib.pms_filtration_free.restype = None
     _lib = lib

@@ -151,6 +151,18 @@ class Filtration:
         out["verts"] = out["verts"][:4 * m].view(m, 4)
         return out
 
+    def left_beta(self):
+        """(left, beta) as device int32 tensors (Defs. "left", "beta"; 2^31 - 1
+        and -1 for none) when the builder produced them, else None."""
+        if not self.view.left:
+            return None
+        m, dev = self.m, self.device
+        left = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        beta = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        ctx = _ctx(dev)
+        B.check(ctx, B.load().pms_filtration_copy_left_beta(ctx, self.handle, left.data_ptr(), beta.data_ptr()))
+        return left[:m], beta[:m]
+
     def __del__(self):
         try:
             lib = B._lib
@@ -262,10 +274,10 @@ def _result(res, t, **extra) -> ReduceResult:
 
 
 def _reduce_ptrs(dev, m, col_ptr_p, rows_p, dim_p, *, outputs=True, inst_col_off=None, noalloc=False,
-                 **kw) -> ReduceResult:
+                 left_p=None, beta_p=None, **kw) -> ReduceResult:
     lib = B.load()
     ctx = _ctx(dev)
-    bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p)
+    bnd = B.PmsBoundary(m, col_ptr_p, rows_p, dim_p, left_p, beta_p)
     opt = _options(**kw)
     res, t = _outputs(dev, m, outputs)
     extra = {}
@@ -396,7 +408,7 @@ def time_candidates(f: "Filtration", candidates, reps: int = 3, **kw):
     ctx = _ctx(f.device)
     v = f.view
     m = int(v.m)
-    bnd = B.PmsBoundary(m, v.col_ptr, v.rows, v.dim)
+    bnd = B.PmsBoundary(m, v.col_ptr, v.rows, v.dim, v.left, v.beta)
     opts = (B.PmsOptions * n)()
     tunes = (B.PmsTuning * n)()
     for i, c in enumerate(candidates):
@@ -445,7 +457,7 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
 def reduce_filtration(f: Filtration, **kw) -> ReduceResult:
     """Reduce a device-built filtration in place of its library-owned arrays."""
     v = f.view
-    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, **kw)
+    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, left_p=v.left, beta_p=v.beta, **kw)
 
 
 def reduce_batched(f: Filtration, col_off, **kw) -> ReduceResult:
@@ -455,4 +467,5 @@ def reduce_batched(f: Filtration, col_off, **kw) -> ReduceResult:
     (count + 1 entries, host list or int64 tensor)."""
     off = torch.as_tensor(col_off, dtype=torch.int64).to(f.device)
     v = f.view
-    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, inst_col_off=off, **kw)
+    return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, inst_col_off=off, left_p=v.left,
+                        beta_p=v.beta, **kw)

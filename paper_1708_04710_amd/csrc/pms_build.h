@@ -16,7 +16,10 @@ struct Filtration {
     void *value = nullptr;       // [m] float or int64
     int32_t *crit = nullptr;     // [2m] critical vertex / critical edge endpoints
     int32_t *verts = nullptr;    // [4m] ascending vertex ids, -1 padded
+    int32_t *left = nullptr;     // [m] Def. "left" (2^31 - 1: no column holds the row), when has_left_beta
+    int32_t *beta = nullptr;     // [m] Def. "beta" (-1: none), when has_left_beta
     int value_is_f32 = 1;
+    int has_left_beta = 0;       // the builder wrote left and beta
 };
 
 // (Re)allocate *f for m simplices and nnz facets; reuses it when big enough.

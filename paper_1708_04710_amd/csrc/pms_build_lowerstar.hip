@@ -19,7 +19,12 @@
 //
 // The boundary matrix (eq. "def:boundary_matrix") follows from a dense
 // (anchor, shape) -> filtration index table: the facets of (v, s) are
-// (v + delta, s') with delta and s' read from a per-shape table.
+// (v + delta, s') with delta and s' read from a per-shape table.  The same
+// table read the other way gives each simplex's cofaces, so the builder also
+// returns left (Def. "left": the first column holding a row, the first
+// coface in the order) and beta (Def. "beta": the largest row of a column
+// whose left is that column), which the reduction would otherwise compute
+// with one atomic per nonzero.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,6 +49,11 @@ struct ShapeTab {
     int8_t by_rank[4][16];    // shape id of (dim, rank)
     int8_t facet[kShapes][4]; // facet shape id after removing vertex k
     int32_t fdelta[kShapes][4];  // anchor shift of that facet
+    // cofaces: the shapes one dimension up with this shape as a facet, and the
+    // step (axis mask, 0: none) from their anchor to this one
+    int8_t ncof[kShapes];
+    int8_t cof_s[kShapes][14];
+    int8_t cof_e[kShapes][14];
 };
 
 __device__ inline uint32_t f32_order_bits(float x)
@@ -124,7 +134,8 @@ __global__ void __launch_bounds__(kBlock) k_ls_index(ShapeTab t, const float *__
 
 __global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned long long *__restrict__ keys, int64_t m,
                                                     int64_t nv, int64_t nnz, const int32_t *__restrict__ idx_tab,
-                                                    const int64_t *tile_off, int64_t *col_ptr, int32_t *rows)
+                                                    const int64_t *tile_off, int64_t *col_ptr, int32_t *rows,
+                                                    const int32_t *__restrict__ left, int32_t *beta)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t nf = 0;
@@ -152,6 +163,112 @@ __global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned l
             r[b + 1] = x;
         }
         for (int k = 0; k < nf; k++) rows[start + k] = r[k];
+        // beta: the largest row whose first column is this one (loads together, then the scan)
+        int32_t lf[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) lf[k] = left[k < nf ? r[k] : 0];
+        int32_t b = -1;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (k < nf && lf[k] == (int32_t)p) b = r[k];  // rows ascending: the last hit is the largest
+        beta[p] = b;
+    }
+}
+
+// left of every simplex (Def. "left"): the smallest filtration index among
+// its cofaces (none: 2^31 - 1).  A coface of (v, s) is anchored at v minus a
+// step e (a subset of the axes), so a workgroup that handles the anchors
+// v0 .. v0 + kLeftV - 1 needs the index-table rows of four planes, v - b and
+// v - b - 1 for b in {0, nx, nx ny, nx ny + nx}: it stages them into LDS with
+// coalesced loads (rows padded to an odd stride), then takes its (anchor,
+// shape) pairs shape-major, so a wavefront holds one shape and reads the
+// coface tables as scalars.  The one scattered access is the write of left at
+// the simplex's filtration index.
+constexpr int kLeftV = 64;                                  // anchors per tile
+constexpr int kLeftRow = kShapes + 1;                       // LDS row stride
+constexpr int kLeftPlane = (kLeftV + 1) * kShapes;          // staged entries per plane
+constexpr int kLeftPer = (kLeftPlane + kBlock - 1) / kBlock;
+
+// The smallest staged index among the cofaces of (v0 + vl, s), kN >= the
+// shape's coface count (a vertex has 14, an edge at most 6, a triangle 2);
+// the LDS reads are issued together.
+template <int kN>
+__device__ inline int32_t ls_first_coface(const ShapeTab &t, int s, int vl, int back, int fwd,
+                                          const int32_t (*seg)[(kLeftV + 1) * kLeftRow])
+{
+    const int nc = t.ncof[s];
+    int32_t got[kN];
+    bool ok[kN];
+#pragma unroll
+    for (int c = 0; c < kN; c++) {
+        const int sp = c < nc ? t.cof_s[s][c] : s;
+        const int e = c < nc ? t.cof_e[s][c] : 0;
+        // the coface's anchor v - e is on the grid, and the coface fits there
+        ok[c] = c < nc && !(e & ~back) && !(t.ext[sp] & ~e & ~fwd);
+        got[c] = seg[(e >> 1) & 3][(vl + 1 - (e & 1)) * kLeftRow + sp];
+    }
+    int32_t best = 0x7FFFFFFF;
+#pragma unroll
+    for (int c = 0; c < kN; c++)
+        if (ok[c]) best = min(best, got[c]);
+    return best;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ls_left(ShapeTab t, int64_t nv, int64_t m,
+                                                    const int32_t *__restrict__ idx_tab, int32_t *left)
+{
+    static_assert(kLeftV == 64 && kBlock % kLeftV == 0, "one shape per wavefront");
+    __shared__ int32_t seg[4][(kLeftV + 1) * kLeftRow];
+    __shared__ uint8_t nb[kLeftV];  // back | fwd << 3: axes with a grid neighbour below / above
+    const int32_t nx = t.nx, ny = t.ny, nz = t.nz, nxy = nx * ny;
+    for (int64_t v0 = (int64_t)blockIdx.x * kLeftV; v0 < nv; v0 += (int64_t)gridDim.x * kLeftV) {
+        // plane g holds the kLeftV + 1 rows from v0 - b_g - 1 on: one
+        // contiguous run of the table starting at a uniform entry
+        int32_t val[4][kLeftPer];
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+            const int64_t start = (v0 - ((g & 1 ? nx : 0) + (g & 2 ? nxy : 0)) - 1) * kShapes;
+#pragma unroll
+            for (int q = 0; q < kLeftPer; q++) {
+                const int r = q * kBlock + (int)threadIdx.x;
+                const int64_t e = start + r;
+                const bool in = r < kLeftPlane && e >= 0 && e < nv * kShapes;
+                val[g][q] = idx_tab[in ? e : 0];
+                if (!in) val[g][q] = -1;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; g++)
+#pragma unroll
+            for (int q = 0; q < kLeftPer; q++) {
+                const int r = q * kBlock + (int)threadIdx.x;
+                const int j = r / kShapes;
+                if (r < kLeftPlane) seg[g][j * kLeftRow + (r - j * kShapes)] = val[g][q];
+            }
+        if (threadIdx.x < kLeftV) {
+            const int64_t v = v0 + threadIdx.x;
+            const int32_t z = (int32_t)(v / nxy), rem = (int32_t)(v - (int64_t)z * nxy), y = rem / nx, x = rem - y * nx;
+            const int fwd = (x + 1 < nx ? 1 : 0) | (y + 1 < ny ? 2 : 0) | (z + 1 < nz ? 4 : 0);
+            const int back = (x > 0 ? 1 : 0) | (y > 0 ? 2 : 0) | (z > 0 ? 4 : 0);
+            nb[threadIdx.x] = (uint8_t)(back | fwd << 3);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kShapes * kLeftV; k += kBlock) {
+            const int s = __builtin_amdgcn_readfirstlane(k / kLeftV);  // k / 64 is one value per wavefront
+            const int vl = k % kLeftV;
+            const int bits = nb[vl], back = bits & 7, fwd = bits >> 3;
+            if (v0 + vl >= nv || (t.ext[s] & ~fwd)) continue;  // past the end, or the shape leaves the grid
+            const int32_t p = seg[0][(vl + 1) * kLeftRow + s];
+            int32_t best = 0x7FFFFFFF;
+            switch (t.dim[s]) {
+            case 0: best = ls_first_coface<14>(t, s, vl, back, fwd, seg); break;
+            case 1: best = ls_first_coface<6>(t, s, vl, back, fwd, seg); break;
+            case 2: best = ls_first_coface<2>(t, s, vl, back, fwd, seg); break;
+            default: break;
+            }
+            if ((uint64_t)(uint32_t)p < (uint64_t)m) left[p] = best;
+        }
+        __syncthreads();
     }
 }
 
@@ -228,6 +345,18 @@ static void make_tables(ShapeTab &t, int nx, int ny, int nz)
             t.by_rank[d][r] = (int8_t)ids[r];
         }
     }
+    // cofaces: facet k of (v', s') is (v' + step, facet[s'][k]), the step being
+    // the shape's first step when k = 0 and none otherwise
+    for (int s = 0; s < kShapes; s++) t.ncof[s] = 0;
+    for (int sp = 0; sp < kShapes; sp++) {
+        const int d = t.dim[sp];
+        for (int k = 0; d >= 1 && k <= d; k++) {
+            const int f = t.facet[sp][k];
+            const int n = t.ncof[f]++;
+            t.cof_s[f][n] = (int8_t)sp;
+            t.cof_e[f][n] = (int8_t)(k == 0 ? shapes[sp][0] : 0);
+        }
+    }
 }
 
 // Number of simplices and facets (closed form: a shape fits at an anchor iff
@@ -298,8 +427,13 @@ pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, in
                (unsigned)tiles, kBlock, t, grid, keys2, m, nv, idx, f->dim, (float *)f->value, f->crit, f->verts, tsum,
                err);
     PMS_LAUNCH(c, K_BUILD_SCAN, 16.0 * tiles, k_scan_i64, 1, 1024, tsum, tiles);
-    PMS_LAUNCH(c, K_LS_ROWS, 8.0 * m + 4.0 * nnz + 4.0 * nnz + 8.0 * m, k_ls_rows, (unsigned)tiles, kBlock, t, keys2,
-               m, nv, nnz, idx, tsum, f->col_ptr, f->rows);
+    // the simplex's and its cofaces' table entries, left out
+    PMS_LAUNCH(c, K_LS_LEFT, 4.0 * m + 4.0 * nnz + 4.0 * m, k_ls_left, grid_for(nv, kLeftV, 65536), kBlock, t, nv, m,
+               idx, f->left);
+    // + the facets' left, beta out
+    PMS_LAUNCH(c, K_LS_ROWS, 8.0 * m + 4.0 * nnz + 4.0 * nnz + 8.0 * m + 4.0 * nnz + 4.0 * m, k_ls_rows,
+               (unsigned)tiles, kBlock, t, keys2, m, nv, nnz, idx, tsum, f->col_ptr, f->rows, f->left, f->beta);
+    f->has_left_beta = 1;
     PMS_HIP(hipGetLastError());
     int32_t herr = 0;
     PMS_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));

@@ -27,7 +27,7 @@ struct Buf {
 enum KernelId {
     K_INIT = 0, K_BETA, K_LOW, K_COLLIDE, K_SCAN, K_PIVOTS, K_XOR, K_COMPACT, K_FINAL, K_FILL, K_DEFRAG,
     K_LS_KEYS, K_SORT, K_LS_INDEX, K_BUILD_SCAN, K_LS_ROWS, K_VR_EDGES, K_VR_TRI, K_VR_INDEX, K_VR_ROWS,
-    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE, K_C8, K_BUDGET, K_SOLVE,
+    K_BACKWARD, K_CHAIN, K_CHAIN_LANE, K_CHAIN_WIDE, K_C8, K_BUDGET, K_SOLVE, K_LS_LEFT,
     K_NUM
 };
 

@@ -17,6 +17,9 @@ static void filtration_release(Filtration *f)
     (void)hipFree(f->value);
     (void)hipFree(f->crit);
     (void)hipFree(f->verts);
+    (void)hipFree(f->left);
+    (void)hipFree(f->beta);
+    f->left = f->beta = nullptr;
     f->col_ptr = nullptr;
     f->rows = nullptr;
     f->dim = nullptr;
@@ -35,6 +38,7 @@ pms_status filtration_reserve(Ctx *c, Filtration **pf, int64_t m, int64_t nnz, i
         f->device = c->device;
         *pf = f;
     }
+    f->has_left_beta = 0;  // until a builder writes them
     if (f->cap_m >= m && f->cap_nnz >= nnz && f->device == c->device) return PMS_OK;
     (void)hipStreamSynchronize(c->stream);
     filtration_release(f);
@@ -46,6 +50,8 @@ pms_status filtration_reserve(Ctx *c, Filtration **pf, int64_t m, int64_t nnz, i
     PMS_HIP(hipMalloc(&f->value, M * 8));
     PMS_HIP(hipMalloc(&f->crit, M * 8));
     PMS_HIP(hipMalloc(&f->verts, M * 16));
+    PMS_HIP(hipMalloc(&f->left, M * 4));
+    PMS_HIP(hipMalloc(&f->beta, M * 4));
     f->cap_m = M;
     f->cap_nnz = Z;
     (void)f32;
@@ -143,6 +149,23 @@ pms_status pms_filtration_view_get(const pms_filtration *fh, pms_filtration_view
     v->value_i64 = f->value_is_f32 ? nullptr : (const int64_t *)f->value;
     v->crit = f->crit;
     v->verts = f->verts;
+    v->left = f->has_left_beta ? f->left : nullptr;
+    v->beta = f->has_left_beta ? f->beta : nullptr;
+    return PMS_OK;
+}
+
+pms_status pms_filtration_copy_left_beta(pms_ctx *ctx, const pms_filtration *fh, int32_t *left, int32_t *beta)
+{
+    pms::Ctx *c = reinterpret_cast<pms::Ctx *>(ctx);
+    const pms::Filtration *f = reinterpret_cast<const pms::Filtration *>(fh);
+    if (!c) return PMS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!f || !f->has_left_beta) return pms::set_err(c, PMS_ERR_INVALID_ARG, "the filtration has no left / beta");
+    if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
+    const size_t n = (size_t)f->m * 4;
+    if (left && n) PMS_HIP(hipMemcpyAsync(left, f->left, n, hipMemcpyDeviceToDevice, c->stream));
+    if (beta && n) PMS_HIP(hipMemcpyAsync(beta, f->beta, n, hipMemcpyDeviceToDevice, c->stream));
+    PMS_HIP(hipStreamSynchronize(c->stream));
     return PMS_OK;
 }
 

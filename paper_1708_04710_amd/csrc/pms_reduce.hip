@@ -307,7 +307,10 @@ __global__ void k_iota(int32_t *p, int64_t n)
 // The structural checks (slice inside rows[0, nnz), rows strictly ascending
 // and in [0, j)) always run, so no later kernel can index out of bounds;
 // `validate` adds the dimension check.
-__global__ void k_init(Dev d, int64_t nnz, int validate)
+// given = 1: left and beta come with the boundary (a builder made them), so
+// the atomics on left are skipped and beta's consequences (a known-negative
+// row's record, its bit in neg) are written here instead of in k_beta.
+__global__ void k_init(Dev d, int64_t nnz, int validate, int given, int compression)
 {
     int top = 0;
     const int lane = threadIdx.x & (kWave - 1);
@@ -325,12 +328,15 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
         const int32_t last = n > 0 ? d.rows[s + n - 1] : -1 - lane;
         const int32_t prev_last = __shfl_up(last, 1, kWave);
         const bool skip_last = lane > 0 && prev_last == last;
+        const bool negb = given && compression && inr && d.beta[j] >= 0;
+        if (given) mark_neg(d.neg, j, negb);  // every lane of the wave takes part
         if (!inr) continue;
         const int dj = validate && d.dim ? d.dim[j] : 0;
         // the rows four at a time: their loads (and the facets' dimensions)
         // go out together instead of one dependent chain per row
         int32_t prev = -1;
-        for (int32_t p0 = 0; p0 < n; p0 += 4) {
+        const int32_t nscan = given && !validate ? 0 : n;  // the rows are read to check them or for left
+        for (int32_t p0 = 0; p0 < nscan; p0 += 4) {
             int32_t r[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) r[u] = p0 + u < n ? d.rows[s + p0 + u] : 0x7FFFFFFF;
@@ -346,10 +352,12 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
                 prev = r[u];
             }
             if (bad) break;
+            if (!given) {
 #pragma unroll
-            for (int u = 0; u < 4; u++)  // left only decreases
-                if (p0 + u < n && !(skip_last && p0 + u == n - 1) && (int32_t)j < d.left[r[u]])
-                    atomicMin(&d.left[r[u]], (int32_t)j);
+                for (int u = 0; u < 4; u++)  // left only decreases
+                    if (p0 + u < n && !(skip_last && p0 + u == n - 1) && (int32_t)j < d.left[r[u]])
+                        atomicMin(&d.left[r[u]], (int32_t)j);
+            }
         }
         if (validate && d.dim && dj < 0) bad = true;
         if (bad) { atomicExch(&d.cnt->error, 1); n = 0; }
@@ -360,7 +368,7 @@ __global__ void k_init(Dev d, int64_t nnz, int validate)
         // row j: no pivot, not known negative (the whole 32-byte record, so
         // the stores fill whole memory sectors)
         int4 *pr = reinterpret_cast<int4 *>(&d.prec[j]);
-        pr[0] = make_int4(-1, 0, 0, 0);
+        pr[0] = make_int4(-1, negb ? -1 : 0, 0, 0);  // with beta given: known negative rows marked here
         pr[1] = make_int4(0, 0, 0, 0);
         if (d.dim && d.dim[j] > top) top = d.dim[j];
     }
@@ -2791,11 +2799,11 @@ __global__ void __launch_bounds__(kBlock) k_fin_scatter(Dev d, const int32_t *of
 // cleared, arena partitions set, and per column left = none, no pivot, no
 // low*, the leftmost table empty, the active list 0..m-1; the negative
 // bitmask cleared; the round counters (count m, round 0) after the clear.
-__global__ void __launch_bounds__(kBlock) k_setup(Dev d, int32_t *act0, int64_t nwords, int64_t nstats)
+__global__ void __launch_bounds__(kBlock) k_setup(Dev d, int32_t *act0, int64_t nwords, int64_t nstats, int fill_left)
 {
     const int64_t gid = blockIdx.x * (int64_t)kBlock + threadIdx.x, gstride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = gid; j < d.m; j += gstride) {
-        d.left[j] = 0x7FFFFFFF;
+        if (fill_left) d.left[j] = 0x7FFFFFFF;
         d.piv[j] = -1;
         d.low_star[j] = -1;
         d.T[j] = ~0ull;
@@ -3009,7 +3017,7 @@ static bool extra_options_ok(const pms_options &o, const pms_boundary *bnd)
     if (o.c8 < 0 || o.c8 > 1 || o.sweep < 0 || o.sweep > 1 || o.priority < 0 || o.priority > 2 ||
         o.round_budget < 0 || o.reserved != 0)
         return false;
-    return bnd->dim || (!o.c8 && !o.sweep);
+    return (bnd->dim || (!o.c8 && !o.sweep)) && (!bnd->left) == (!bnd->beta);
 }
 
 static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options *opt, pms_result *res,
@@ -3050,8 +3058,10 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     d.len = (int32_t *)S.get(B_LEN, m * 4);
     d.low = (int32_t *)S.get(B_LOW, m * 4);
     d.state = (uint8_t *)S.get(B_STATE, m);
-    d.beta = (int32_t *)S.get(B_BETA, m * 4);
-    d.left = (int32_t *)S.get(B_LEFT, m * 4);
+    // left and beta: the caller's when a builder gave them (read only), else computed in Phase 0
+    const bool given_lb = bnd->left && bnd->beta;
+    d.beta = given_lb ? const_cast<int32_t *>(bnd->beta) : (int32_t *)S.get(B_BETA, m * 4);
+    d.left = given_lb ? const_cast<int32_t *>(bnd->left) : (int32_t *)S.get(B_LEFT, m * 4);
     d.piv = (int32_t *)S.get(B_PIV, m * 4);
     d.T = (unsigned long long *)S.get(B_T, m * 8);
     d.neg = (uint32_t *)S.get(B_NEG, nwords * 4);
@@ -3119,14 +3129,21 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     const unsigned gm = grid_for(m, kBlock, 65536);
     const double dm = (double)m, dz = (double)nnz;
     // left, piv, low*, T, the active list; the negative bitmask
-    PMS_LAUNCH(c, K_FILL, 24 * dm + 4.0 * nwords, k_setup, gm, kBlock, d, act0, (int64_t)nwords,
-               (int64_t)S_NUM * kStripe * 16);
+    PMS_LAUNCH(c, K_FILL, (given_lb ? 20 : 24) * dm + 4.0 * nwords, k_setup, gm, kBlock, d, act0, (int64_t)nwords,
+               (int64_t)S_NUM * kStripe * 16, given_lb ? 0 : 1);
     // col_ptr, rows, left updates, dims (facets and columns), headers out
-    // + the 32-byte record of every row (no pivot, not known negative)
-    PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm + 32 * dm, k_init, gm, kBlock, d, nnz,
-               opt->validate);
+    // + the 32-byte record of every row (no pivot, not known negative); with
+    // left and beta given, no left updates (rows read only to check them) but beta read
+    if (given_lb)
+        PMS_LAUNCH(c, K_INIT, 8 * dm + (opt->validate ? 4 * dz + (bnd->dim ? dm + dz : 0) : 4 * dm) + 25 * dm + 32 * dm +
+                                  4 * dm + dm / 8,
+                   k_init, gm, kBlock, d, nnz, opt->validate, 1, opt->compression);
+    else
+        PMS_LAUNCH(c, K_INIT, 8 * dm + 8 * dz + (bnd->dim ? dm + dz : 0) + 25 * dm + 32 * dm, k_init, gm, kBlock, d,
+                   nnz, opt->validate, 0, opt->compression);
     // col_ptr, len, rows, left, beta out, neg bits
-    PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
+    if (!given_lb)
+        PMS_LAUNCH(c, K_BETA, 12 * dm + 8 * dz + 4 * dm + dm / 8, k_beta, gm, kBlock, d, opt->compression);
     // priority with a budget: the key histogram (and threshold) and, for
     // priority 1, the sizes of the sets N per low
     const bool budget = opt->round_budget > 0;
@@ -3729,7 +3746,7 @@ static const char *const kKernelNames[pms::K_NUM] = {
     "k_init", "k_beta", "k_low", "k_collide", "k_scan", "k_pivots", "k_xor", "k_compact", "k_finalize", "k_fill",
     "k_defrag", "k_ls_keys", "k_sort", "k_ls_index", "k_build_scan", "k_ls_rows", "k_vr_edges", "k_vr_tri",
     "k_vr_index", "k_vr_rows", "k_backward", "k_chain", "k_chain_lane", "k_chain_wide", "k_c8", "k_budget",
-    "k_chain_solve"};
+    "k_chain_solve", "k_ls_left"};
 
 pms_status pms_profile_enable(pms_ctx *c, int enable)
 {
@@ -3897,7 +3914,7 @@ pms_status pms_reduce(pms_ctx *c, const pms_boundary *bnd, const pms_options *op
     if (o.variant < 0 || o.variant > 1 || o.max_rounds < 0 || o.arena_entries < 0 || o.graph_rounds < 0 ||
         o.graph_rounds > 1024 || o.diagnostics < 0 || o.diagnostics > 1 || o.debug_invariants < 0 ||
         o.debug_invariants > 1 || !pms::extra_options_ok(o, bnd))
-        return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options (c8 and sweep need dim)");
+        return pms::set_err(c, PMS_ERR_INVALID_ARG, "bad options (c8 and sweep need dim; left and beta come together)");
     if (hipSetDevice(c->device) != hipSuccess) return pms::set_err(c, PMS_ERR_HIP, "hipSetDevice failed");
     pms::ScratchSource S;
     S.c = c;

@@ -41,7 +41,7 @@ def test_options_layout_and_defaults():
     assert (o.variant, o.compression, o.max_rounds, o.chain, o.validate, o.arena_entries) == (0, 1, 0, 1, 1, 0)
     assert ctypes.sizeof(_binding.PmsOptions) == 64
     assert (o.debug_invariants, o.c8, o.sweep, o.priority, o.round_budget, o.reserved) == (0, 0, 0, 0, 0, 0)
-    assert ctypes.sizeof(_binding.PmsBoundary) == 32
+    assert ctypes.sizeof(_binding.PmsBoundary) == 48
     assert lib.pms_version().decode().startswith("pms-gfx950")
     # no context: the error text is static, and a null handle is rejected
     assert lib.pms_last_error(None) == b"no context"

@@ -27,6 +27,23 @@ def _compare_lowerstar(g, dev):
     best = vv.max(axis=1, keepdims=True)
     crit = np.where(vv == best, ref.verts, -1).max(axis=1)
     assert np.array_equal(got["crit"][:, 0], crit)
+    # left and beta (Defs. "left", "beta") from the builder: the oracle's on small
+    # grids; on large ones the definitions evaluated with numpy scatters
+    lb = f.left_beta()
+    assert lb is not None
+    left, beta = (t.cpu().numpy() for t in lb)
+    if ref.m <= 200_000:
+        want_left, want_beta = oracle.left_beta(ref.col_ptr, ref.rows)
+    else:
+        colidx = np.repeat(np.arange(ref.m), np.diff(ref.col_ptr))
+        want_left = np.full(ref.m, ref.m, np.int64)
+        np.minimum.at(want_left, ref.rows, colidx)
+        want_left[want_left == ref.m] = -1
+        hit = want_left[ref.rows] == colidx
+        want_beta = np.full(ref.m, -1, np.int64)
+        np.maximum.at(want_beta, colidx[hit], ref.rows[hit])
+    assert np.array_equal(np.where(left == 0x7FFFFFFF, -1, left), want_left)
+    assert np.array_equal(beta, want_beta)
     return f, ref
 
 
