@@ -95,6 +95,8 @@ struct Ctx {
     // (the caller's may be the legacy default stream, which cannot capture)
     hipStream_t graph_stream = nullptr;
     hipEvent_t graph_ev = nullptr;
+    // pipelined rounds: one event per pinned counter buffer
+    hipEvent_t pipe_ev[2] = {nullptr, nullptr};
     // the last captured round graph, reused while its key (the device
     // arguments and options it was captured with) is unchanged
     hipGraphExec_t graph_exec = nullptr;

@@ -3358,11 +3358,11 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // round's take, so the rounds after it (and later calls, which start from
     // the kept arena) do not grow it again.
     unsigned long long free_prev = d.arena_cap - d.part_base, want_cap = 0;
-    auto grow_early = [&](int32_t n_left) {
-        const unsigned long long took = free_prev > h->arena_free ? free_prev - h->arena_free : 0;
-        free_prev = h->arena_free;
-        want_cap = (d.arena_cap - h->arena_free) + 4 * took;
-        return n_left > 0 && h->arena_free < 2 * took;
+    auto grow_early = [&](int32_t n_left, const Counters *hc) {
+        const unsigned long long took = free_prev > hc->arena_free ? free_prev - hc->arena_free : 0;
+        free_prev = hc->arena_free;
+        want_cap = (d.arena_cap - hc->arena_free) + 4 * took;
+        return n_left > 0 && hc->arena_free < 2 * took;
     };
 
     // Graph mode: `graph_rounds` rounds (rounded up to even, so the active
@@ -3465,7 +3465,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             if (e != hipSuccess) return set_err(c, PMS_ERR_HIP, std::string("graph round: ") + hipGetErrorString(e));
             round = h->round;
             if (h->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*h));
-            if (h->overflow || (!S.base && grow_early(h->n_cur))) {  // the arena moves: grow it (on the caller's stream) and capture again
+            if (h->overflow || (!S.base && grow_early(h->n_cur, h))) {  // the arena moves: grow it (on the caller's stream) and capture again
                 pms_status s = grow_arena(c, d, h, S, h->overflow ? 0 : want_cap);
                 if (s != PMS_OK) return s;
                 free_prev = d.arena_cap - d.part_base;
@@ -3476,6 +3476,62 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
                 continue;
             }
             if (h->n_cur == 0) break;
+        }
+        nA = 0;
+    }
+    // Pipelined rounds: once few columns are active, the next round is queued
+    // before this one's counters reach the host.  The active list only
+    // shrinks, so the count a round started with bounds the next round's grid
+    // (an oversized grid costs little at that size), and a round queued after
+    // convergence finds no active column and returns at once.  Consecutive
+    // rounds' counters land in two pinned buffers, each behind its own event.
+    // Off where the host acts on every round before the next may start
+    // (profiling, traces, diagnostics, invariant checks, a round cap) and for
+    // the c8 and budget options.
+    constexpr int32_t kPipeCols = 1 << 18;
+    if (nA > 0 && !c->prof_on && !trace && !diag && !dbg && opt->max_rounds == 0 && !c8on && !budget) {
+        Counters *hb[2] = {h, h + 1};
+        auto queue = [&](const int32_t *a, int32_t *an, int32_t bound, int q) -> pms_status {
+            const pms_status sr = launch_round(a, an, (bound + kBlock - 1) / kBlock, (double)bound);
+            if (sr != PMS_OK) return sr;
+            PMS_HIP(hipGetLastError());
+            PMS_HIP(hipMemcpyAsync(hb[q], d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+            PMS_HIP(hipEventRecord(c->pipe_ev[q], st));
+            return PMS_OK;
+        };
+        int q = 0;
+        pms_status sr = queue(act, act_next, nA, q);
+        if (sr != PMS_OK) return sr;
+        bool grown = false;  // the round read next ran before the arena moved
+        for (;;) {
+            // the round reading `act` is queued, its counters going to hb[q]
+            const bool ahead = nA <= kPipeCols;
+            if (ahead) {  // queue the one after it
+                sr = queue(act_next, act, nA, q ^ 1);
+                if (sr != PMS_OK) return sr;
+            }
+            PMS_HIP(hipEventSynchronize(c->pipe_ev[q]));
+            const Counters *hr = hb[q];
+            round++;
+            if (hr->bad_source) return set_err(c, PMS_ERR_HIP, bad_source_text(*hr));
+            const int32_t nn = hr->n_next;
+            if (grown) {
+                grown = false;  // its arena figures are the old arena's
+            } else if (hr->overflow || (!S.base && grow_early(nn, hr))) {
+                // the arena moves once a queued round is done (grow_arena waits for it)
+                const pms_status s = grow_arena(c, d, hb[q], S, hr->overflow ? 0 : want_cap);
+                if (s != PMS_OK) return s;
+                free_prev = d.arena_cap - d.part_base;
+                grown = ahead;
+            }
+            if (nn == 0) break;  // a queued round finds no active column
+            std::swap(act, act_next);
+            nA = nn;
+            q ^= 1;
+            if (!ahead) {  // the next round, its grid from the count just read
+                sr = queue(act, act_next, nA, q);
+                if (sr != PMS_OK) return sr;
+            }
         }
         nA = 0;
     }
@@ -3553,7 +3609,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
             const pms_status sdb = dbg_check("in round", (int32_t)round);
             if (sdb != PMS_OK) return sdb;
         }
-        if (h->overflow || (!S.base && grow_early(h->n_next))) {
+        if (h->overflow || (!S.base && grow_early(h->n_next, h))) {
             pms_status s = grow_arena(c, d, h, S, h->overflow ? 0 : want_cap);
             if (s != PMS_OK) return s;
             free_prev = d.arena_cap - d.part_base;
@@ -3704,16 +3760,24 @@ pms_status pms_create(pms_ctx **ctx, int device, void *stream)
     if (!c) return PMS_ERR_OOM;
     c->device = device;
     c->stream = (hipStream_t)stream;
-    if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&c->host_pinned, 2 * sizeof(pms::Counters), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return PMS_ERR_OOM;
     }
+    for (int q = 0; q < 2; q++)
+        if (hipEventCreateWithFlags(&c->pipe_ev[q], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k < q; k++) (void)hipEventDestroy(c->pipe_ev[k]);
+            (void)hipHostFree(c->host_pinned);
+            delete c;
+            return PMS_ERR_HIP;
+        }
     // once per device: the device address of its copy of the allocation-free region
     if (device < kNoAllocDevices) {
         std::lock_guard<std::mutex> lk(noalloc_mu);
         if (!noalloc_ptr[device]) {
             void *p = nullptr;
             if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                for (int q = 0; q < 2; q++) (void)hipEventDestroy(c->pipe_ev[q]);
                 (void)hipHostFree(c->host_pinned);
                 delete c;
                 return PMS_ERR_HIP;
@@ -3738,6 +3802,8 @@ void pms_destroy(pms_ctx *c)
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph_ev) (void)hipEventDestroy(c->graph_ev);
+    for (auto e : c->pipe_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
     delete c;
 }

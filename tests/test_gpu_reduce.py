@@ -159,6 +159,27 @@ def test_arena_regrowth(gpu):
     _check(_reduce(f.col_ptr, f.rows, f.dim, gpu), ref)
 
 
+def test_pipelined_rounds_match_rounds_read_one_by_one(gpu):
+    """By default a round is queued before the previous round's counters reach
+    the host (its grid bounded by the count that round started with; a round
+    queued after convergence does nothing).  The low*, round count and
+    additions equal those of rounds the host reads one by one (a round cap far
+    above the rounds needed turns the pipelining off), also with the twist
+    sweep, and with an arena small enough to grow while a round is queued."""
+    big = 1 << 24
+    cases = [oracle.build_vr_i32(synth.vr_grid_cloud(), -1, 2),
+             oracle.build_lowerstar(synth.random_grid(81, (9, 10, 11)))]
+    for f in cases:
+        ref = oracle.reduce_twist(f.col_ptr, f.rows, f.dim)
+        for kw in (dict(), dict(sweep=True), dict(chain=False)):
+            a = _reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=big, **kw)
+            b = _reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=big, max_rounds=1 << 20, **kw)
+            _check(a, ref)
+            _check(b, ref)
+            assert (a.rounds, a.additions) == (b.rounds, b.additions), kw
+        _check(_reduce(f.col_ptr, f.rows, f.dim, gpu, arena_entries=1024), ref)
+
+
 # ---------------------------------------------------------------- graph mode
 @pytest.mark.parametrize("k", [1, 2, 5])
 def test_graph_rounds_parity(gpu, k):
