@@ -350,9 +350,11 @@ __device__ inline int64_t block_sum64(int64_t v)
 // One-block exclusive scan of n values in place (1024 threads): per pass
 // each thread takes kSeg consecutive values (loaded together: the index is
 // clamped rather than branched on, so one wait covers them), the block scans
-// the threads' sums, and each thread writes its values back.  A pass covers
-// 16 K values with two barriers, where a 1024-value chunk loop needs three
-// barriers and one dependent load per chunk.  Returns the total.
+// the threads' sums, and each thread writes its values back.  kSeg holds 64
+// bytes per thread (16 int32, 8 int64, 4 I4): more would not fit the 128
+// VGPRs a 1024-thread block leaves each lane.  A pass covers 16 K int32 with
+// two barriers, where a 1024-value chunk loop needs three barriers and one
+// dependent load per chunk.  Returns the total.
 __device__ inline int32_t shfl_up_t(int32_t x, int dd) { return __shfl_up(x, dd, kWave); }
 __device__ inline int64_t shfl_up_t(int64_t x, int dd) { return __shfl_up(x, dd, kWave); }
 __device__ inline I4 shfl_up_t(I4 x, int dd)
@@ -365,7 +367,7 @@ __device__ inline I4 shfl_up_t(I4 x, int dd)
 template <typename T, typename Op>
 __device__ inline T block_seg_scan(T *a, int64_t n, T ident, Op op)
 {
-    constexpr int kThr = 1024, kSeg = 16;
+    constexpr int kThr = 1024, kSeg = (int)(64 / sizeof(T));
     __shared__ T s_part[kThr / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     T carry = ident;
