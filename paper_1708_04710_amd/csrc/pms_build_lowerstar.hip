@@ -10,12 +10,13 @@
 // compatible (Sec. 2.2): by value, then dimension, then the lexicographic
 // order of the ascending vertex tuple.  Because a simplex's vertices are the
 // anchor plus fixed offsets, the lexicographic order is (anchor, rank of the
-// shape's offset tuple), so the whole order is one 64-bit key:
+// shape's offset tuple), so the whole order is one key of b + 38 bits, b the
+// bits of a vertex id (nx ny nz <= 2^b, b <= 26), sorted by those bits only:
 //
-//   [63:32] value, as order-preserving bits of the FP32 (-0 read as +0)
-//   [31:30] dimension
-//   [29: 4] anchor vertex id (26 bits)
-//   [ 3: 0] rank of the shape among the shapes of its dimension
+//   [b+37:b+6] value, as order-preserving bits of the FP32 (-0 read as +0)
+//   [b+5 :b+4] dimension
+//   [b+3 :  4] anchor vertex id
+//   [3   :  0] rank of the shape among the shapes of its dimension
 //
 // The boundary matrix (eq. "def:boundary_matrix") follows from a dense
 // (anchor, shape) -> filtration index table: the facets of (v, s) are
@@ -30,11 +31,11 @@
 
 #include <algorithm>
 #include <new>
-#include <rocprim/device/device_radix_sort.hpp>
 #include <vector>
 
 #include "pms_common.h"
 #include "pms_build.h"
+#include "pms_sort.h"
 
 namespace pms {
 
@@ -54,6 +55,7 @@ struct ShapeTab {
     int8_t ncof[kShapes];
     int8_t cof_s[kShapes][14];
     int8_t cof_e[kShapes][14];
+    int32_t vbits;  // bits of an anchor index in the order key (nx ny nz <= 2^vbits)
 };
 
 __device__ inline uint32_t f32_order_bits(float x)
@@ -89,8 +91,9 @@ __global__ void k_ls_keys(ShapeTab t, const float *__restrict__ grid, int64_t nv
             float val = grid[v];
             for (int k = 1; k <= t.dim[s]; k++) val = fmaxf(val, grid[v + t.cum[s][k]]);
             if (val != val) atomicExch(err, 1);  // NaN has no place in an order
-            key = ((unsigned long long)f32_order_bits(val) << 32) | ((unsigned long long)t.dim[s] << 30) |
-                  ((unsigned long long)v << 4) | (unsigned long long)t.rank[s];
+            key = ((unsigned long long)f32_order_bits(val) << (t.vbits + 6)) |
+                  ((unsigned long long)t.dim[s] << (t.vbits + 4)) | ((unsigned long long)v << 4) |
+                  (unsigned long long)t.rank[s];
         }
         keys[i] = key;
     }
@@ -106,14 +109,15 @@ __global__ void __launch_bounds__(kBlock) k_ls_index(ShapeTab t, const float *__
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t nf = 0;
     const unsigned long long key = p < m ? keys[p] : ~0ull;
-    if (p < m && (key == ~0ull || (int64_t)((key >> 4) & 0x3FFFFFFu) >= nv)) atomicExch(err, 2);
+    const unsigned long long vmask = (1ull << t.vbits) - 1;
+    if (p < m && (key == ~0ull || (int64_t)((key >> 4) & vmask) >= nv)) atomicExch(err, 2);
     else if (p < m) {
-        const int32_t v = (int32_t)((key >> 4) & 0x3FFFFFFu);
-        const int dm = (int)((key >> 30) & 3u);
+        const int32_t v = (int32_t)((key >> 4) & vmask);
+        const int dm = (int)((key >> (t.vbits + 4)) & 3u);
         const int s = t.by_rank[dm][key & 15u];
         idx_tab[(int64_t)v * kShapes + s] = (int32_t)p;
         dim[p] = (int8_t)dm;
-        value[p] = f32_from_order_bits((uint32_t)(key >> 32));
+        value[p] = f32_from_order_bits((uint32_t)(key >> (t.vbits + 6)));
         // argmax vertex by (value, id): the vertex whose value the simplex takes
         int32_t best = v;
         float bv = grid[v];
@@ -144,9 +148,10 @@ __global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned l
     bool ok = false;
     if (p < m) {
         const unsigned long long key = keys[p];
-        ok = key != ~0ull && (int64_t)((key >> 4) & 0x3FFFFFFu) < nv;
-        v = (int32_t)((key >> 4) & 0x3FFFFFFu);
-        dm = (int)((key >> 30) & 3u);
+        const unsigned long long vmask = (1ull << t.vbits) - 1;
+        ok = key != ~0ull && (int64_t)((key >> 4) & vmask) < nv;
+        v = (int32_t)((key >> 4) & vmask);
+        dm = (int)((key >> (t.vbits + 4)) & 3u);
         s = t.by_rank[dm][key & 15u];
         nf = (ok && dm > 0) ? dm + 1 : 0;
     }
@@ -283,6 +288,8 @@ static void make_tables(ShapeTab &t, int nx, int ny, int nz)
     t.nx = nx;
     t.ny = ny;
     t.nz = nz;
+    t.vbits = 1;
+    while ((1ll << t.vbits) < (long long)nx * ny * nz) t.vbits++;
     std::vector<std::vector<int>> shapes;
     shapes.push_back({});
     for (int e = 1; e < 8; e++) shapes.push_back({e});
@@ -405,10 +412,6 @@ pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, in
     int64_t *tsum = (int64_t *)grow_scratch(c, B_BUILD3, (tiles + 1) * 8);
     int32_t *err = (int32_t *)grow_scratch(c, B_BUILD4, 64);
     if (!keys || !keys2 || !idx || !tsum || !err) return set_err(c, PMS_ERR_OOM, "builder scratch");
-    size_t tmp_bytes = 0;
-    PMS_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys2, (size_t)nk, 0, 64, s));
-    void *tmp = grow_scratch(c, B_BUILD5, tmp_bytes);
-    if (!tmp) return set_err(c, PMS_ERR_OOM, "sort scratch");
     PMS_HIP(hipMemsetAsync(err, 0, 4, s));
     // grid reads are cache resident; the key write is the stream
     PMS_LAUNCH(c, K_LS_KEYS, 8.0 * nk + 4.0 * nv, k_ls_keys, grid_for(nk, kBlock, 1u << 16), kBlock, t, grid, nv, keys,
@@ -416,7 +419,12 @@ pms_status build_lowerstar(Ctx *c, const float *grid, int32_t nx, int32_t ny, in
     {
         hipEvent_t e0 = nullptr;
         if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
-        PMS_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, keys, keys2, (size_t)nk, 0, 64, s));
+        bool in_b = false;
+        // bits: value, dim, anchor, shape rank (keys of shapes off the grid are all ones)
+        const pms_status ss = radix_sort<unsigned long long, uint32_t>(c, keys, keys2, nullptr, nullptr, nk, t.vbits + 38, B_BUILD5,
+                                                                       B_BUILD6, &in_b);
+        if (ss != PMS_OK) return ss;
+        if (!in_b) std::swap(keys, keys2);  // keys2: the sorted keys
         if (c->prof_on) {
             hipEvent_t e1 = prof_event(c);
             (void)hipEventRecord(e1, s);

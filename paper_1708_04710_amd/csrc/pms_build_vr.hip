@@ -23,12 +23,12 @@
 
 #include <new>
 #include <algorithm>
+#include <cstring>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 #include <vector>
 
 #include "pms_build.h"
+#include "pms_sort.h"
 #include "pms_common.h"
 
 namespace pms {
@@ -176,10 +176,10 @@ __global__ void k_vr_bounds(VrInst *inst, int32_t B, const int64_t *escan, const
 template <bool F32, bool kWide>
 __global__ void k_vr_emit(const VrInst *inst, const unsigned long long *val, const unsigned long long *adj,
                           const int64_t *escan, const int64_t *tscan, const int64_t *qscan, unsigned long long *keys,
-                          unsigned long long *hi, uint16_t *cl, int maxdim, int lexb, int cshift)
+                          unsigned long long *hi, uint32_t *cl, int maxdim, int lexb, int cshift)
 {
     const VrInst I = inst[blockIdx.y];
-    const uint16_t cb = (uint16_t)blockIdx.y;
+    const uint32_t cb = blockIdx.y;
     const unsigned long long ck = cshift > 0 ? (unsigned long long)blockIdx.y << cshift : 0ull;
     constexpr int kVb = F32 ? kValueBitsF : kValueBitsI;
     const unsigned long long chi = (unsigned long long)blockIdx.y << (kVb + 2);
@@ -560,20 +560,21 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
                        keys, hw, nullptr, maxdim, lexb, 0);
         hipEvent_t e0 = nullptr;
         if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
-        size_t tb = 0, tb2 = 0;
-        PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, hw, hw2, (size_t)m, 0, lexb, s));
-        PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, hw2, hw, keys2, keys, (size_t)m, 0, hibits, s));
-        void *tmps = grow_scratch(c, B_AGG, tb > tb2 ? tb : tb2);
-        if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-        PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, hw, hw2, (size_t)m, 0, lexb, s));
-        PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, hw2, hw, keys2, keys, (size_t)m, 0, hibits, s));
+        // by lex, then (stable) by (cloud, value, dim)
+        bool in_b = false;
+        pms_status ss = radix_sort(c, keys, keys2, hw, hw2, m, lexb, B_AGG, B_AGG2, &in_b);
+        if (ss != PMS_OK) return ss;
+        unsigned long long *lx = in_b ? keys2 : keys, *lx2 = in_b ? keys : keys2;
+        unsigned long long *hx = in_b ? hw2 : hw, *hx2 = in_b ? hw : hw2;
+        ss = radix_sort(c, hx, hx2, lx, lx2, m, hibits, B_AGG, B_AGG2, &in_b);
+        if (ss != PMS_OK) return ss;
         if (c->prof_on) {
             hipEvent_t e1 = prof_event(c);
             (void)hipEventRecord(e1, s);
             c->pend.push_back({K_SORT, e0, e1, 64.0 * m});
         }
-        sorted = keys;
-        sorted_hi = hw;
+        sorted = in_b ? lx2 : lx;
+        sorted_hi = in_b ? hx2 : hx;
     } else {
         // key widths: lex for the largest cloud's n^3, the value's bits, and the
         // cloud's when a batch is sorted in one pass
@@ -584,11 +585,11 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
         // stable sort of all keys (carrying their cloud) by key, then a stable
         // sort by cloud, so each cloud's columns come out in key order
         const bool one_pass = B > 1 && keybits + cbits <= 64;
-        const bool by_cloud = B > 1 && !one_pass && B <= 65536;
-        uint16_t *cl = nullptr, *cl2 = nullptr;
+        const bool by_cloud = B > 1 && !one_pass;
+        uint32_t *cl = nullptr, *cl2 = nullptr;
         if (by_cloud) {
-            cl = (uint16_t *)grow_scratch(c, B_BUILD12, M * 2);
-            cl2 = (uint16_t *)grow_scratch(c, B_BUILD13, M * 2);
+            cl = (uint32_t *)grow_scratch(c, B_BUILD12, M * 4);
+            cl2 = (uint32_t *)grow_scratch(c, B_BUILD13, M * 4);
             if (!cl || !cl2) return set_err(c, PMS_ERR_OOM, "builder scratch");
         }
         if (f32)
@@ -599,34 +600,27 @@ static pms_status build_vr(Ctx *c, const void *pts, bool f32, const int32_t *n, 
                        keys, nullptr, cl, maxdim, lexb, one_pass ? keybits : 0);
         hipEvent_t e0 = nullptr;
         if (c->prof_on) { e0 = prof_event(c); (void)hipEventRecord(e0, s); }
-        size_t tb = 0;
-        if (B == 1 || one_pass) {
+        bool in_b = false;
+        if (!by_cloud) {
             const int bits = keybits + (one_pass ? cbits : 0);
-            PMS_HIP(rocprim::radix_sort_keys(nullptr, tb, keys, keys2, (size_t)m, 0, bits, s));
-            void *tmps = grow_scratch(c, B_AGG, tb);
-            if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-            PMS_HIP(rocprim::radix_sort_keys(tmps, tb, keys, keys2, (size_t)m, 0, bits, s));
-        } else if (by_cloud) {
-            size_t tb2 = 0;
-            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
-            PMS_HIP(rocprim::radix_sort_pairs(nullptr, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
-            void *tmps = grow_scratch(c, B_AGG, tb > tb2 ? tb : tb2);
-            if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb, keys, keys2, cl, cl2, (size_t)m, 0, keybits, s));
-            PMS_HIP(rocprim::radix_sort_pairs(tmps, tb2, cl2, cl, keys2, keys, (size_t)m, 0, cbits, s));
-            sorted = keys;
+            const pms_status ss = radix_sort<unsigned long long, uint32_t>(c, keys, keys2, nullptr, nullptr, m, bits,
+                                                                           B_AGG, B_AGG2, &in_b);
+            if (ss != PMS_OK) return ss;
+            sorted = in_b ? keys2 : keys;
         } else {
-            PMS_HIP(rocprim::segmented_radix_sort_keys(nullptr, tb, keys, keys2, (unsigned)m, (unsigned)B, seg,
-                                                       seg + B, 0, keybits, s));
-            void *tmps = grow_scratch(c, B_AGG, tb);
-            if (!tmps) return set_err(c, PMS_ERR_OOM, "sort scratch");
-            PMS_HIP(rocprim::segmented_radix_sort_keys(tmps, tb, keys, keys2, (unsigned)m, (unsigned)B, seg, seg + B,
-                                                       0, keybits, s));
+            // by key (carrying the cloud), then stable by cloud
+            pms_status ss = radix_sort(c, keys, keys2, cl, cl2, m, keybits, B_AGG, B_AGG2, &in_b);
+            if (ss != PMS_OK) return ss;
+            unsigned long long *kx = in_b ? keys2 : keys, *kx2 = in_b ? keys : keys2;
+            uint32_t *cx = in_b ? cl2 : cl, *cx2 = in_b ? cl : cl2;
+            ss = radix_sort(c, cx, cx2, kx, kx2, m, cbits, B_AGG, B_AGG2, &in_b);
+            if (ss != PMS_OK) return ss;
+            sorted = in_b ? kx2 : kx;
         }
         if (c->prof_on) {
             hipEvent_t e1 = prof_event(c);
             (void)hipEventRecord(e1, s);
-            c->pend.push_back({K_SORT, e0, e1, by_cloud ? 40.0 * m : 16.0 * m});
+            c->pend.push_back({K_SORT, e0, e1, by_cloud ? 48.0 * m : 16.0 * m});
         }
     }
 #define VR_INDEX(F, W)                                                                                            \
