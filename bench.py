@@ -375,8 +375,6 @@ COPY_BYTES = 256 << 20
 
 def _slot(kernel_name):
     """Profiler slot of a rocprof kernel name (pms::k_xor(...) -> k_xor)."""
-    if "rocprim" in kernel_name:
-        return "k_sort"
     if "pms::" not in kernel_name:
         return None
     name = kernel_name.split("pms::", 1)[1].split("(", 1)[0].split("<", 1)[0]
@@ -386,7 +384,8 @@ def _slot(kernel_name):
             "k_backward_lowerstar": "k_backward", "k_backward_vr": "k_backward",
             "k_fill_i32": "k_fill", "k_fill_u64": "k_fill", "k_iota": "k_fill", "k_part_init": "k_fill",
             "k_stats_fold": "k_fill", "k_scan_i64": "k_build_scan", "k_tile_sums": "k_build_scan",
-            "k_tile_apply": "k_build_scan"}.get(name, name)
+            "k_tile_apply": "k_build_scan", "k_rs_count": "k_sort", "k_rs_offsets": "k_sort",
+            "k_rs_scatter": "k_sort", "k_setup": "k_fill"}.get(name, name)
 
 
 def rocprof_summary(tdir, fdir, wdir, out_md, bench_json=None):

@@ -455,7 +455,10 @@ def reduce(col_ptr: torch.Tensor, rows: torch.Tensor, dim: torch.Tensor | None =
 
 
 def reduce_filtration(f: Filtration, **kw) -> ReduceResult:
-    """Reduce a device-built filtration in place of its library-owned arrays."""
+    """Reduce a device-built filtration in place of its library-owned arrays.
+    The input check (``validate``) is off unless asked for: the builders'
+    matrices are those of compatible filtrations by construction."""
+    kw.setdefault("validate", False)
     v = f.view
     return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, left_p=v.left, beta_p=v.beta, **kw)
 
@@ -465,6 +468,7 @@ def reduce_batched(f: Filtration, col_off, **kw) -> ReduceResult:
     ``reduce_filtration``, plus the per-instance pair / essential offsets and
     the instance of every pair.  ``col_off``: the instances' column offsets
     (count + 1 entries, host list or int64 tensor)."""
+    kw.setdefault("validate", False)
     off = torch.as_tensor(col_off, dtype=torch.int64).to(f.device)
     v = f.view
     return _reduce_ptrs(f.device, int(v.m), v.col_ptr, v.rows, v.dim, inst_col_off=off, left_p=v.left,
