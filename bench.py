@@ -385,7 +385,7 @@ def _slot(kernel_name):
             "k_fill_i32": "k_fill", "k_fill_u64": "k_fill", "k_iota": "k_fill", "k_part_init": "k_fill",
             "k_stats_fold": "k_fill", "k_scan_i64": "k_build_scan", "k_tile_sums": "k_build_scan",
             "k_tile_apply": "k_build_scan", "k_rs_count": "k_sort", "k_rs_offsets": "k_sort",
-            "k_rs_scatter": "k_sort", "k_setup": "k_fill"}.get(name, name)
+            "k_rs_scatter": "k_sort", "k_setup": "k_fill", "k_round_end": "k_fill"}.get(name, name)
 
 
 def rocprof_summary(tdir, fdir, wdir, out_md, bench_json=None):
