@@ -42,9 +42,10 @@ __global__ void k_backward_lowerstar(const Filtration f, int64_t n, const int32_
             atomicExch(err, 1);
             continue;
         }
-        const int32_t v = f.crit[2 * (int64_t)j];
         const float g = grad[k];
-        if (v >= 0 && v < nv && g != 0.0f) atomicAdd(&grad_grid[v], g);
+        if (g == 0.0f) continue;  // nothing to add: no gather of the critical vertex
+        const int32_t v = f.crit[2 * (int64_t)j];
+        if (v >= 0 && v < nv) atomicAdd(&grad_grid[v], g);
     }
 }
 
@@ -57,9 +58,10 @@ __global__ void k_backward_vr(const Filtration f, int64_t n, const int32_t *simp
             atomicExch(err, 1);
             continue;
         }
-        const int32_t a = f.crit[2 * (int64_t)j], b = f.crit[2 * (int64_t)j + 1];
         const float g = grad[k];
-        if (a < 0 || b < 0 || g == 0.0f) continue;  // vertices: value 0, no dependence
+        if (g == 0.0f) continue;  // nothing to add: no gather of the critical edge
+        const int32_t a = f.crit[2 * (int64_t)j], b = f.crit[2 * (int64_t)j + 1];
+        if (a < 0 || b < 0) continue;  // vertices: value 0, no dependence
         if ((int64_t)a >= npts || (int64_t)b >= npts) {
             atomicExch(err, 1);
             continue;

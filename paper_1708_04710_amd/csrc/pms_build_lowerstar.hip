@@ -71,29 +71,40 @@ __device__ inline float f32_from_order_bits(uint32_t u)
     return __uint_as_float(b);
 }
 
-__device__ inline bool shape_fits(const ShapeTab &t, int32_t v, int s)
+// One key per (anchor, shape); shapes that leave the grid get ~0 (sorted
+// last).  The shape tables sit in LDS (a thread's shape differs from its
+// neighbours'), 32-bit index arithmetic (nv * 26 < 2^31), and the value's
+// up to four vertex reads are issued together (clamped to the anchor).
+__global__ void __launch_bounds__(kBlock) k_ls_keys(ShapeTab t, const float *__restrict__ grid, int64_t nv,
+                                                    unsigned long long *keys, int32_t *err)
 {
-    const int32_t x = v % t.nx, y = (v / t.nx) % t.ny, z = v / (t.nx * t.ny);
-    const int e = t.ext[s];
-    return !((e & 1) && x + 1 >= t.nx) && !((e & 2) && y + 1 >= t.ny) && !((e & 4) && z + 1 >= t.nz);
-}
-
-// One key per (anchor, shape); shapes that leave the grid get ~0 (sorted last).
-__global__ void k_ls_keys(ShapeTab t, const float *__restrict__ grid, int64_t nv, unsigned long long *keys,
-                          int32_t *err)
-{
-    const int64_t n = nv * kShapes;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = (int32_t)(i / kShapes);
-        const int s = (int)(i - (int64_t)v * kShapes);
+    __shared__ int32_t s_cum[kShapes][4];
+    __shared__ int8_t s_dim[kShapes], s_ext[kShapes], s_rank[kShapes];
+    for (int k = threadIdx.x; k < kShapes * 4; k += kBlock) s_cum[k / 4][k % 4] = t.cum[k / 4][k % 4];
+    if (threadIdx.x < kShapes) {
+        s_dim[threadIdx.x] = t.dim[threadIdx.x];
+        s_ext[threadIdx.x] = t.ext[threadIdx.x];
+        s_rank[threadIdx.x] = t.rank[threadIdx.x];
+    }
+    __syncthreads();
+    const uint32_t n = (uint32_t)(nv * kShapes), nx = (uint32_t)t.nx, nxy = (uint32_t)(t.nx * t.ny);
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const uint32_t v = i / kShapes;
+        const int s = (int)(i - v * kShapes);
+        const uint32_t z = v / nxy, r = v - z * nxy, y = r / nx, x = r - y * nx;
+        const int e = s_ext[s], dm = s_dim[s];
         unsigned long long key = ~0ull;
-        if (shape_fits(t, v, s)) {
-            float val = grid[v];
-            for (int k = 1; k <= t.dim[s]; k++) val = fmaxf(val, grid[v + t.cum[s][k]]);
+        if (!((e & 1) && x + 1 >= nx) && !((e & 2) && y + 1 >= (uint32_t)t.ny) && !((e & 4) && z + 1 >= (uint32_t)t.nz)) {
+            float g[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) g[k] = grid[v + (k <= dm ? s_cum[s][k] : 0)];
+            float val = g[0];
+#pragma unroll
+            for (int k = 1; k < 4; k++) val = k <= dm ? fmaxf(val, g[k]) : val;
             if (val != val) atomicExch(err, 1);  // NaN has no place in an order
             key = ((unsigned long long)f32_order_bits(val) << (t.vbits + 6)) |
-                  ((unsigned long long)t.dim[s] << (t.vbits + 4)) | ((unsigned long long)v << 4) |
-                  (unsigned long long)t.rank[s];
+                  ((unsigned long long)dm << (t.vbits + 4)) | ((unsigned long long)v << 4) |
+                  (unsigned long long)s_rank[s];
         }
         keys[i] = key;
     }
