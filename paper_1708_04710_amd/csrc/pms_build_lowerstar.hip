@@ -117,6 +117,12 @@ __global__ void __launch_bounds__(kBlock) k_ls_index(ShapeTab t, const float *__
                                                      int32_t *idx_tab, int8_t *dim, float *value, int32_t *crit,
                                                      int32_t *verts, int64_t *tile_sum, int32_t *err)
 {
+    // the shape tables in LDS: neighbouring simplices have different shapes
+    __shared__ int32_t s_cum[kShapes][4];
+    __shared__ int8_t s_shape[4][16];
+    for (int k = threadIdx.x; k < kShapes * 4; k += kBlock) s_cum[k / 4][k % 4] = t.cum[k / 4][k % 4];
+    if (threadIdx.x < 64) s_shape[threadIdx.x / 16][threadIdx.x % 16] = t.by_rank[threadIdx.x / 16][threadIdx.x % 16];
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t nf = 0;
     const unsigned long long key = p < m ? keys[p] : ~0ull;
@@ -125,22 +131,28 @@ __global__ void __launch_bounds__(kBlock) k_ls_index(ShapeTab t, const float *__
     else if (p < m) {
         const int32_t v = (int32_t)((key >> 4) & vmask);
         const int dm = (int)((key >> (t.vbits + 4)) & 3u);
-        const int s = t.by_rank[dm][key & 15u];
+        const int s = s_shape[dm][key & 15u];
         idx_tab[(int64_t)v * kShapes + s] = (int32_t)p;
         dim[p] = (int8_t)dm;
         value[p] = f32_from_order_bits((uint32_t)(key >> (t.vbits + 6)));
+        // the vertices (k > dm: the anchor again), their values read together
+        int32_t u[4];
+        float gu[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            u[k] = v + (k <= dm ? s_cum[s][k] : 0);
+            gu[k] = grid[u[k]];
+        }
         // argmax vertex by (value, id): the vertex whose value the simplex takes
         int32_t best = v;
-        float bv = grid[v];
-        for (int k = 1; k <= dm; k++) {
-            const int32_t u = v + t.cum[s][k];
-            const float gu = grid[u];
-            if (gu > bv || (gu == bv && u > best)) { best = u; bv = gu; }
-        }
-        crit[2 * p] = best;
-        crit[2 * p + 1] = -1;
+        float bv = gu[0];
+#pragma unroll
+        for (int k = 1; k < 4; k++)
+            if (k <= dm && (gu[k] > bv || (gu[k] == bv && u[k] > best))) { best = u[k]; bv = gu[k]; }
+        reinterpret_cast<int2 *>(crit)[p] = make_int2(best, -1);
         if (verts)
-            for (int k = 0; k < 4; k++) verts[4 * p + k] = k <= dm ? v + t.cum[s][k] : -1;
+            reinterpret_cast<int4 *>(verts)[p] =
+                make_int4(u[0], dm >= 1 ? u[1] : -1, dm >= 2 ? u[2] : -1, dm >= 3 ? u[3] : -1);
         nf = dm > 0 ? dm + 1 : 0;
     }
     const int64_t tot = block_sum64(nf);
@@ -152,6 +164,15 @@ __global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned l
                                                     const int64_t *tile_off, int64_t *col_ptr, int32_t *rows,
                                                     const int32_t *__restrict__ left, int32_t *beta)
 {
+    // the shape tables in LDS: neighbouring simplices have different shapes
+    __shared__ int32_t s_fdelta[kShapes][4];
+    __shared__ int8_t s_facet[kShapes][4], s_shape[4][16];
+    for (int k = threadIdx.x; k < kShapes * 4; k += kBlock) {
+        s_fdelta[k / 4][k % 4] = t.fdelta[k / 4][k % 4];
+        s_facet[k / 4][k % 4] = t.facet[k / 4][k % 4];
+    }
+    if (threadIdx.x < 64) s_shape[threadIdx.x / 16][threadIdx.x % 16] = t.by_rank[threadIdx.x / 16][threadIdx.x % 16];
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t nf = 0;
     int32_t v = 0;
@@ -163,15 +184,19 @@ __global__ void __launch_bounds__(kBlock) k_ls_rows(ShapeTab t, const unsigned l
         ok = key != ~0ull && (int64_t)((key >> 4) & vmask) < nv;
         v = (int32_t)((key >> 4) & vmask);
         dm = (int)((key >> (t.vbits + 4)) & 3u);
-        s = t.by_rank[dm][key & 15u];
+        s = s_shape[dm][key & 15u];
         nf = (ok && dm > 0) ? dm + 1 : 0;
     }
     const int64_t start = tile_off[blockIdx.x] + block_excl_sum64(nf);
     if (p < m && start + nf <= nnz) {
         col_ptr[p] = start;
         if (p == m - 1) col_ptr[m] = start + nf;
+        // the facets' indices, read together (k >= nf: the simplex's own entry)
         int32_t r[4];
-        for (int k = 0; k < nf; k++) r[k] = idx_tab[(int64_t)(v + t.fdelta[s][k]) * kShapes + t.facet[s][k]];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            r[k] = idx_tab[k < nf ? (int64_t)(v + s_fdelta[s][k]) * kShapes + s_facet[s][k]
+                                  : (int64_t)v * kShapes + s];
         for (int a = 1; a < nf; a++) {  // ascending rows
             const int32_t x = r[a];
             int b = a - 1;
