@@ -379,7 +379,7 @@ def _slot(kernel_name):
         return None
     name = kernel_name.split("pms::", 1)[1].split("(", 1)[0].split("<", 1)[0]
     return {"k_vr_dist": "k_vr_edges", "k_vr_count": "k_vr_tri", "k_vr_emit": "k_vr_tri",
-            "k_keep_count": "k_compact", "k_scan_max4": "k_scan", "k_scan_sum": "k_scan",
+            "k_keep_count": "k_compact", "k_scan_max4": "k_scan", "k_scan_sum": "k_scan", "k_scan_sum2": "k_scan",
             "k_fin_count": "k_finalize", "k_fin_scatter": "k_finalize", "k_gather": "k_finalize",
             "k_backward_lowerstar": "k_backward", "k_backward_vr": "k_backward",
             "k_fill_i32": "k_fill", "k_fill_u64": "k_fill", "k_iota": "k_fill", "k_part_init": "k_fill",

@@ -485,6 +485,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sum(int32_t *cnt, int64_t
     if (threadIdx.x == 0) *total = tot;
 }
 
+// Two independent scans of nb entries in one launch: workgroup 0 scans a
+// (total to *ta), workgroup 1 scans b (total to *tb).
+__global__ void __launch_bounds__(kScanThreads) k_scan_sum2(int32_t *a, int32_t *b, int64_t nb, int32_t *ta,
+                                                            int32_t *tb)
+{
+    int32_t *x = blockIdx.x ? b : a;
+    const int32_t tot = block_seg_scan(x, nb, 0, [](int32_t u, int32_t v) { return u + v; });
+    if (threadIdx.x == 0) *(blockIdx.x ? tb : ta) = tot;
+}
+
 // Phase I + the beta test + clearing.
 __global__ void __launch_bounds__(kBlock) k_pivots(Dev d, const int32_t *act, const I4 *agg, int compression)
 {
@@ -3642,8 +3652,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     // pairs and essential simplices, canonical order
     int32_t *cp = keep, *ce = keep2;
     PMS_LAUNCH(c, K_FINAL, 8 * dm, k_fin_count, (unsigned)nblk, kBlock, d, cp, ce);
-    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, cp, nblk, nullptr, &d.cnt->n_pairs);
-    PMS_LAUNCH(c, K_SCAN, 8.0 * nblk, k_scan_sum, 1, kScanThreads, ce, nblk, nullptr, &d.cnt->n_ess);
+    PMS_LAUNCH(c, K_SCAN, 16.0 * nblk, k_scan_sum2, 2, kScanThreads, cp, ce, nblk, &d.cnt->n_pairs, &d.cnt->n_ess);
     PMS_HIP(hipGetLastError());
     PMS_HIP(hipMemcpyAsync(h, d.cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
     PMS_HIP(hipStreamSynchronize(st));
