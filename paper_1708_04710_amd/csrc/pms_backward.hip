@@ -33,19 +33,43 @@ __global__ void k_gather(const Filtration f, int64_t n, const int32_t *simplex, 
     }
 }
 
-__global__ void k_backward_lowerstar(const Filtration f, int64_t n, const int32_t *simplex, const float *grad,
-                                     float *grad_grid, int64_t nv, int32_t *err)
+// Each paired simplex's gradient goes to its critical vertex.  Pairs come
+// in ascending order of death, and a vertex's lower star is contiguous in
+// the filtration, so neighbouring lanes often add to the same vertex: a
+// segmented sum over each run of equal vertices in neighbouring lanes (only
+// the run's own values are added) leaves one atomic per run.
+__global__ void __launch_bounds__(kBlock) k_backward_lowerstar(const Filtration f, int64_t n, const int32_t *simplex,
+                                                              const float *grad, float *grad_grid, int64_t nv,
+                                                              int32_t *err)
 {
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t j = simplex[k];
-        if (j < 0 || (int64_t)j >= f.m) {
-            atomicExch(err, 1);
-            continue;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t k0 = blockIdx.x * (int64_t)kBlock; k0 < n; k0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t k = k0 + threadIdx.x;
+        int32_t v = -1;
+        float g = 0.0f;
+        if (k < n) {
+            const int32_t j = simplex[k];
+            if (j < 0 || (int64_t)j >= f.m) {
+                atomicExch(err, 1);
+            } else {
+                g = grad[k];
+                if (g != 0.0f) {  // nothing to add otherwise: no gather of the critical vertex
+                    const int32_t c = f.crit[2 * (int64_t)j];
+                    if (c >= 0 && c < nv) v = c;
+                }
+            }
         }
-        const float g = grad[k];
-        if (g == 0.0f) continue;  // nothing to add: no gather of the critical vertex
-        const int32_t v = f.crit[2 * (int64_t)j];
-        if (v >= 0 && v < nv) atomicAdd(&grad_grid[v], g);
+        if (v < 0) g = 0.0f;
+        const int32_t vprev = __shfl_up(v, 1, kWave), vnext = __shfl_down(v, 1, kWave);
+        const uint64_t heads = __ballot(lane == 0 || vprev != v);
+        const int start = 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull));  // the run's first lane
+        float inc = g;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const float y = __shfl_up(inc, o, kWave);
+            if (lane - o >= start) inc += y;
+        }
+        if (v >= 0 && (lane == kWave - 1 || vnext != v) && inc != 0.0f) atomicAdd(&grad_grid[v], inc);
     }
 }
 
