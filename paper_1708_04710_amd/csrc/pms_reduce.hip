@@ -2721,19 +2721,23 @@ __global__ void k_one_instance(int64_t *off, int64_t m)
 
 // End of a round: the compacted list is the next round's; a round that did
 // work advances the round number (the T table's stamp).
-__global__ void k_round_end(Dev d)
+// One wavefront: lane p reads partition p's fill.
+__global__ void __launch_bounds__(kWave) k_round_end(Dev d)
 {
-    d.cnt->active_sum += (unsigned long long)d.cnt->n_cur;
-    if (d.cnt->n_cur > 0) d.cnt->round = d.cnt->round + 1;
-    d.cnt->n_cur = d.cnt->n_next;
-    unsigned long long fr = 0;  // a partition past its end is full
-    for (int p = 0; p < kPart; p++) {
-        const unsigned long long end =
-            p == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(p + 1) * d.part_size;
-        const unsigned long long cur = d.part[p * 16];
-        fr += cur < end ? end - cur : 0;
+    static_assert(kPart == kWave, "one lane per arena partition");
+    const int p = threadIdx.x;
+    const unsigned long long end =
+        p == kPart - 1 ? d.arena_cap : d.part_base + (unsigned long long)(p + 1) * d.part_size;
+    const unsigned long long cur = d.part[p * 16];
+    unsigned long long fr = cur < end ? end - cur : 0;  // a partition past its end is full
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) fr += __shfl_xor(fr, o, kWave);
+    if (p == 0) {
+        d.cnt->active_sum += (unsigned long long)d.cnt->n_cur;
+        if (d.cnt->n_cur > 0) d.cnt->round = d.cnt->round + 1;
+        d.cnt->n_cur = d.cnt->n_next;
+        d.cnt->arena_free = fr;
     }
-    d.cnt->arena_free = fr;
 }
 
 // Arena regrowth: copy every live arena column into a new arena.
@@ -3242,6 +3246,16 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
     const pms_tuning tn = c->tune;
     auto launch_round = [&](const int32_t *a, int32_t *an, int64_t grid_tiles, double dA) -> pms_status {
         const unsigned gT = (unsigned)(grid_tiles > 0 ? grid_tiles : 1);
+        // the chaining kernels take queued columns (at most the active ones)
+        // in wavefront-sized chunks over any grid: with the active count known
+        // (dA > 0), no more workgroups than it can use
+        auto chain_grid = [&](int64_t tuned, int64_t cols_per_block) -> unsigned {
+            if (dA <= 0) return (unsigned)tuned;
+            const int64_t need = ((int64_t)dA + cols_per_block - 1) / cols_per_block;
+            return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tuned, need));
+        };
+        const unsigned g_lane = chain_grid(tn.lane_blocks, kLaneThreads), g_wide = chain_grid(tn.wide_blocks, kWideThreads);
+        const unsigned g_solve = chain_grid(tn.chain_blocks, 1), g_chain = chain_grid(tn.chain_blocks, kChainWaves);
         const unsigned gA = grid_for(grid_tiles * kBlock, kBlock, 65536);
         const double dt = (double)grid_tiles;
         // act, len, off, last row, low out, T atomic
@@ -3281,37 +3295,31 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         xor_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (trace)
-            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<true>, (unsigned)tn.lane_blocks, kLaneThreads, d,
-                       opt->compression, tn);
+            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<true>, g_lane, kLaneThreads, d, opt->compression, tn);
         else
-            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<false>, (unsigned)tn.lane_blocks, kLaneThreads, d,
-                       opt->compression, tn);
+            PMS_LAUNCH(c, K_CHAIN_LANE, -1.0, k_chain_lane<false>, g_lane, kLaneThreads, d, opt->compression, tn);
         lane_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (trace)
-            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<true>, (unsigned)tn.wide_blocks, kWideThreads, d,
-                       opt->compression, tn);
+            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<true>, g_wide, kWideThreads, d, opt->compression, tn);
         else
-            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<false>, (unsigned)tn.wide_blocks, kWideThreads, d,
-                       opt->compression, tn);
+            PMS_LAUNCH(c, K_CHAIN_WIDE, -1.0, k_chain_wide<false>, g_wide, kWideThreads, d, opt->compression, tn);
         wide_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (tn.solve > 0) {  // few handed-over columns: by sweeps; what does not fit, serially
             if (trace)
-                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<true>, (unsigned)tn.chain_blocks, kSolveThreads, d,
-                           opt->compression, tn.solve);
+                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<true>, g_solve, kSolveThreads, d, opt->compression,
+                           tn.solve);
             else
-                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<false>, (unsigned)tn.chain_blocks, kSolveThreads, d,
-                           opt->compression, tn.solve);
+                PMS_LAUNCH(c, K_SOLVE, -1.0, k_chain_solve<false>, g_solve, kSolveThreads, d, opt->compression,
+                           tn.solve);
             solve_slot = c->pend.size() - 1;
             if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         }
         if (trace)
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression,
-                       tn.solve);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<true>, g_chain, kChainWaves * kWave, d, opt->compression, tn.solve);
         else
-            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, (unsigned)tn.chain_blocks, kChainWaves * kWave, d, opt->compression,
-                       tn.solve);
+            PMS_LAUNCH(c, K_CHAIN, -1.0, k_chain<false>, g_chain, kChainWaves * kWave, d, opt->compression, tn.solve);
         chain_slot = c->pend.size() - 1;
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         PMS_LAUNCH(c, K_COMPACT, 5 * dA, k_keep_count, gT, kBlock, d, a, keep, -1);
@@ -3320,7 +3328,7 @@ static pms_status reduce_impl(Ctx *c, const pms_boundary *bnd, const pms_options
         PMS_LAUNCH(c, K_COMPACT, 9 * dA, k_compact, gT, kBlock, d, a, keep, an, -1);
         if (dbg) PMS_LAUNCH(c, K_FILL, 0, k_dbg_writes, gm, kBlock, d);
         if (c->prof_on || trace || diag) PMS_LAUNCH(c, K_FILL, 0, k_stats_fold, 1, 256, d);
-        PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, 1, d);
+        PMS_LAUNCH(c, K_FILL, 0, k_round_end, 1, kWave, d);
         return PMS_OK;
     };
     // diagnostics after Phase 0 and after each round: low^l's l1 norm, the
