@@ -58,6 +58,17 @@ def test_lowerstar_builder_ties_and_zero_signs(gpu):
     _compare_lowerstar(g, gpu)
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+def test_lowerstar_builder_few_values_many_tiles(gpu, levels):
+    """A constant grid and a two-valued one over 94 sort tiles (193 K keys):
+    the order keys then differ only in their dimension, anchor and shape bits,
+    so most sort passes move long runs of equal digits; the filtration must
+    still be the oracle's."""
+    rng = np.random.default_rng(31 + levels)
+    g = rng.integers(0, levels, (23, 19, 17)).astype(np.float32)
+    _compare_lowerstar(g, gpu)
+
+
 def test_lowerstar_builder_gaussian_64_and_reduce(gpu):
     g = synth.gaussian_field()
     f, ref = _compare_lowerstar(g, gpu)
